@@ -1,0 +1,213 @@
+/*
+ * tmhip -- T-matrix multiple-scattering solve on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the shared library libtmhip.so.  Every compute step runs in HIP
+ * kernels on the device selected at tm_create; PyTorch (or any caller) only
+ * provides device memory and a HIP stream.
+ *
+ * The problem follows the statement of App. I.C ("Simulating collective
+ * scattering"): N scatterers at positions x_i with T-matrices T_i in a host
+ * medium of wavenumber k; incident-field coefficients a0 (expansion of the
+ * incident field in regular waves about every x_i); unknown scattered
+ * coefficients s with s_j = T_j (a0_j + sum_{i!=j} xi(k(x_j - x_i))^T s_i),
+ * solved in the block-diagonally preconditioned form
+ *      (I - T A) s = T a0,           A_ji = xi(k(x_j - x_i))^T,
+ * by restarted GMRES with a matrix-free block matvec (App. I.D).
+ *
+ * Conventions shared by every entry point
+ *   - Coefficient order per scatterer (App. I.B truncation at lmax, L =
+ *     2 lmax(lmax+2) coefficients): n = p*lmax(lmax+2) + l(l+1) - 1 + m,
+ *     l = 1..lmax, m = -l..l, p = 0 (M-type, grad(phi) x x) or 1 (N-type).
+ *     Basis: App. I.A, normalised Legendre functions without the
+ *     Condon-Shortley phase, outgoing waves h_l^(1), time factor e^{-i w t}.
+ *   - Coefficient vectors are complex, interleaved (re, im), laid out
+ *     [rhs][scatterer][n]; tm_c128 has the memory layout of torch.complex128.
+ *   - Pointers marked "device" must be device memory of the context's GPU;
+ *     "host" pointers are ordinary host memory.  The caller owns every array
+ *     passed in; the context owns its tables and workspaces and frees them
+ *     in tm_destroy.
+ *   - Calls enqueue work on the context's stream and return without waiting,
+ *     except those that fill host outputs (solve info, host result arrays),
+ *     which synchronise the stream before returning.
+ *   - One context per host thread.  Calls never throw and never abort; they
+ *     return a tm_status.  tm_last_error gives a message for the last failing
+ *     call on a context.
+ *
+ * Scope: scatterers on a rectangular lattice in the z = 0 plane (the
+ * metasurface setting of the paper), which lets the library tabulate one
+ * translation block per lattice displacement.  lmax 1..3.
+ */
+#ifndef TMHIP_H
+#define TMHIP_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TMHIP_ABI_VERSION 1
+
+typedef struct tm_ctx tm_ctx;
+
+typedef struct { double re, im; } tm_c128;
+
+typedef enum {
+  TM_OK = 0,
+  TM_NOT_CONVERGED = 1,     /* result written, residual above tolerance */
+  TM_ERR_INVALID_ARG = -1,  /* null pointer, size or range out of bounds   */
+  TM_ERR_OVERLAP = -2,      /* enclosing spheres intersect (App. I.C)      */
+  TM_ERR_NOT_LATTICE = -3,  /* positions are not a z = 0 rectangular grid  */
+  TM_ERR_OOM = -4,          /* device allocation failed                    */
+  TM_ERR_HIP = -5,          /* a HIP runtime call failed                   */
+  TM_ERR_NAN = -6,          /* non-finite input                            */
+  TM_ERR_STATE = -7         /* call out of order (e.g. solve before T set) */
+} tm_status;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context on HIP device `device`, enqueuing on `hip_stream`
+ * (a hipStream_t; NULL = the device's null stream). */
+int tm_create(tm_ctx** ctx, int device, void* hip_stream);
+void tm_destroy(tm_ctx* ctx);
+const char* tm_status_string(int status);
+const char* tm_last_error(const tm_ctx* ctx);
+/* Number of coefficients per scatterer, 2 lmax(lmax+2); 0 if lmax invalid. */
+int tm_coeff_count(int lmax);
+int tm_abi_version(void);
+
+/* ---- problem set-up ------------------------------------------------------ */
+
+/* Scatterer centres and host wavenumber.  pos: host, [n][3] (x, y, z).  The
+ * centres must form an nx-by-ny grid with equal pitch in x and y, z = 0,
+ * ordered index = iy*nx + ix (TM_ERR_NOT_LATTICE otherwise).  Builds the
+ * translation tables (one block per lattice displacement, App. I.C, eq.
+ * "tran_coeff") on the device in FP64 and complex64.  Invalidates T. */
+int tm_set_geometry(tm_ctx* ctx, int n, const double* pos, double k, int lmax);
+
+/* Lattice dimensions of the current geometry (host outputs). */
+int tm_get_lattice(const tm_ctx* ctx, int* nx, int* ny, double* pitch);
+
+/* Homogeneous spheres (Mie T-matrices, the sphere case of App. I.B):
+ * radii: device, [N] (> 0, finite; neighbouring spheres must not overlap,
+ * i.e. r_i + r_j < pitch for lattice neighbours, else TM_ERR_OVERLAP);
+ * relative refractive index n_re + i n_im (n_im >= 0).  Computes the
+ * diagonal T and dT/dr on the device. */
+int tm_set_spheres(tm_ctx* ctx, const double* radii, double n_re, double n_im);
+
+/* Arbitrary diagonal T-matrices: t: device, [N][L] (entry n of T_i's
+ * diagonal).  Clears dT/dr (tm_grad_radius then returns TM_ERR_STATE). */
+int tm_set_tmatrix_diag(tm_ctx* ctx, const tm_c128* t);
+
+/* Copy the current T diagonal and dT/dr (spheres only; dtdr may be NULL)
+ * to device arrays [N][L]. */
+int tm_get_tmatrix_diag(tm_ctx* ctx, tm_c128* t, tm_c128* dtdr);
+
+/* ---- incident field ------------------------------------------------------ */
+
+/* Plane waves pol_r e^{i k khat_r . x} (App. II, expansion in regular waves,
+ * eqs. "integrand_p_0"/"integrand_p_1"), expanded about every scatterer:
+ * khat: host [R][3] unit vectors; pol: host [R][3] complex, pol . khat = 0;
+ * a0: device [R][N][L] output. */
+int tm_plane_wave_rhs(tm_ctx* ctx, int n_rhs, const double* khat, const tm_c128* pol,
+                      tm_c128* a0);
+
+/* ---- solve ---------------------------------------------------------------- */
+
+enum { TM_PREC_FP64 = 0, TM_PREC_MIXED = 1 };
+
+typedef struct {
+  double tol;        /* relative true residual ||T a0 - B s|| / ||T a0||   */
+  int restart;       /* Krylov dimension per cycle (1..200)                 */
+  int max_iter;      /* total Arnoldi steps over all cycles                 */
+  int precision;     /* TM_PREC_FP64: FP64 matvec throughout;
+                        TM_PREC_MIXED: complex64 matvec with FP32
+                        accumulation inside each cycle, FP64 Arnoldi and an
+                        FP64 true residual between cycles (iterative
+                        refinement)                                         */
+  double inner_tol;  /* mixed only: relative residual reduction per cycle   */
+  int use_x0;        /* 1: s holds the initial guess on entry               */
+} tm_solve_opts;
+
+typedef struct {
+  int status;          /* TM_OK or TM_NOT_CONVERGED                          */
+  int iters;           /* Arnoldi steps                                      */
+  int cycles;          /* restart / refinement cycles                        */
+  int matvecs_fp64;
+  int matvecs_lowp;
+  double rel_residual; /* final FP64 true relative residual                  */
+} tm_solve_info;
+
+/* Fill opts with defaults (tol 1e-8, restart 50, max_iter 2000, FP64,
+ * inner_tol 1e-4, use_x0 0). */
+void tm_default_opts(tm_solve_opts* opts);
+
+/* Solve (I - T A) s = T a0 for each right-hand side.
+ * a0: device [R][N][L]; s: device [R][N][L] (initial guess if use_x0);
+ * info: host [R].  Returns TM_OK if every RHS converged, TM_NOT_CONVERGED if
+ * any did not (its best iterate is still written). */
+int tm_solve(tm_ctx* ctx, int n_rhs, const tm_c128* a0, tm_c128* s,
+             const tm_solve_opts* opts, tm_solve_info* info);
+
+/* Adjoint system (I - A^T T) mu = v (the transpose of App. IV's
+ * Omega^T a = v in preconditioned form; the paper's adjoint unknown is
+ * T mu).  v, mu: device [R][N][L]. */
+int tm_adjoint_solve(tm_ctx* ctx, int n_rhs, const tm_c128* v, tm_c128* mu,
+                     const tm_solve_opts* opts, tm_solve_info* info);
+
+enum {
+  TM_OP_FORWARD = 0,   /* y = (I - T A) x   */
+  TM_OP_COUPLING = 1,  /* y = A x           */
+  TM_OP_ADJOINT = 2,   /* y = (I - A^T T) x */
+  TM_OP_COUPLING_T = 3 /* y = A^T x         */
+};
+
+/* One application of the operator (the matvec GMRES uses).  x, y: device
+ * [R][N][L], must not alias.  precision: TM_PREC_FP64 or TM_PREC_MIXED
+ * (complex64 blocks and inputs, FP32 accumulation, FP64 output). */
+int tm_apply_operator(tm_ctx* ctx, int n_rhs, const tm_c128* x, tm_c128* y, int precision,
+                      int op);
+
+/* ---- readout ------------------------------------------------------------- */
+
+/* Scattered field E_sca(x) = sum_i s_i^T Phi(k(x - x_i)) (App. I.C, eq.
+ * "sca_fld_concise") at points: pts device [P][3] (each outside every
+ * scatterer's enclosing sphere); E device [R][P][3] complex128.
+ * precision: TM_PREC_FP64, or TM_PREC_MIXED (basis functions and sums in
+ * FP32 with k|x - x_i| reduced modulo 2 pi in FP64). */
+int tm_near_field(tm_ctx* ctx, int n_rhs, const tm_c128* s, int n_pts, const double* pts,
+                  tm_c128* E, int precision);
+
+/* Far-field amplitude F(d) = lim_r r e^{-ikr} E_sca(r d): dirs device [D][3]
+ * unit vectors; F device [R][D][3]. */
+int tm_far_field(tm_ctx* ctx, int n_rhs, const tm_c128* s, int n_dir, const double* dirs,
+                 tm_c128* F);
+
+/* ---- sensitivities (App. IV) -------------------------------------------- */
+
+/* Detector vector of a point detector: v[i][n] = sum_c w_c Phi_n(k(xd - x_i))_c
+ * so that sum_c w_c E_sca,c(xd) = v^T s.  xd: host [3]; w: host [3];
+ * v: device [N][L]. */
+int tm_detector_vector(tm_ctx* ctx, const double* xd, const tm_c128* w, tm_c128* v);
+
+/* Radius gradient contraction for spheres:
+ * grad[r][i] = 2 Re sum_n mu[r][i][n] * dT_i,n/dr * a_exc[r][i][n],
+ * a_exc = a0 + A s (exciting field).  mu, s, a0: device [R][N][L];
+ * grad: device [R][N] doubles.  With mu from tm_adjoint_solve of the
+ * objective's weighted detector vector this is dO/dr_i (App. IV,
+ * eq. "grad_geometry_overlap"). */
+int tm_grad_radius(tm_ctx* ctx, int n_rhs, const tm_c128* mu, const tm_c128* s,
+                   const tm_c128* a0, double* grad);
+
+/* ---- profiling ------------------------------------------------------------ */
+
+/* When enabled, the block-matvec launches are bracketed by HIP events on the
+ * context stream and their durations accumulated per precision. */
+int tm_profile_enable(tm_ctx* ctx, int enable);
+/* which: 0 = FP64 block matvec, 1 = complex64 block matvec.  Synchronises. */
+int tm_profile_query(tm_ctx* ctx, int which, double* total_ms, long long* launches,
+                     double* flops_per_launch);
+int tm_profile_reset(tm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TMHIP_H */

@@ -1,0 +1,599 @@
+// C ABI of libtmhip: context, set-up, restarted GMRES drivers, readout and
+// sensitivities.  The GMRES loop runs on the host; every vector operation,
+// reduction and matvec is a HIP kernel on the context stream.  Per Arnoldi
+// step the host reads back one Hessenberg column (j+2 complex values) to
+// apply the Givens rotations and test convergence.
+//
+// Solver (App. I.D: matrix-free matvecs inside GMRES; the preconditioned
+// system of App. I.C):
+//   restarted GMRES(m), x0 = 0 unless given, classical Gram-Schmidt with one
+//   re-orthogonalisation pass (CGS2) in FP64, complex Givens rotations, stop
+//   when the FP64 true residual ||b - B s||/||b|| <= tol.
+// Mixed precision (iterative refinement): each cycle starts from the FP64
+// true residual r = b - B s, runs Arnoldi with the complex64/FP32-accumulate
+// operator (basis, Hessenberg and rotations in FP64) until the estimated
+// residual falls by inner_tol or the cycle ends, then updates s in FP64.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+
+#include "tm_internal.h"
+
+using tmh::c128;
+using tmh::Op;
+
+namespace tmh {
+
+int set_err(tm_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+int ensure(tm_ctx* c, DevBuf& b, size_t bytes) {
+  if (b.bytes >= bytes && b.p) return TM_OK;
+  if (b.p) {
+    hipStreamSynchronize(c->stream);
+    hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  if (bytes == 0) return TM_OK;
+  hipError_t e = hipMalloc(&b.p, bytes);
+  if (e != hipSuccess) {
+    b.p = nullptr;
+    (void)hipGetLastError();
+    return set_err(c, TM_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+  }
+  b.bytes = bytes;
+  return TM_OK;
+}
+
+void release(DevBuf& b) {
+  if (b.p) hipFree(b.p);
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
+static int ensure_pinned(tm_ctx* c, size_t bytes) {
+  if (c->host_pinned_bytes >= bytes) return TM_OK;
+  if (c->host_pinned) hipHostFree(c->host_pinned);
+  c->host_pinned = nullptr;
+  c->host_pinned_bytes = 0;
+  if (hipHostMalloc(&c->host_pinned, bytes, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    return set_err(c, TM_ERR_OOM, "pinned host allocation failed");
+  }
+  c->host_pinned_bytes = bytes;
+  return TM_OK;
+}
+
+// ---------------------------------------------------------------- GMRES
+struct Gm {
+  tm_ctx* c;
+  Op op;
+  long long len;
+  int nblk;
+  c128 *V, *w, *r, *dots, *dots2, *dp;
+  double *np, *nout;
+};
+
+static double dev_norm(Gm& G, const c128* v) {
+  k_norm2_partial(G.c->stream, v, G.len, G.np, G.nblk);
+  k_reduce_norm(G.c->stream, G.np, G.nblk, G.nout);
+  double h = 0.0;
+  hipMemcpyAsync(G.c->host_pinned, G.nout, sizeof(double), hipMemcpyDeviceToHost, G.c->stream);
+  hipStreamSynchronize(G.c->stream);
+  std::memcpy(&h, G.c->host_pinned, sizeof(double));
+  return h;
+}
+
+// x (slot, one RHS) solves B x = b with B the operator `op`.
+static int gmres(tm_ctx* c, Op op, const c128* b, c128* x, const tm_solve_opts& o, bool use_x0,
+                 tm_solve_info& info) {
+  const Geometry& g = c->g;
+  const long long len = g.vec_len();
+  const int m = o.restart;
+  int rc;
+  // workspace: basis (m+1) vectors, w, r
+  if ((rc = ensure(c, c->basis, (size_t)(m + 1) * len * sizeof(c128))) != TM_OK) return rc;
+  if ((rc = ensure(c, c->work_c, (size_t)2 * len * sizeof(c128))) != TM_OK) return rc;
+  const int nblk = krylov_blocks(len);
+  if ((rc = ensure(c, c->dotpart, (size_t)nblk * (m + 2) * sizeof(c128))) != TM_OK) return rc;
+  if ((rc = ensure(c, c->dots, (size_t)(2 * (m + 2) + 4) * sizeof(c128))) != TM_OK) return rc;
+  if ((rc = ensure(c, c->scal, (size_t)(nblk + 8) * sizeof(double))) != TM_OK) return rc;
+  if ((rc = ensure_pinned(c, (size_t)(2 * m + 6) * sizeof(c128))) != TM_OK) return rc;
+  Gm G;
+  G.c = c;
+  G.op = op;
+  G.len = len;
+  G.nblk = nblk;
+  G.V = (c128*)c->basis.p;
+  G.w = (c128*)c->work_c.p;
+  G.r = G.w + len;
+  G.dp = (c128*)c->dotpart.p;
+  G.dots = (c128*)c->dots.p;
+  G.dots2 = G.dots + (m + 2);
+  G.np = (double*)c->scal.p;
+  G.nout = G.np + nblk;
+  hipStream_t st = c->stream;
+
+  info = tm_solve_info{};
+  const double bnorm = dev_norm(G, b);
+  if (!std::isfinite(bnorm)) return set_err(c, TM_ERR_NAN, "right-hand side is not finite");
+  if (bnorm == 0.0) {
+    TM_HIP(c, hipMemsetAsync(x, 0, len * sizeof(c128), st));
+    info.status = TM_OK;
+    return TM_OK;
+  }
+  if (use_x0) {
+    if ((rc = apply_op(c, op, TM_PREC_FP64, 1, x, G.r)) != TM_OK) return rc;
+    info.matvecs_fp64++;
+    k_sub(st, G.r, b, G.r, len);
+  } else {
+    TM_HIP(c, hipMemsetAsync(x, 0, len * sizeof(c128), st));
+    k_copy(st, G.r, b, len);
+  }
+  std::vector<std::complex<double>> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), y(m);
+  auto Hij = [&](int i, int j) -> std::complex<double>& { return H[(size_t)i * m + j]; };
+  int it = 0;
+  double relres = 0.0;
+  const int prec = o.precision;
+  for (;;) {
+    const double beta = dev_norm(G, G.r);
+    relres = beta / bnorm;
+    if (!std::isfinite(beta)) return set_err(c, TM_ERR_NAN, "residual became non-finite");
+    if (relres <= o.tol || it >= o.max_iter) break;
+    info.cycles++;
+    k_scale(st, G.V, G.r, 1.0 / beta, len);
+    std::fill(gv.begin(), gv.end(), 0.0);
+    gv[0] = beta;
+    const double target =
+        (prec == TM_PREC_MIXED) ? std::max(o.tol * bnorm, o.inner_tol * beta) : o.tol * bnorm;
+    int jend = 0;
+    for (int j = 0; j < m; ++j) {
+      c128* vj = G.V + (size_t)j * len;
+      if ((rc = apply_op(c, op, prec, 1, vj, G.w)) != TM_OK) return rc;
+      if (prec == TM_PREC_MIXED) info.matvecs_lowp++;
+      else info.matvecs_fp64++;
+      // CGS2: h1 = V^H w, w -= V h1, h2 = V^H w, w -= V h2, H(:,j) = h1 + h2
+      k_multidot(st, G.V, len, j + 1, G.w, len, G.dp, nblk);
+      k_reduce_dots(st, G.dp, nblk, j + 1, G.dots, nullptr);
+      k_update(st, G.w, G.V, len, j + 1, G.dots, len, -1.0);
+      k_multidot(st, G.V, len, j + 1, G.w, len, G.dp, nblk);
+      k_reduce_dots(st, G.dp, nblk, j + 1, G.dots2, nullptr);
+      k_update(st, G.w, G.V, len, j + 1, G.dots2, len, -1.0);
+      k_norm2_partial(st, G.w, len, G.np, nblk);
+      k_reduce_norm(st, G.np, nblk, G.nout);
+      const size_t hb = (size_t)(j + 1) * sizeof(c128);
+      TM_HIP(c, hipMemcpyAsync(c->host_pinned, G.dots, hb, hipMemcpyDeviceToHost, st));
+      TM_HIP(c, hipMemcpyAsync((char*)c->host_pinned + hb, G.dots2, hb, hipMemcpyDeviceToHost, st));
+      TM_HIP(c, hipMemcpyAsync((char*)c->host_pinned + 2 * hb, G.nout, sizeof(double),
+                               hipMemcpyDeviceToHost, st));
+      TM_HIP(c, hipStreamSynchronize(st));
+      const c128* hh = (const c128*)c->host_pinned;
+      const c128* hh2 = hh + (j + 1);
+      double hn;
+      std::memcpy(&hn, (const char*)c->host_pinned + 2 * hb, sizeof(double));
+      for (int i = 0; i <= j; ++i)
+        Hij(i, j) = std::complex<double>(hh[i].re + hh2[i].re, hh[i].im + hh2[i].im);
+      Hij(j + 1, j) = hn;
+      if (!std::isfinite(hn)) return set_err(c, TM_ERR_NAN, "Arnoldi produced a non-finite value");
+      if (hn > 0.0) k_scale(st, G.V + (size_t)(j + 1) * len, G.w, 1.0 / hn, len);
+      for (int i = 0; i < j; ++i) {
+        const std::complex<double> t = std::conj(cs[i]) * Hij(i, j) + std::conj(sn[i]) * Hij(i + 1, j);
+        Hij(i + 1, j) = -sn[i] * Hij(i, j) + cs[i] * Hij(i + 1, j);
+        Hij(i, j) = t;
+      }
+      const double den = std::hypot(std::abs(Hij(j, j)), std::abs(Hij(j + 1, j)));
+      if (den == 0.0) {
+        cs[j] = 1.0;
+        sn[j] = 0.0;
+      } else {
+        cs[j] = Hij(j, j) / den;
+        sn[j] = Hij(j + 1, j) / den;
+      }
+      Hij(j, j) = den;
+      Hij(j + 1, j) = 0.0;
+      gv[j + 1] = -sn[j] * gv[j];
+      gv[j] = std::conj(cs[j]) * gv[j];
+      ++it;
+      jend = j + 1;
+      if (std::abs(gv[j + 1]) <= target || it >= o.max_iter || hn == 0.0) break;
+    }
+    // back substitution H y = g
+    for (int i = jend - 1; i >= 0; --i) {
+      std::complex<double> s = gv[i];
+      for (int q = i + 1; q < jend; ++q) s -= Hij(i, q) * y[q];
+      y[i] = (Hij(i, i) != 0.0) ? s / Hij(i, i) : 0.0;
+    }
+    std::memcpy(c->host_pinned, y.data(), (size_t)jend * sizeof(c128));
+    TM_HIP(c, hipMemcpyAsync(G.dots, c->host_pinned, (size_t)jend * sizeof(c128),
+                             hipMemcpyHostToDevice, st));
+    k_update(st, x, G.V, len, jend, G.dots, len, +1.0);
+    // true residual in FP64
+    if ((rc = apply_op(c, op, TM_PREC_FP64, 1, x, G.r)) != TM_OK) return rc;
+    info.matvecs_fp64++;
+    k_sub(st, G.r, b, G.r, len);
+  }
+  info.iters = it;
+  info.rel_residual = relres;
+  info.status = (relres <= o.tol) ? TM_OK : TM_NOT_CONVERGED;
+  TM_HIP(c, hipGetLastError());
+  return TM_OK;
+}
+
+}  // namespace tmh
+
+// ============================================================== C ABI
+extern "C" {
+
+int tm_abi_version(void) { return TMHIP_ABI_VERSION; }
+
+int tm_coeff_count(int lmax) {
+  if (lmax < 1 || lmax > tmh::LMAX_SUPPORTED) return 0;
+  return 2 * lmax * (lmax + 2);
+}
+
+const char* tm_status_string(int s) {
+  switch (s) {
+    case TM_OK: return "ok";
+    case TM_NOT_CONVERGED: return "not converged";
+    case TM_ERR_INVALID_ARG: return "invalid argument";
+    case TM_ERR_OVERLAP: return "enclosing spheres overlap";
+    case TM_ERR_NOT_LATTICE: return "positions are not a z=0 rectangular lattice";
+    case TM_ERR_OOM: return "out of device memory";
+    case TM_ERR_HIP: return "HIP runtime error";
+    case TM_ERR_NAN: return "non-finite input";
+    case TM_ERR_STATE: return "call out of order";
+    default: return "unknown status";
+  }
+}
+
+const char* tm_last_error(const tm_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+void tm_default_opts(tm_solve_opts* o) {
+  if (!o) return;
+  o->tol = 1e-8;
+  o->restart = 50;
+  o->max_iter = 2000;
+  o->precision = TM_PREC_FP64;
+  o->inner_tol = 1e-4;
+  o->use_x0 = 0;
+}
+
+int tm_create(tm_ctx** out, int device, void* stream) {
+  if (!out) return TM_ERR_INVALID_ARG;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+    (void)hipGetLastError();
+    return TM_ERR_INVALID_ARG;
+  }
+  if (hipSetDevice(device) != hipSuccess) return TM_ERR_HIP;
+  tm_ctx* c = new (std::nothrow) tm_ctx();
+  if (!c) return TM_ERR_OOM;
+  c->device = device;
+  c->stream = (hipStream_t)stream;
+  *out = c;
+  return TM_OK;
+}
+
+void tm_destroy(tm_ctx* c) {
+  if (!c) return;
+  hipSetDevice(c->device);
+  hipStreamSynchronize(c->stream);
+  for (tmh::DevBuf* b : {&c->tab64, &c->tab32, &c->tabT64, &c->tabT32, &c->t64, &c->t32, &c->dt64,
+                        &c->partial, &c->xlow, &c->work_a, &c->work_b, &c->work_c, &c->basis,
+                        &c->dots, &c->dotpart, &c->scal})
+    tmh::release(*b);
+  if (c->host_pinned) hipHostFree(c->host_pinned);
+  for (int w = 0; w < 2; ++w)
+    for (auto& pr : c->prof_pending[w]) {
+      hipEventDestroy(pr.first);
+      hipEventDestroy(pr.second);
+    }
+  delete c;
+}
+
+#define CHECK_CTX(c)                  \
+  do {                                \
+    if (!(c)) return TM_ERR_INVALID_ARG; \
+    hipSetDevice((c)->device);        \
+  } while (0)
+
+int tm_set_geometry(tm_ctx* c, int n, const double* pos, double k, int lmax) {
+  CHECK_CTX(c);
+  if (n < 1 || !pos) return tmh::set_err(c, TM_ERR_INVALID_ARG, "need n >= 1 positions");
+  if (lmax < 1 || lmax > tmh::LMAX_SUPPORTED)
+    return tmh::set_err(c, TM_ERR_INVALID_ARG, "lmax must be in [1, 3]");
+  if (!(k > 0.0) || !std::isfinite(k)) return tmh::set_err(c, TM_ERR_INVALID_ARG, "k must be > 0");
+  for (int i = 0; i < 3 * n; ++i)
+    if (!std::isfinite(pos[i])) return tmh::set_err(c, TM_ERR_NAN, "non-finite position");
+  // lattice detection: row-major nx x ny grid, equal pitch, z = 0
+  const double x0 = pos[0], y0 = pos[1];
+  int nx = 1;
+  while (nx < n && pos[3 * nx + 1] == y0) ++nx;
+  if (n % nx != 0) return tmh::set_err(c, TM_ERR_NOT_LATTICE, "row length does not divide n");
+  const int ny = n / nx;
+  double pitch = 1.0;
+  if (nx > 1) pitch = pos[3] - pos[0];
+  else if (ny > 1) pitch = pos[3 * nx + 1] - pos[1];
+  if (!(pitch > 0.0)) return tmh::set_err(c, TM_ERR_NOT_LATTICE, "non-positive pitch");
+  const double tolp = 1e-9 * pitch;
+  for (int i = 0; i < n; ++i) {
+    const int ix = i % nx, iy = i / nx;
+    if (std::fabs(pos[3 * i] - (x0 + ix * pitch)) > tolp ||
+        std::fabs(pos[3 * i + 1] - (y0 + iy * pitch)) > tolp || std::fabs(pos[3 * i + 2]) > tolp)
+      return tmh::set_err(c, TM_ERR_NOT_LATTICE,
+                         "site " + std::to_string(i) + " is off the z=0 lattice");
+  }
+  tmh::Geometry& g = c->g;
+  g = tmh::Geometry{};
+  g.n = n;
+  g.nx = nx;
+  g.ny = ny;
+  g.lmax = lmax;
+  g.pitch = pitch;
+  g.k = k;
+  g.x0 = x0;
+  g.y0 = y0;
+  g.tnx = nx;
+  g.tny = ny;
+  tmh::host_slot_maps(lmax, g, c->maps);
+  c->have_geom = c->have_t = c->have_dt = c->have_tabT = false;
+  int rc;
+  if ((rc = tmh::build_tables(c)) != TM_OK) return rc;
+  const size_t vb = (size_t)g.vec_len();
+  if ((rc = tmh::ensure(c, c->t64, vb * sizeof(c128))) != TM_OK) return rc;
+  if ((rc = tmh::ensure(c, c->t32, vb * sizeof(tmh::c64))) != TM_OK) return rc;
+  if ((rc = tmh::ensure(c, c->dt64, vb * sizeof(c128))) != TM_OK) return rc;
+  TM_HIP(c, hipMemsetAsync(c->t64.p, 0, vb * sizeof(c128), c->stream));
+  TM_HIP(c, hipMemsetAsync(c->t32.p, 0, vb * sizeof(tmh::c64), c->stream));
+  TM_HIP(c, hipMemsetAsync(c->dt64.p, 0, vb * sizeof(c128), c->stream));
+  c->have_geom = true;
+  return TM_OK;
+}
+
+int tm_get_lattice(const tm_ctx* c, int* nx, int* ny, double* pitch) {
+  if (!c || !c->have_geom) return TM_ERR_STATE;
+  if (nx) *nx = c->g.nx;
+  if (ny) *ny = c->g.ny;
+  if (pitch) *pitch = c->g.pitch;
+  return TM_OK;
+}
+
+int tm_set_spheres(tm_ctx* c, const double* radii, double n_re, double n_im) {
+  CHECK_CTX(c);
+  if (!c->have_geom) return tmh::set_err(c, TM_ERR_STATE, "set geometry first");
+  if (!radii) return tmh::set_err(c, TM_ERR_INVALID_ARG, "null radii");
+  if (!std::isfinite(n_re) || !std::isfinite(n_im) || n_im < 0.0)
+    return tmh::set_err(c, TM_ERR_INVALID_ARG, "invalid refractive index");
+  const tmh::Geometry& g = c->g;
+  std::vector<double> r(g.n);
+  TM_HIP(c, hipMemcpyAsync(r.data(), radii, g.n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  TM_HIP(c, hipStreamSynchronize(c->stream));
+  const double nabs = std::hypot(n_re, n_im);
+  for (int i = 0; i < g.n; ++i) {
+    if (!std::isfinite(r[i])) return tmh::set_err(c, TM_ERR_NAN, "non-finite radius");
+    if (!(r[i] > 0.0)) return tmh::set_err(c, TM_ERR_INVALID_ARG, "radius must be > 0");
+    if (g.k * r[i] * std::max(1.0, nabs) > 12.0)
+      return tmh::set_err(c, TM_ERR_INVALID_ARG, "k r |n| > 12 is outside the supported range");
+  }
+  for (int i = 0; i < g.n; ++i) {
+    const int ix = i % g.nx, iy = i / g.nx;
+    if (ix + 1 < g.nx && r[i] + r[i + 1] >= g.pitch)
+      return tmh::set_err(c, TM_ERR_OVERLAP, "spheres " + std::to_string(i) + " and " +
+                                                std::to_string(i + 1) + " overlap");
+    if (iy + 1 < g.ny && r[i] + r[i + g.nx] >= g.pitch)
+      return tmh::set_err(c, TM_ERR_OVERLAP, "spheres " + std::to_string(i) + " and " +
+                                                std::to_string(i + g.nx) + " overlap");
+  }
+  int rc = tmh::launch_mie(c, radii, n_re, n_im);
+  if (rc != TM_OK) return rc;
+  c->have_t = c->have_dt = true;
+  return TM_OK;
+}
+
+int tm_set_tmatrix_diag(tm_ctx* c, const tm_c128* t) {
+  CHECK_CTX(c);
+  if (!c->have_geom) return tmh::set_err(c, TM_ERR_STATE, "set geometry first");
+  if (!t) return tmh::set_err(c, TM_ERR_INVALID_ARG, "null T");
+  int rc = tmh::launch_set_tdiag(c, t);
+  if (rc != TM_OK) return rc;
+  TM_HIP(c, hipMemsetAsync(c->dt64.p, 0, c->dt64.bytes, c->stream));
+  c->have_t = true;
+  c->have_dt = false;
+  return TM_OK;
+}
+
+int tm_get_tmatrix_diag(tm_ctx* c, tm_c128* t, tm_c128* dtdr) {
+  CHECK_CTX(c);
+  if (!c->have_t) return tmh::set_err(c, TM_ERR_STATE, "T not set");
+  if (!t) return tmh::set_err(c, TM_ERR_INVALID_ARG, "null output");
+  return tmh::launch_get_tdiag(c, t, c->have_dt ? dtdr : nullptr);
+}
+
+int tm_plane_wave_rhs(tm_ctx* c, int R, const double* khat, const tm_c128* pol, tm_c128* a0) {
+  CHECK_CTX(c);
+  if (!c->have_geom) return tmh::set_err(c, TM_ERR_STATE, "set geometry first");
+  if (R < 1 || !khat || !pol || !a0) return tmh::set_err(c, TM_ERR_INVALID_ARG, "bad arguments");
+  for (int r = 0; r < R; ++r) {
+    const double* kh = khat + 3 * r;
+    const double nk = std::sqrt(kh[0] * kh[0] + kh[1] * kh[1] + kh[2] * kh[2]);
+    if (!std::isfinite(nk) || std::fabs(nk - 1.0) > 1e-9)
+      return tmh::set_err(c, TM_ERR_INVALID_ARG, "khat must be a unit vector");
+    double dr = 0, di = 0;
+    for (int q = 0; q < 3; ++q) {
+      if (!std::isfinite(pol[3 * r + q].re) || !std::isfinite(pol[3 * r + q].im))
+        return tmh::set_err(c, TM_ERR_NAN, "non-finite polarisation");
+      dr += kh[q] * pol[3 * r + q].re;
+      di += kh[q] * pol[3 * r + q].im;
+    }
+    if (std::hypot(dr, di) > 1e-9)
+      return tmh::set_err(c, TM_ERR_INVALID_ARG, "polarisation must be transverse to khat");
+  }
+  return tmh::launch_plane_wave(c, R, khat, pol, a0);
+}
+
+static int validate_opts(tm_ctx* c, const tm_solve_opts* o) {
+  if (!o) return tmh::set_err(c, TM_ERR_INVALID_ARG, "null options");
+  if (!(o->tol > 0.0) || o->restart < 1 || o->restart > 200 || o->max_iter < 1 ||
+      (o->precision != TM_PREC_FP64 && o->precision != TM_PREC_MIXED) ||
+      (o->precision == TM_PREC_MIXED && !(o->inner_tol > 0.0 && o->inner_tol < 1.0)))
+    return tmh::set_err(c, TM_ERR_INVALID_ARG, "invalid solver options");
+  return TM_OK;
+}
+
+static int solve_common(tm_ctx* c, Op op, int R, const tm_c128* rhs, tm_c128* out,
+                        const tm_solve_opts* o, tm_solve_info* info) {
+  CHECK_CTX(c);
+  if (!c->have_geom || !c->have_t) return tmh::set_err(c, TM_ERR_STATE, "geometry and T must be set");
+  if (R < 1 || !rhs || !out || !info) return tmh::set_err(c, TM_ERR_INVALID_ARG, "bad arguments");
+  int rc;
+  if ((rc = validate_opts(c, o)) != TM_OK) return rc;
+  const tmh::Geometry& g = c->g;
+  const long long len = g.vec_len();
+  if ((rc = tmh::ensure(c, c->work_a, (size_t)R * len * sizeof(c128))) != TM_OK) return rc;
+  if ((rc = tmh::ensure(c, c->work_b, (size_t)R * len * sizeof(c128))) != TM_OK) return rc;
+  c128* bsl = (c128*)c->work_a.p;
+  c128* xsl = (c128*)c->work_b.p;
+  tmh::pack_slots(c->stream, g, c->maps, R, rhs, bsl);
+  if (op == Op::Forward) tmh::k_mul_t(c->stream, bsl, (const c128*)c->t64.p, bsl, len, R);
+  if (o->use_x0) tmh::pack_slots(c->stream, g, c->maps, R, out, xsl);
+  bool all_ok = true;
+  for (int r = 0; r < R; ++r) {
+    rc = tmh::gmres(c, op, bsl + (size_t)r * len, xsl + (size_t)r * len, *o, o->use_x0 != 0, info[r]);
+    if (rc != TM_OK) return rc;
+    if (info[r].status != TM_OK) all_ok = false;
+  }
+  tmh::unpack_slots(c->stream, g, c->maps, R, xsl, out);
+  TM_HIP(c, hipStreamSynchronize(c->stream));
+  return all_ok ? TM_OK : TM_NOT_CONVERGED;
+}
+
+int tm_solve(tm_ctx* c, int R, const tm_c128* a0, tm_c128* s, const tm_solve_opts* o,
+             tm_solve_info* info) {
+  return solve_common(c, Op::Forward, R, a0, s, o, info);
+}
+
+int tm_adjoint_solve(tm_ctx* c, int R, const tm_c128* v, tm_c128* mu, const tm_solve_opts* o,
+                     tm_solve_info* info) {
+  return solve_common(c, Op::Adjoint, R, v, mu, o, info);
+}
+
+int tm_apply_operator(tm_ctx* c, int R, const tm_c128* x, tm_c128* y, int precision, int op) {
+  CHECK_CTX(c);
+  if (!c->have_geom) return tmh::set_err(c, TM_ERR_STATE, "set geometry first");
+  if ((op == TM_OP_FORWARD || op == TM_OP_ADJOINT) && !c->have_t)
+    return tmh::set_err(c, TM_ERR_STATE, "T not set");
+  if (R < 1 || !x || !y || x == y || op < 0 || op > 3 ||
+      (precision != TM_PREC_FP64 && precision != TM_PREC_MIXED))
+    return tmh::set_err(c, TM_ERR_INVALID_ARG, "bad arguments");
+  const tmh::Geometry& g = c->g;
+  const long long len = g.vec_len();
+  int rc;
+  if ((rc = tmh::ensure(c, c->work_a, (size_t)R * len * sizeof(c128))) != TM_OK) return rc;
+  if ((rc = tmh::ensure(c, c->work_b, (size_t)R * len * sizeof(c128))) != TM_OK) return rc;
+  tmh::pack_slots(c->stream, g, c->maps, R, x, (c128*)c->work_a.p);
+  if ((rc = tmh::apply_op(c, (Op)op, precision, R, (const c128*)c->work_a.p, (c128*)c->work_b.p)) !=
+      TM_OK)
+    return rc;
+  tmh::unpack_slots(c->stream, g, c->maps, R, (const c128*)c->work_b.p, y);
+  TM_HIP(c, hipGetLastError());
+  return TM_OK;
+}
+
+int tm_near_field(tm_ctx* c, int R, const tm_c128* s, int P, const double* pts, tm_c128* E,
+                  int precision) {
+  CHECK_CTX(c);
+  if (!c->have_geom) return tmh::set_err(c, TM_ERR_STATE, "set geometry first");
+  if (R < 1 || P < 0 || !s || (P > 0 && (!pts || !E)) ||
+      (precision != TM_PREC_FP64 && precision != TM_PREC_MIXED))
+    return tmh::set_err(c, TM_ERR_INVALID_ARG, "bad arguments");
+  if (P == 0) return TM_OK;
+  return tmh::launch_near_field(c, R, s, P, pts, E, precision);
+}
+
+int tm_far_field(tm_ctx* c, int R, const tm_c128* s, int D, const double* dirs, tm_c128* F) {
+  CHECK_CTX(c);
+  if (!c->have_geom) return tmh::set_err(c, TM_ERR_STATE, "set geometry first");
+  if (R < 1 || D < 0 || !s || (D > 0 && (!dirs || !F)))
+    return tmh::set_err(c, TM_ERR_INVALID_ARG, "bad arguments");
+  if (D == 0) return TM_OK;
+  return tmh::launch_far_field(c, R, s, D, dirs, F);
+}
+
+int tm_detector_vector(tm_ctx* c, const double* xd, const tm_c128* w, tm_c128* v) {
+  CHECK_CTX(c);
+  if (!c->have_geom) return tmh::set_err(c, TM_ERR_STATE, "set geometry first");
+  if (!xd || !w || !v) return tmh::set_err(c, TM_ERR_INVALID_ARG, "bad arguments");
+  for (int q = 0; q < 3; ++q)
+    if (!std::isfinite(xd[q]) || !std::isfinite(w[q].re) || !std::isfinite(w[q].im))
+      return tmh::set_err(c, TM_ERR_NAN, "non-finite detector input");
+  return tmh::launch_detector(c, xd, w, v);
+}
+
+int tm_grad_radius(tm_ctx* c, int R, const tm_c128* mu, const tm_c128* s, const tm_c128* a0,
+                   double* grad) {
+  CHECK_CTX(c);
+  if (!c->have_dt) return tmh::set_err(c, TM_ERR_STATE, "dT/dr unavailable (spheres not set)");
+  if (R < 1 || !mu || !s || !a0 || !grad) return tmh::set_err(c, TM_ERR_INVALID_ARG, "bad arguments");
+  const tmh::Geometry& g = c->g;
+  const long long len = g.vec_len();
+  int rc;
+  if ((rc = tmh::ensure(c, c->work_a, (size_t)2 * R * len * sizeof(c128))) != TM_OK) return rc;
+  if ((rc = tmh::ensure(c, c->work_b, (size_t)R * len * sizeof(c128))) != TM_OK) return rc;
+  c128* s_sl = (c128*)c->work_a.p;
+  c128* a_sl = s_sl + (size_t)R * len;
+  c128* as_sl = (c128*)c->work_b.p;
+  // exciting field a_exc = a0 + A s
+  tmh::pack_slots(c->stream, g, c->maps, R, s, s_sl);
+  if ((rc = tmh::apply_op(c, Op::Coupling, TM_PREC_FP64, R, s_sl, as_sl)) != TM_OK) return rc;
+  tmh::pack_slots(c->stream, g, c->maps, R, a0, a_sl);
+  tmh::k_add(c->stream, a_sl, a_sl, as_sl, (long long)R * len);
+  tmh::pack_slots(c->stream, g, c->maps, R, mu, s_sl);
+  return tmh::launch_grad(c, R, s_sl, a_sl, grad);
+}
+
+int tm_profile_enable(tm_ctx* c, int enable) {
+  CHECK_CTX(c);
+  c->prof = enable != 0;
+  return TM_OK;
+}
+
+int tm_profile_reset(tm_ctx* c) {
+  CHECK_CTX(c);
+  hipStreamSynchronize(c->stream);
+  for (int w = 0; w < 2; ++w) {
+    for (auto& pr : c->prof_pending[w]) {
+      hipEventDestroy(pr.first);
+      hipEventDestroy(pr.second);
+    }
+    c->prof_pending[w].clear();
+    c->prof_acc[w] = tmh::ProfAcc{};
+  }
+  return TM_OK;
+}
+
+int tm_profile_query(tm_ctx* c, int which, double* total_ms, long long* launches,
+                     double* flops_per_launch) {
+  CHECK_CTX(c);
+  if (which < 0 || which > 1) return tmh::set_err(c, TM_ERR_INVALID_ARG, "which must be 0 or 1");
+  TM_HIP(c, hipStreamSynchronize(c->stream));
+  for (auto& pr : c->prof_pending[which]) {
+    float ms = 0.f;
+    TM_HIP(c, hipEventElapsedTime(&ms, pr.first, pr.second));
+    c->prof_acc[which].ms += ms;
+    c->prof_acc[which].launches++;
+    hipEventDestroy(pr.first);
+    hipEventDestroy(pr.second);
+  }
+  c->prof_pending[which].clear();
+  if (total_ms) *total_ms = c->prof_acc[which].ms;
+  if (launches) *launches = c->prof_acc[which].launches;
+  if (flops_per_launch) *flops_per_launch = c->prof_acc[which].flops;
+  return TM_OK;
+}
+
+}  // extern "C"

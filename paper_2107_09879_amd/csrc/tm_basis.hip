@@ -1,0 +1,564 @@
+// Per-scatterer and readout kernels built on the spherical-wave basis:
+//   * Mie T-matrix diagonal of a sphere and its radius derivative
+//     (the sphere case of App. I.B's T-matrix; Lorenz-Mie coefficients with
+//     Riccati-Bessel functions, t_{l,p=0} = -b_l, t_{l,p=1} = -a_l);
+//   * plane-wave incident coefficients (App. II, eqs. "integrand_p_0" and
+//     "integrand_p_1": the second printed forms, with the scatterer-centre
+//     phase e^{i k khat.x_i});
+//   * scattered near field E_sca(x) = sum_i s_i^T Phi(k(x - x_i)) (App. I.C,
+//     eq. "sca_fld_concise") and its far-field amplitude;
+//   * point-detector vector and radius-gradient contraction (App. IV).
+// Basis (App. I.A): Phi_lm0 = z_l [i pi theta_hat - tau phi_hat] e^{im phi} / sqrt(2l(l+1)),
+// Phi_lm1 = [l(l+1) z_l/rho Pbar r_hat + (rho z_l)'/rho (tau theta_hat + i pi phi_hat)]
+// e^{im phi} / sqrt(2l(l+1)), Pbar normalised without Condon-Shortley phase,
+// pi = m Pbar / sin(theta), tau = d Pbar / d theta.
+#include <cmath>
+
+#include "tm_internal.h"
+
+namespace tmh {
+
+template <typename T>
+struct cx {
+  T re, im;
+  __device__ cx() : re(0), im(0) {}
+  __device__ cx(T r, T i) : re(r), im(i) {}
+};
+template <typename T>
+__device__ inline cx<T> operator+(cx<T> a, cx<T> b) { return cx<T>(a.re + b.re, a.im + b.im); }
+template <typename T>
+__device__ inline cx<T> operator-(cx<T> a, cx<T> b) { return cx<T>(a.re - b.re, a.im - b.im); }
+template <typename T>
+__device__ inline cx<T> operator*(cx<T> a, cx<T> b) {
+  return cx<T>(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+template <typename T>
+__device__ inline cx<T> operator*(T a, cx<T> b) { return cx<T>(a * b.re, a * b.im); }
+template <typename T>
+__device__ inline cx<T> operator/(cx<T> a, cx<T> b) {
+  const T d = b.re * b.re + b.im * b.im;
+  return cx<T>((a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d);
+}
+template <typename T>
+__device__ inline cx<T> mul_i(cx<T> a) { return cx<T>(-a.im, a.re); }
+// i^e
+template <typename T>
+__device__ inline cx<T> ipow(int e) {
+  switch (((e % 4) + 4) % 4) {
+    case 0: return cx<T>(1, 0);
+    case 1: return cx<T>(0, 1);
+    case 2: return cx<T>(-1, 0);
+    default: return cx<T>(0, -1);
+  }
+}
+
+__device__ inline void sincos_t(float x, float* s, float* c) { sincosf(x, s, c); }
+__device__ inline void sincos_t(double x, double* s, double* c) { sincos(x, s, c); }
+
+__device__ inline void plm_of_n(int n, int lmax, int& p, int& l, int& m) {
+  const int half = lmax * (lmax + 2);
+  p = n / half;
+  const int r = n - p * half;
+  l = 1;
+  while ((l + 1) * (l + 1) - 1 <= r) ++l;
+  m = r - (l * (l + 1) - 1);
+}
+__device__ inline int n_of_plm(int p, int l, int m, int lmax) {
+  return p * lmax * (lmax + 2) + l * (l + 1) - 1 + m;
+}
+
+// Normalised Legendre data at one (l, |m|): Pbar, U = Pbar/sin(theta) (|m| >= 1,
+// regular at the poles), tau = dPbar/dtheta.  Recurrences on
+// u_l^m = P_l^m / sin(theta): u_m^m = (2m-1)!! sin^{m-1}, (l-m) u_l^m =
+// cos (2l-1) u_{l-1}^m - (l+m-1) u_{l-2}^m, dP_l^m/dtheta = l cos u_l^m -
+// (l+m) u_{l-1}^m; for m = 0, tau = -P_l^1 = -sin u_l^1.
+template <typename T>
+__device__ inline void legendre_one(int l, int am, T ct, T st, T& P, T& U, T& tau) {
+  T nrm = (T)(2 * l + 1) / (T)2;
+  for (int q = l - am + 1; q <= l + am; ++q) nrm /= (T)q;
+  nrm = sqrt(nrm);
+  if (am == 0) {
+    T p0 = 1, p1 = ct;
+    T Pl = (l == 0) ? p0 : p1;
+    for (int q = 2; q <= l; ++q) {
+      const T p2 = ((T)(2 * q - 1) * ct * p1 - (T)(q - 1) * p0) / (T)q;
+      p0 = p1;
+      p1 = p2;
+      Pl = p2;
+    }
+    T u0 = 0, u1 = 1, ul = (l >= 1) ? (T)1 : (T)0;
+    for (int q = 2; q <= l; ++q) {
+      const T u2 = ((T)(2 * q - 1) * ct * u1 - (T)q * u0) / (T)(q - 1);
+      u0 = u1;
+      u1 = u2;
+      ul = u2;
+    }
+    P = nrm * Pl;
+    U = 0;
+    tau = -nrm * st * ul;
+    return;
+  }
+  T um = 1;
+  for (int q = 1; q <= 2 * am - 1; q += 2) um *= (T)q;
+  for (int q = 0; q < am - 1; ++q) um *= st;
+  T uprev = 0, ucur = um;
+  for (int q = am + 1; q <= l; ++q) {
+    const T un = ((T)(2 * q - 1) * ct * ucur - (T)(q + am - 1) * uprev) / (T)(q - am);
+    uprev = ucur;
+    ucur = un;
+  }
+  P = nrm * st * ucur;
+  U = nrm * ucur;
+  tau = nrm * ((T)l * ct * ucur - (T)(l + am) * uprev);
+}
+
+// ---------------------------------------------------------------- Mie
+// j_l(z) by its power series z^l/(2l+1)!! sum_k (-z^2/2)^k / (k! prod (2l+2i+1))
+// (accurate for the small size parameters of subwavelength spheres, |z| <= 12).
+__device__ inline cx<double> sph_j_series(int l, cx<double> z) {
+  const cx<double> mz2h = (-0.5) * (z * z);
+  cx<double> term(1.0, 0.0), sum(1.0, 0.0);
+  for (int k = 1; k < 120; ++k) {
+    term = (1.0 / ((double)k * (double)(2 * l + 2 * k + 1))) * (term * mz2h);
+    sum = sum + term;
+    if (fabs(term.re) + fabs(term.im) < 1e-18 * (fabs(sum.re) + fabs(sum.im))) break;
+  }
+  cx<double> zl(1.0, 0.0);
+  double df = 1.0;
+  for (int q = 0; q < l; ++q) zl = zl * z;
+  for (int q = 1; q <= 2 * l + 1; q += 2) df *= (double)q;
+  return (1.0 / df) * (zl * sum);
+}
+
+__global__ void mie_kernel(const double* __restrict__ radii, int N, double k, double nre,
+                           double nim, int lmax, SlotMaps mp, c128* __restrict__ t64,
+                           c64* __restrict__ t32, c128* __restrict__ dt64) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const double x = k * radii[i];
+  const cx<double> m(nre, nim);
+  const cx<double> X(x, 0.0);
+  const cx<double> Y = m * X;
+  cx<double> jx[LMAX_SUPPORTED + 1], hx[LMAX_SUPPORTED + 1], jy[LMAX_SUPPORTED + 1];
+  double sx, cxs;
+  sincos(x, &sx, &cxs);
+  double y0 = -cxs / x, y1 = -cxs / (x * x) - sx / x;
+  for (int l = 0; l <= lmax; ++l) {
+    jx[l] = sph_j_series(l, X);
+    jy[l] = sph_j_series(l, Y);
+    double yl;
+    if (l == 0) yl = y0;
+    else if (l == 1) yl = y1;
+    else {
+      yl = (double)(2 * l - 1) / x * y1 - y0;
+      y0 = y1;
+      y1 = yl;
+    }
+    hx[l] = cx<double>(jx[l].re, yl);
+  }
+  for (int l = 1; l <= lmax; ++l) {
+    const double ll = (double)(l * (l + 1));
+    const cx<double> px = X * jx[l];
+    const cx<double> pdx = X * jx[l - 1] - (double)l * jx[l];
+    const cx<double> xx = X * hx[l];
+    const cx<double> xdx = X * hx[l - 1] - (double)l * hx[l];
+    const cx<double> py = Y * jy[l];
+    const cx<double> pdy = Y * jy[l - 1] - (double)l * jy[l];
+    const double fx = ll / (x * x) - 1.0;
+    const cx<double> fy = cx<double>(ll, 0.0) / (Y * Y) - cx<double>(1.0, 0.0);
+    const cx<double> pddx = fx * px, xddx = fx * xx, pddy = fy * py;
+    const cx<double> na = m * py * pdx - px * pdy;
+    const cx<double> da = m * py * xdx - xx * pdy;
+    const cx<double> nb = py * pdx - m * px * pdy;
+    const cx<double> db = py * xdx - m * xx * pdy;
+    const cx<double> m2 = m * m;
+    const cx<double> na_x = m2 * pdy * pdx + m * py * pddx - pdx * pdy - m * px * pddy;
+    const cx<double> da_x = m2 * pdy * xdx + m * py * xddx - xdx * pdy - m * xx * pddy;
+    const cx<double> nb_x = m * pdy * pdx + py * pddx - m * pdx * pdy - m2 * px * pddy;
+    const cx<double> db_x = m * pdy * xdx + py * xddx - m * xdx * pdy - m2 * xx * pddy;
+    const cx<double> a = na / da, b = nb / db;
+    const cx<double> dadx = (na_x * da - na * da_x) / (da * da);
+    const cx<double> dbdx = (nb_x * db - nb * db_x) / (db * db);
+    for (int mm = -l; mm <= l; ++mm) {
+      for (int p = 0; p < 2; ++p) {
+        const int n = n_of_plm(p, l, mm, lmax);
+        const size_t o = ((size_t)mp.cls_of[n] * N + i) * SLOTS + mp.slot_of[n];
+        const cx<double> t = (p == 0) ? cx<double>(-b.re, -b.im) : cx<double>(-a.re, -a.im);
+        const cx<double> d = (p == 0) ? (-k) * dbdx : (-k) * dadx;
+        t64[o] = c128{t.re, t.im};
+        t32[o] = c64{(float)t.re, (float)t.im};
+        dt64[o] = c128{d.re, d.im};
+      }
+    }
+  }
+}
+
+// t (boundary [N][L]) -> slot layouts
+__global__ void set_t_kernel(const tm_c128* __restrict__ t, int N, SlotMaps mp,
+                             c128* __restrict__ t64, c64* __restrict__ t32) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)N * mp.L) return;
+  const int n = (int)(e % mp.L);
+  const long long i = e / mp.L;
+  const size_t o = ((size_t)mp.cls_of[n] * N + i) * SLOTS + mp.slot_of[n];
+  const tm_c128 v = t[e];
+  t64[o] = c128{v.re, v.im};
+  t32[o] = c64{(float)v.re, (float)v.im};
+}
+
+// ---------------------------------------------------------------- plane wave
+struct PwArgs {
+  double khat[3 * 8];
+  double pol[6 * 8];  // re, im interleaved per component
+};
+
+__global__ void plane_wave_kernel(PwArgs pw, int R, int N, int L, int lmax, int nx, double x0,
+                                  double y0, double pitch, double k, tm_c128* __restrict__ a0) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)R * N * L) return;
+  const int n = (int)(e % L);
+  const long long i = (e / L) % N;
+  const int r = (int)(e / ((long long)L * N));
+  const double* kh = pw.khat + 3 * r;
+  const double* po = pw.pol + 6 * r;
+  const double sb = sqrt(kh[0] * kh[0] + kh[1] * kh[1]);
+  const double cb = kh[2];
+  const double al = (sb > 0.0) ? atan2(kh[1], kh[0]) : 0.0;
+  double sa, ca;
+  sincos(al, &sa, &ca);
+  const double bh[3] = {cb * ca, cb * sa, -sb};
+  const double ah[3] = {-sa, ca, 0.0};
+  cx<double> bA, aA;
+  for (int q = 0; q < 3; ++q) {
+    const cx<double> pq(po[2 * q], po[2 * q + 1]);
+    bA = bA + bh[q] * pq;
+    aA = aA + ah[q] * pq;
+  }
+  int p, l, m;
+  plm_of_n(n, lmax, p, l, m);
+  double P, U, tau;
+  legendre_one<double>(l, m < 0 ? -m : m, cb, sb, P, U, tau);
+  const double pi = (double)m * U;
+  double sm, cm;
+  sincos(-(double)m * al, &sm, &cm);
+  const cx<double> pre = (-4.0 / sqrt(2.0 * l * (l + 1))) * cx<double>(cm, sm);
+  cx<double> v;
+  if (p == 0)
+    v = pre * ipow<double>(l) * (mul_i(pi * bA) + tau * aA);
+  else
+    v = pre * ipow<double>(l + 1) * (tau * bA - mul_i(pi * aA));
+  const double xi = x0 + pitch * (double)(i % nx), yi = y0 + pitch * (double)(i / nx);
+  double sp, cp;
+  sincos(k * (kh[0] * xi + kh[1] * yi), &sp, &cp);
+  v = cx<double>(cp, sp) * v;
+  a0[e] = tm_c128{v.re, v.im};
+}
+
+// ---------------------------------------------------------------- readout
+// Hankel functions h_0..h_lmax at x with e^{ix} given as (c, s).
+template <typename T>
+__device__ inline void hankel_set(T x, T c, T s, int lmax, cx<T>* h) {
+  const T ix = (T)1 / x;
+  h[0] = cx<T>(s * ix, -c * ix);
+  h[1] = cx<T>(-(c * x - s) * ix * ix, -(s * x + c) * ix * ix);
+  for (int q = 1; q < lmax; ++q) {
+    const T f = (T)(2 * q + 1) * ix;
+    h[q + 1] = cx<T>(f * h[q].re - h[q - 1].re, f * h[q].im - h[q - 1].im);
+  }
+}
+
+constexpr int NF_MAXR = 4;
+
+template <typename T>
+__global__ __launch_bounds__(256) void near_field_kernel(
+    const tm_c128* __restrict__ s, int R, int N, int L, int lmax, int nx, double x0, double y0,
+    double pitch, double k, const double* __restrict__ pts, int P, tm_c128* __restrict__ E) {
+  const int ip = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = ip < P;
+  const double px = live ? pts[3 * ip] : 0.0, py = live ? pts[3 * ip + 1] : 0.0,
+               pz = live ? pts[3 * ip + 2] : 1.0;
+  cx<T> acc[NF_MAXR][3];
+  const double twopi = 6.283185307179586476925286766559;
+  for (int i = 0; i < N; ++i) {
+    const double dx = px - (x0 + pitch * (double)(i % nx));
+    const double dy = py - (y0 + pitch * (double)(i / nx));
+    const double dz = pz;
+    const double rho2 = dx * dx + dy * dy;
+    const double rr = sqrt(rho2 + dz * dz);
+    const double kr = k * rr;
+    const double red = kr - twopi * rint(kr / twopi);
+    T sn, cs;
+    sincos_t((T)red, &sn, &cs);
+    const T x = (T)kr;
+    const T ct = (T)(dz / rr), st = (T)(sqrt(rho2) / rr);
+    T cf = 1, sf = 0;
+    if (rho2 > 0.0) {
+      const double rh = sqrt(rho2);
+      cf = (T)(dx / rh);
+      sf = (T)(dy / rh);
+    }
+    cx<T> h[LMAX_SUPPORTED + 1];
+    hankel_set<T>(x, cs, sn, lmax, h);
+    cx<T> Er[NF_MAXR], Et[NF_MAXR], Ep[NF_MAXR];
+    for (int l = 1; l <= lmax; ++l) {
+      const cx<T> dh((x * h[l - 1].re - (T)l * h[l].re) / x, (x * h[l - 1].im - (T)l * h[l].im) / x);
+      const T nrm = (T)1 / sqrt((T)(2 * l * (l + 1)));
+      const cx<T> hr = ((T)(l * (l + 1)) / x) * h[l];
+      for (int am = 0; am <= l; ++am) {
+        T Pb, U, tau;
+        legendre_one<T>(l, am, ct, st, Pb, U, tau);
+        // e^{i am phi}
+        cx<T> e(1, 0);
+        for (int q = 0; q < am; ++q) e = e * cx<T>(cf, sf);
+        for (int sg = (am == 0 ? 1 : -1); sg <= 1; sg += 2) {
+          const int m = sg * am;
+          const cx<T> em = (sg > 0) ? e : cx<T>(e.re, -e.im);
+          const T pi = (T)m * U;
+          const int n0 = n_of_plm(0, l, m, lmax), n1 = n_of_plm(1, l, m, lmax);
+          for (int r = 0; r < R; ++r) {
+            const tm_c128 a = s[((size_t)r * N + i) * L + n0];
+            const tm_c128 b = s[((size_t)r * N + i) * L + n1];
+            const cx<T> sM = nrm * (cx<T>((T)a.re, (T)a.im) * em);
+            const cx<T> sN = nrm * (cx<T>((T)b.re, (T)b.im) * em);
+            Er[r] = Er[r] + (Pb * (hr * sN));
+            Et[r] = Et[r] + mul_i(pi * (h[l] * sM)) + tau * (dh * sN);
+            Ep[r] = Ep[r] - tau * (h[l] * sM) + mul_i(pi * (dh * sN));
+          }
+        }
+      }
+    }
+    for (int r = 0; r < R; ++r) {
+      acc[r][0] = acc[r][0] + (st * cf) * Er[r] + (ct * cf) * Et[r] - sf * Ep[r];
+      acc[r][1] = acc[r][1] + (st * sf) * Er[r] + (ct * sf) * Et[r] + cf * Ep[r];
+      acc[r][2] = acc[r][2] + ct * Er[r] - st * Et[r];
+    }
+  }
+  if (!live) return;
+  for (int r = 0; r < R; ++r)
+    for (int q = 0; q < 3; ++q)
+      E[((size_t)r * P + ip) * 3 + q] = tm_c128{(double)acc[r][q].re, (double)acc[r][q].im};
+}
+
+// F(d) = (1/k) sum_i e^{-ik d.x_i} sum_n s_{i,n} F_n(d), with
+// F_n = (-i)^{l+1} [i pi th - tau ph] e^{im phi} (p = 0), (-i)^l [tau th + i pi ph] e^{im phi}
+// (p = 1), times 1/sqrt(2l(l+1)): the h_l(x) ~ (-i)^{l+1} e^{ix}/x limit.
+__global__ void far_field_kernel(const tm_c128* __restrict__ s, int R, int N, int L, int lmax,
+                                 int nx, double x0, double y0, double pitch, double k,
+                                 const double* __restrict__ dirs, int D,
+                                 tm_c128* __restrict__ F) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= R * D) return;
+  const int r = e / D, id = e % D;
+  const double ux = dirs[3 * id], uy = dirs[3 * id + 1], uz = dirs[3 * id + 2];
+  cx<double> cn[2 * LMAX_SUPPORTED * (LMAX_SUPPORTED + 2)];
+  for (int i = 0; i < N; ++i) {
+    const double xi = x0 + pitch * (double)(i % nx), yi = y0 + pitch * (double)(i / nx);
+    double sp, cp;
+    sincos(-k * (ux * xi + uy * yi), &sp, &cp);
+    const cx<double> ph(cp, sp);
+    const tm_c128* si = s + ((size_t)r * N + i) * L;
+    for (int n = 0; n < L; ++n) cn[n] = cn[n] + ph * cx<double>(si[n].re, si[n].im);
+  }
+  const double rho = sqrt(ux * ux + uy * uy);
+  const double ct = uz, st = rho;
+  double cf = 1.0, sf = 0.0;
+  if (rho > 0.0) {
+    cf = ux / rho;
+    sf = uy / rho;
+  }
+  cx<double> Ft, Fp;
+  for (int n = 0; n < L; ++n) {
+    int p, l, m;
+    plm_of_n(n, lmax, p, l, m);
+    double Pb, U, tau;
+    legendre_one<double>(l, m < 0 ? -m : m, ct, st, Pb, U, tau);
+    const double pi = (double)m * U;
+    double sm, cm;
+    sincos((double)m * atan2(sf, cf), &sm, &cm);
+    const cx<double> em(cm, sm);
+    const double nrm = 1.0 / sqrt(2.0 * l * (l + 1));
+    const cx<double> c = nrm * (cn[n] * em);
+    if (p == 0) {
+      const cx<double> f = ipow<double>(-(l + 1)) * c;  // (-i)^{l+1} = i^{-(l+1)}
+      Ft = Ft + mul_i(pi * f);
+      Fp = Fp - tau * f;
+    } else {
+      const cx<double> f = ipow<double>(-l) * c;
+      Ft = Ft + tau * f;
+      Fp = Fp + mul_i(pi * f);
+    }
+  }
+  const double ik = 1.0 / k;
+  const cx<double> Fx = ik * ((ct * cf) * Ft - sf * Fp);
+  const cx<double> Fy = ik * ((ct * sf) * Ft + cf * Fp);
+  const cx<double> Fz = ik * ((-st) * Ft);
+  F[(size_t)e * 3 + 0] = tm_c128{Fx.re, Fx.im};
+  F[(size_t)e * 3 + 1] = tm_c128{Fy.re, Fy.im};
+  F[(size_t)e * 3 + 2] = tm_c128{Fz.re, Fz.im};
+}
+
+// v[i][n] = sum_c w_c Phi_n(k(xd - x_i))_c
+__global__ void detector_kernel(double xdx, double xdy, double xdz, double wxr, double wxi,
+                                double wyr, double wyi, double wzr, double wzi, int N, int L,
+                                int lmax, int nx, double x0, double y0, double pitch, double k,
+                                tm_c128* __restrict__ v) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)N * L) return;
+  const int n = (int)(e % L);
+  const long long i = e / L;
+  const double dx = xdx - (x0 + pitch * (double)(i % nx));
+  const double dy = xdy - (y0 + pitch * (double)(i / nx));
+  const double dz = xdz;
+  const double rho2 = dx * dx + dy * dy;
+  const double rr = sqrt(rho2 + dz * dz);
+  const double x = k * rr;
+  double sn, cs;
+  sincos(x, &sn, &cs);
+  cx<double> h[LMAX_SUPPORTED + 1];
+  hankel_set<double>(x, cs, sn, lmax, h);
+  const double ct = dz / rr, st = sqrt(rho2) / rr;
+  double cf = 1.0, sf = 0.0;
+  if (rho2 > 0.0) {
+    cf = dx / sqrt(rho2);
+    sf = dy / sqrt(rho2);
+  }
+  int p, l, m;
+  plm_of_n(n, lmax, p, l, m);
+  double Pb, U, tau;
+  legendre_one<double>(l, m < 0 ? -m : m, ct, st, Pb, U, tau);
+  const double pi = (double)m * U;
+  double sm, cm;
+  sincos((double)m * atan2(sf, cf), &sm, &cm);
+  const cx<double> em(cm, sm);
+  const double nrm = 1.0 / sqrt(2.0 * l * (l + 1));
+  cx<double> Er, Et, Ep;
+  if (p == 0) {
+    Et = mul_i(pi * h[l]);
+    Ep = (-tau) * h[l];
+  } else {
+    const cx<double> dh = (1.0 / x) * (x * h[l - 1] - (double)l * h[l]);
+    Er = ((double)(l * (l + 1)) / x * Pb) * h[l];
+    Et = tau * dh;
+    Ep = mul_i(pi * dh);
+  }
+  Er = nrm * (Er * em);
+  Et = nrm * (Et * em);
+  Ep = nrm * (Ep * em);
+  const cx<double> Ex = (st * cf) * Er + (ct * cf) * Et - sf * Ep;
+  const cx<double> Ey = (st * sf) * Er + (ct * sf) * Et + cf * Ep;
+  const cx<double> Ez = ct * Er - st * Et;
+  const cx<double> o = cx<double>(wxr, wxi) * Ex + cx<double>(wyr, wyi) * Ey + cx<double>(wzr, wzi) * Ez;
+  v[e] = tm_c128{o.re, o.im};
+}
+
+// grad[r][i] = 2 Re sum_slots mu * dt * aexc   (slot layout inputs)
+__global__ void grad_kernel(const c128* __restrict__ mu, const c128* __restrict__ dt,
+                            const c128* __restrict__ aexc, int R, int N, double* __restrict__ g) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)R * N) return;
+  const int r = (int)(e / N);
+  const long long i = e % N;
+  double acc = 0.0;
+  for (int c = 0; c < NCLASS; ++c) {
+    for (int sl = 0; sl < SLOTS; ++sl) {
+      const size_t o = ((size_t)c * N + i) * SLOTS + sl;
+      const size_t ov = (size_t)r * NCLASS * N * SLOTS + o;
+      const c128 a = mu[ov], d = dt[o], b = aexc[ov];
+      const double pr = a.re * d.re - a.im * d.im, pi = a.re * d.im + a.im * d.re;
+      acc += pr * b.re - pi * b.im;
+    }
+  }
+  g[e] = 2.0 * acc;
+}
+
+static inline unsigned nblk(long long n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+int launch_mie(tm_ctx* c, const double* radii, double n_re, double n_im) {
+  const Geometry& g = c->g;
+  hipLaunchKernelGGL(mie_kernel, dim3(nblk(g.n, 64)), dim3(64), 0, c->stream, radii, g.n, g.k,
+                     n_re, n_im, g.lmax, c->maps, (c128*)c->t64.p, (c64*)c->t32.p,
+                     (c128*)c->dt64.p);
+  TM_HIP(c, hipGetLastError());
+  return TM_OK;
+}
+
+int launch_set_tdiag(tm_ctx* c, const tm_c128* t) {
+  const Geometry& g = c->g;
+  hipLaunchKernelGGL(set_t_kernel, dim3(nblk((long long)g.n * g.L)), dim3(256), 0, c->stream, t,
+                     g.n, c->maps, (c128*)c->t64.p, (c64*)c->t32.p);
+  TM_HIP(c, hipGetLastError());
+  return TM_OK;
+}
+
+int launch_get_tdiag(tm_ctx* c, tm_c128* t, tm_c128* dt) {
+  unpack_slots(c->stream, c->g, c->maps, 1, (const c128*)c->t64.p, t);
+  if (dt) unpack_slots(c->stream, c->g, c->maps, 1, (const c128*)c->dt64.p, dt);
+  TM_HIP(c, hipGetLastError());
+  return TM_OK;
+}
+
+int launch_plane_wave(tm_ctx* c, int R, const double* khat, const tm_c128* pol, tm_c128* a0) {
+  const Geometry& g = c->g;
+  for (int r0 = 0; r0 < R; r0 += 8) {
+    const int nr = std::min(8, R - r0);
+    PwArgs pw{};
+    for (int r = 0; r < nr; ++r) {
+      for (int q = 0; q < 3; ++q) {
+        pw.khat[3 * r + q] = khat[3 * (r0 + r) + q];
+        pw.pol[6 * r + 2 * q] = pol[3 * (r0 + r) + q].re;
+        pw.pol[6 * r + 2 * q + 1] = pol[3 * (r0 + r) + q].im;
+      }
+    }
+    const long long total = (long long)nr * g.n * g.L;
+    hipLaunchKernelGGL(plane_wave_kernel, dim3(nblk(total)), dim3(256), 0, c->stream, pw, nr, g.n,
+                       g.L, g.lmax, g.nx, g.x0, g.y0, g.pitch, g.k,
+                       a0 + (size_t)r0 * g.n * g.L);
+  }
+  TM_HIP(c, hipGetLastError());
+  return TM_OK;
+}
+
+int launch_near_field(tm_ctx* c, int R, const tm_c128* s, int P, const double* pts, tm_c128* E,
+                      int precision) {
+  const Geometry& g = c->g;
+  for (int r0 = 0; r0 < R; r0 += NF_MAXR) {
+    const int nr = std::min(NF_MAXR, R - r0);
+    const tm_c128* sr = s + (size_t)r0 * g.n * g.L;
+    tm_c128* Er = E + (size_t)r0 * P * 3;
+    if (precision == TM_PREC_MIXED)
+      hipLaunchKernelGGL(near_field_kernel<float>, dim3(nblk(P)), dim3(256), 0, c->stream, sr, nr,
+                         g.n, g.L, g.lmax, g.nx, g.x0, g.y0, g.pitch, g.k, pts, P, Er);
+    else
+      hipLaunchKernelGGL(near_field_kernel<double>, dim3(nblk(P)), dim3(256), 0, c->stream, sr,
+                         nr, g.n, g.L, g.lmax, g.nx, g.x0, g.y0, g.pitch, g.k, pts, P, Er);
+  }
+  TM_HIP(c, hipGetLastError());
+  return TM_OK;
+}
+
+int launch_far_field(tm_ctx* c, int R, const tm_c128* s, int D, const double* dirs, tm_c128* F) {
+  const Geometry& g = c->g;
+  hipLaunchKernelGGL(far_field_kernel, dim3(nblk((long long)R * D, 64)), dim3(64), 0, c->stream,
+                     s, R, g.n, g.L, g.lmax, g.nx, g.x0, g.y0, g.pitch, g.k, dirs, D, F);
+  TM_HIP(c, hipGetLastError());
+  return TM_OK;
+}
+
+int launch_detector(tm_ctx* c, const double* xd, const tm_c128* w, tm_c128* v) {
+  const Geometry& g = c->g;
+  hipLaunchKernelGGL(detector_kernel, dim3(nblk((long long)g.n * g.L)), dim3(256), 0, c->stream,
+                     xd[0], xd[1], xd[2], w[0].re, w[0].im, w[1].re, w[1].im, w[2].re, w[2].im,
+                     g.n, g.L, g.lmax, g.nx, g.x0, g.y0, g.pitch, g.k, v);
+  TM_HIP(c, hipGetLastError());
+  return TM_OK;
+}
+
+int launch_grad(tm_ctx* c, int R, const c128* mu_slot, const c128* aexc_slot, double* grad) {
+  const Geometry& g = c->g;
+  hipLaunchKernelGGL(grad_kernel, dim3(nblk((long long)R * g.n)), dim3(256), 0, c->stream, mu_slot,
+                     (const c128*)c->dt64.p, aexc_slot, R, g.n, grad);
+  TM_HIP(c, hipGetLastError());
+  return TM_OK;
+}
+
+}  // namespace tmh

@@ -1,0 +1,156 @@
+// Internal declarations of libtmhip (not part of the C ABI).
+//
+// Internal vector layout ("slot layout"): the in-plane lattice makes every
+// translation block split into two classes c = (l + m + p) mod 2 (z-mirror
+// symmetry of App. I.C's alpha/beta: P_q^|mu|(0) vanishes unless q + |mu| is
+// even, alpha needs l+l'+q even and beta odd).  Each class holds L/2 <= 15
+// coefficients, padded to 16 slots, so a per-scatterer vector is stored as
+//   [rhs][class 0..1][site 0..N-1][slot 0..15]   complex
+// and a translation block per displacement as [class][16][16].  Pad slots are
+// zero in every table, T and vector, and stay zero under every operation.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/tmhip.h"
+
+namespace tmh {
+
+constexpr int SLOTS = 16;         // slots per class
+constexpr int NCLASS = 2;
+constexpr int LMAX_SUPPORTED = 3; // 2*lmax(lmax+2)/2 <= 16
+constexpr int QMAX = 2 * LMAX_SUPPORTED;
+
+template <typename T>
+struct cplx {
+  T re, im;
+};
+using c64 = cplx<float>;
+using c128 = cplx<double>;
+
+struct Geometry {
+  int n = 0, nx = 0, ny = 0, lmax = 0, L = 0;
+  double pitch = 0.0, k = 0.0, x0 = 0.0, y0 = 0.0;
+  // slot map: for boundary index n -> class, slot; and per class the list
+  std::vector<int> cls_of, slot_of;           // [L]
+  std::vector<int> n_of[NCLASS];              // [class][slot] -> n or -1
+  int tnx = 0, tny = 0;                       // table half extents (= nx, ny)
+  long long n_disp() const { return (long long)(2 * tnx - 1) * (2 * tny - 1); }
+  long long vec_len() const { return (long long)NCLASS * n * SLOTS; }  // complex per RHS
+};
+
+// Device-side argument bundle for coefficient maps.
+struct SlotMaps {
+  int cls_of[2 * LMAX_SUPPORTED * (LMAX_SUPPORTED + 2)];
+  int slot_of[2 * LMAX_SUPPORTED * (LMAX_SUPPORTED + 2)];
+  int n_of[NCLASS][SLOTS];
+  int L, lmax;
+};
+
+// Workspace buffer that grows on demand.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct ProfAcc {
+  double ms = 0.0;
+  long long launches = 0;
+  double flops = 0.0;
+};
+
+}  // namespace tmh
+
+struct tm_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  tmh::Geometry g;
+  tmh::SlotMaps maps{};
+  bool have_geom = false, have_t = false, have_dt = false;
+  // translation tables [D][2][16][16]
+  tmh::DevBuf tab64, tab32, tabT64, tabT32;
+  bool have_tabT = false;
+  // T and dT/dr in slot layout [2][N][16]
+  tmh::DevBuf t64, t32, dt64;
+  // workspaces
+  tmh::DevBuf partial, xlow, work_a, work_b, work_c, basis, dots, dotpart, scal;
+  // host staging (pinned)
+  void* host_pinned = nullptr;
+  size_t host_pinned_bytes = 0;
+  // profiling
+  bool prof = false;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  tmh::ProfAcc prof_acc[2];
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pending[2];
+  // matvec launch configuration (tuned)
+  int chunks_override = 0;
+};
+
+namespace tmh {
+
+// ---- error helpers -------------------------------------------------------
+int set_err(tm_ctx* c, int code, const std::string& msg);
+#define TM_HIP(ctx, call)                                                       \
+  do {                                                                          \
+    hipError_t e_ = (call);                                                     \
+    if (e_ != hipSuccess)                                                       \
+      return ::tmh::set_err((ctx), TM_ERR_HIP,                                   \
+                           std::string(#call ": ") + hipGetErrorString(e_));    \
+  } while (0)
+
+int ensure(tm_ctx* c, DevBuf& b, size_t bytes);
+void release(DevBuf& b);
+
+// ---- launchers implemented in the .hip files ------------------------------
+// tables (tm_table.hip)
+int build_tables(tm_ctx* c);            // forward tables, FP64 + c64
+int build_transposed_tables(tm_ctx* c); // A^T tables
+void host_slot_maps(int lmax, Geometry& g, SlotMaps& m);
+
+// basis kernels (tm_basis.hip)
+int launch_mie(tm_ctx* c, const double* radii, double n_re, double n_im);
+int launch_set_tdiag(tm_ctx* c, const tm_c128* t);
+int launch_get_tdiag(tm_ctx* c, tm_c128* t, tm_c128* dt);
+int launch_plane_wave(tm_ctx* c, int R, const double* khat, const tm_c128* pol, tm_c128* a0);
+int launch_near_field(tm_ctx* c, int R, const tm_c128* s, int P, const double* pts, tm_c128* E,
+                      int precision);
+int launch_far_field(tm_ctx* c, int R, const tm_c128* s, int D, const double* dirs, tm_c128* F);
+int launch_detector(tm_ctx* c, const double* xd, const tm_c128* w, tm_c128* v);
+int launch_grad(tm_ctx* c, int R, const c128* mu_slot, const c128* aexc_slot, double* grad);
+
+// layout conversions (tm_krylov.hip)
+void pack_slots(hipStream_t st, const Geometry& g, const SlotMaps& m, int R, const tm_c128* in,
+                c128* out);
+void unpack_slots(hipStream_t st, const Geometry& g, const SlotMaps& m, int R, const c128* in,
+                  tm_c128* out);
+
+// matvec (tm_matvec.hip)
+enum class Op { Forward = 0, Coupling = 1, Adjoint = 2, CouplingT = 3 };
+// x, y in slot layout FP64, R right-hand sides contiguous (stride vec_len).
+int apply_op(tm_ctx* c, Op op, int prec, int R, const c128* x, c128* y);
+double matvec_flops(const Geometry& g);
+
+// Krylov kernels (tm_krylov.hip)
+void k_multidot(hipStream_t st, const c128* V, long long stride, int nvec, const c128* w,
+                long long len, c128* partial, int nblk);
+void k_reduce_dots(hipStream_t st, const c128* partial, int nblk, int nvec, c128* out,
+                   const c128* add);
+void k_update(hipStream_t st, c128* w, const c128* V, long long stride, int nvec,
+              const c128* h, long long len, double sign);
+void k_norm2_partial(hipStream_t st, const c128* w, long long len, double* partial, int nblk);
+void k_reduce_norm(hipStream_t st, const double* partial, int nblk, double* out);
+void k_scale(hipStream_t st, c128* y, const c128* x, double a, long long len);
+void k_axpy_dev(hipStream_t st, c128* y, const c128* x, const c128* V, long long stride,
+                int nvec, const c128* coef, long long len);
+void k_sub(hipStream_t st, c128* out, const c128* a, const c128* b, long long len);
+void k_add(hipStream_t st, c128* out, const c128* a, const c128* b, long long len);
+void k_copy(hipStream_t st, c128* out, const c128* in, long long len);
+void k_mul_t(hipStream_t st, c128* out, const c128* t, const c128* x, long long len_per_rhs,
+             int R);
+int krylov_blocks(long long len);
+
+}  // namespace tmh

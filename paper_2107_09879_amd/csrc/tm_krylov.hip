@@ -1,0 +1,251 @@
+// Krylov-subspace vector kernels for GMRES (App. I.D: the non-matvec GMRES
+// operations) and conversions between the boundary layout [rhs][site][n] and
+// the internal class/slot layout.  All FP64; reductions are two-stage with a
+// fixed assignment of elements to blocks and a fixed combine order, so every
+// result is reproducible run to run.
+#include "tm_internal.h"
+
+namespace tmh {
+
+constexpr int KB = 256;  // threads per block for vector kernels
+
+int krylov_blocks(long long len) {
+  long long b = (len + 4 * KB - 1) / (4 * KB);
+  if (b > 1024) b = 1024;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+__device__ inline double warp_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// block-wide sum of a double, result valid in thread 0
+__device__ inline double block_sum(double v, double* sh) {
+  v = warp_sum(v);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l == 0) sh[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r += sh[i];
+  __syncthreads();
+  return r;
+}
+
+// partial[blk][k] = sum over the block's element range of conj(V_k[e]) w[e]
+__global__ __launch_bounds__(KB) void multidot_kernel(const c128* __restrict__ V, long long stride,
+                                                      int nvec, const c128* __restrict__ w,
+                                                      long long len, c128* __restrict__ partial) {
+  __shared__ double sh[KB / 64];
+  const long long per = (len + gridDim.x - 1) / gridDim.x;
+  const long long lo = (long long)blockIdx.x * per;
+  const long long hi = min(len, lo + per);
+  for (int k = 0; k < nvec; ++k) {
+    const c128* vk = V + (size_t)k * stride;
+    double sr = 0.0, si = 0.0;
+    for (long long e = lo + threadIdx.x; e < hi; e += blockDim.x) {
+      const c128 a = vk[e], b = w[e];
+      sr += a.re * b.re + a.im * b.im;
+      si += a.re * b.im - a.im * b.re;
+    }
+    sr = block_sum(sr, sh);
+    si = block_sum(si, sh);
+    if (threadIdx.x == 0) partial[(size_t)blockIdx.x * nvec + k] = c128{sr, si};
+  }
+}
+
+// out[k] = sum_blk partial[blk][k] (+ add[k]); one block per k
+__global__ __launch_bounds__(KB) void reduce_dots_kernel(const c128* __restrict__ partial,
+                                                         int nblk, int nvec, c128* __restrict__ out,
+                                                         const c128* __restrict__ add) {
+  __shared__ double sh[KB / 64];
+  const int k = blockIdx.x;
+  double sr = 0.0, si = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+    const c128 v = partial[(size_t)b * nvec + k];
+    sr += v.re;
+    si += v.im;
+  }
+  sr = block_sum(sr, sh);
+  si = block_sum(si, sh);
+  if (threadIdx.x == 0) {
+    if (add) {
+      sr += add[k].re;
+      si += add[k].im;
+    }
+    out[k] = c128{sr, si};
+  }
+}
+
+// w += sign * sum_k V_k h_k
+__global__ void update_kernel(c128* __restrict__ w, const c128* __restrict__ V, long long stride,
+                              int nvec, const c128* __restrict__ h, long long len, double sign) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= len) return;
+  double sr = 0.0, si = 0.0;
+  for (int k = 0; k < nvec; ++k) {
+    const c128 v = V[(size_t)k * stride + e];
+    const c128 c = h[k];
+    sr += v.re * c.re - v.im * c.im;
+    si += v.re * c.im + v.im * c.re;
+  }
+  c128 o = w[e];
+  o.re += sign * sr;
+  o.im += sign * si;
+  w[e] = o;
+}
+
+__global__ __launch_bounds__(KB) void norm2_partial_kernel(const c128* __restrict__ w, long long len,
+                                                           double* __restrict__ partial) {
+  __shared__ double sh[KB / 64];
+  const long long per = (len + gridDim.x - 1) / gridDim.x;
+  const long long lo = (long long)blockIdx.x * per;
+  const long long hi = min(len, lo + per);
+  double s = 0.0;
+  for (long long e = lo + threadIdx.x; e < hi; e += blockDim.x) {
+    const c128 a = w[e];
+    s += a.re * a.re + a.im * a.im;
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(KB) void reduce_norm_kernel(const double* __restrict__ partial, int nblk,
+                                                         double* __restrict__ out) {
+  __shared__ double sh[KB / 64];
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) s += partial[b];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) out[0] = sqrt(s);
+}
+
+__global__ void scale_kernel(c128* __restrict__ y, const c128* __restrict__ x, double a,
+                             long long len) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= len) return;
+  const c128 v = x[e];
+  y[e] = c128{a * v.re, a * v.im};
+}
+
+__global__ void sub_kernel(c128* __restrict__ out, const c128* __restrict__ a,
+                           const c128* __restrict__ b, long long len) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= len) return;
+  out[e] = c128{a[e].re - b[e].re, a[e].im - b[e].im};
+}
+
+__global__ void add_kernel(c128* __restrict__ out, const c128* __restrict__ a,
+                           const c128* __restrict__ b, long long len) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= len) return;
+  out[e] = c128{a[e].re + b[e].re, a[e].im + b[e].im};
+}
+
+__global__ void copy_kernel(c128* __restrict__ out, const c128* __restrict__ in, long long len) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= len) return;
+  out[e] = in[e];
+}
+
+__global__ void mul_t_kernel(c128* __restrict__ out, const c128* __restrict__ t,
+                             const c128* __restrict__ x, long long vec, long long total) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const c128 a = t[e % vec], b = x[e];
+  out[e] = c128{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+
+// boundary [R][N][L] -> slot [R][2][N][16]
+__global__ void pack_kernel(const tm_c128* __restrict__ in, c128* __restrict__ out, SlotMaps m,
+                            long long N, long long total) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const int slot = (int)(e % SLOTS);
+  const long long site = (e / SLOTS) % N;
+  const int cls = (int)((e / (SLOTS * N)) % NCLASS);
+  const long long r = e / (SLOTS * N * NCLASS);
+  const int n = m.n_of[cls][slot];
+  c128 v{0.0, 0.0};
+  if (n >= 0) {
+    const tm_c128 a = in[(r * N + site) * m.L + n];
+    v = c128{a.re, a.im};
+  }
+  out[e] = v;
+}
+
+// slot [R][2][N][16] -> boundary [R][N][L]
+__global__ void unpack_kernel(const c128* __restrict__ in, tm_c128* __restrict__ out, SlotMaps m,
+                              long long N, long long total) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const int n = (int)(e % m.L);
+  const long long site = (e / m.L) % N;
+  const long long r = e / (m.L * N);
+  const c128 v = in[((r * NCLASS + m.cls_of[n]) * N + site) * SLOTS + m.slot_of[n]];
+  out[e] = tm_c128{v.re, v.im};
+}
+
+static inline unsigned nb_of(long long n) { return (unsigned)((n + KB - 1) / KB); }
+
+void pack_slots(hipStream_t st, const Geometry& g, const SlotMaps& m, int R, const tm_c128* in,
+                c128* out) {
+  const long long total = g.vec_len() * R;
+  hipLaunchKernelGGL(pack_kernel, dim3(nb_of(total)), dim3(KB), 0, st, in, out, m,
+                     (long long)g.n, total);
+}
+void unpack_slots(hipStream_t st, const Geometry& g, const SlotMaps& m, int R, const c128* in,
+                  tm_c128* out) {
+  const long long total = (long long)R * g.n * g.L;
+  hipLaunchKernelGGL(unpack_kernel, dim3(nb_of(total)), dim3(KB), 0, st, in, out, m,
+                     (long long)g.n, total);
+}
+void k_multidot(hipStream_t st, const c128* V, long long stride, int nvec, const c128* w,
+                long long len, c128* partial, int nblk) {
+  hipLaunchKernelGGL(multidot_kernel, dim3(nblk), dim3(KB), 0, st, V, stride, nvec, w, len,
+                     partial);
+}
+void k_reduce_dots(hipStream_t st, const c128* partial, int nblk, int nvec, c128* out,
+                   const c128* add) {
+  hipLaunchKernelGGL(reduce_dots_kernel, dim3(nvec), dim3(KB), 0, st, partial, nblk, nvec, out,
+                     add);
+}
+void k_update(hipStream_t st, c128* w, const c128* V, long long stride, int nvec, const c128* h,
+              long long len, double sign) {
+  hipLaunchKernelGGL(update_kernel, dim3(nb_of(len)), dim3(KB), 0, st, w, V, stride, nvec, h, len,
+                     sign);
+}
+void k_norm2_partial(hipStream_t st, const c128* w, long long len, double* partial, int nblk) {
+  hipLaunchKernelGGL(norm2_partial_kernel, dim3(nblk), dim3(KB), 0, st, w, len, partial);
+}
+void k_reduce_norm(hipStream_t st, const double* partial, int nblk, double* out) {
+  hipLaunchKernelGGL(reduce_norm_kernel, dim3(1), dim3(KB), 0, st, partial, nblk, out);
+}
+void k_scale(hipStream_t st, c128* y, const c128* x, double a, long long len) {
+  hipLaunchKernelGGL(scale_kernel, dim3(nb_of(len)), dim3(KB), 0, st, y, x, a, len);
+}
+void k_axpy_dev(hipStream_t st, c128* y, const c128* x, const c128* V, long long stride, int nvec,
+                const c128* coef, long long len) {
+  (void)x;
+  hipLaunchKernelGGL(update_kernel, dim3(nb_of(len)), dim3(KB), 0, st, y, V, stride, nvec, coef,
+                     len, 1.0);
+}
+void k_sub(hipStream_t st, c128* out, const c128* a, const c128* b, long long len) {
+  hipLaunchKernelGGL(sub_kernel, dim3(nb_of(len)), dim3(KB), 0, st, out, a, b, len);
+}
+void k_add(hipStream_t st, c128* out, const c128* a, const c128* b, long long len) {
+  hipLaunchKernelGGL(add_kernel, dim3(nb_of(len)), dim3(KB), 0, st, out, a, b, len);
+}
+void k_copy(hipStream_t st, c128* out, const c128* in, long long len) {
+  hipLaunchKernelGGL(copy_kernel, dim3(nb_of(len)), dim3(KB), 0, st, out, in, len);
+}
+void k_mul_t(hipStream_t st, c128* out, const c128* t, const c128* x, long long len_per_rhs,
+             int R) {
+  const long long total = len_per_rhs * R;
+  hipLaunchKernelGGL(mul_t_kernel, dim3(nb_of(total)), dim3(KB), 0, st, out, t, x, len_per_rhs,
+                     total);
+}
+
+}  // namespace tmh

@@ -1,0 +1,275 @@
+// Translation-table build: one block of translation coefficients per lattice
+// displacement (App. I.C, addition theorem and eq. "tran_coeff").
+//
+// For a source scatterer at x_s and a target at x_t = x_s + pitch*(dx, dy, 0),
+// the field the source radiates, sum_u s_u Phi_u(k(x - x_s)), re-expands about
+// x_t as sum_v a_v R Phi_v(k(x - x_t)) with a_v = sum_u xi_uv(k(x_t - x_s)) s_u,
+// i.e. the matvec block is M(dx,dy) = xi^T.  With u = (l, m, p), v = (l', m', p'):
+//   xi_uv(d) = e^{i(m-m') phi_d} sum_q C_uvq h_q(k|d|),
+//   C_uvq = (p == p' ? a5 : b5)(l, m | l', m' | q) * Pbar_q^{|m-m'|}(cos theta_d = 0),
+// where a5/b5 are the Wigner-3j expressions of eq. "tran_coeff" read as:
+// (l, m) the source indices, q the Legendre/Hankel order (printed as p),
+// second 3j of b5 with lower row (l l' q-1), normalisation root
+// sqrt((2l+1)(2l'+1)/(2 l(l+1) l'(l'+1))).  The constants C are computed on
+// the host once per geometry (exact factorials); the per-displacement work --
+// Hankel functions, phases, sums, rounding to complex64 -- runs on the GPU.
+//
+// Table layout: [disp][class][16 target slots][16 source slots], with
+// disp = (dy + tny - 1) * (2 tnx - 1) + (dx + tnx - 1); the dx = dy = 0 block
+// is zero so the matvec needs no special case for the excluded self term.
+// The transposed table holds the blocks of A^T: (A^T)_ts = xi(x_s - x_t) =
+// S xi(x_t - x_s) S with S = diag((-1)^(l+p)), so MT(dx,dy)[i][j] =
+// sigma_i sigma_j M(dx,dy)[j][i].
+#include <cmath>
+
+#include "tm_internal.h"
+
+namespace tmh {
+
+static long double lfact(int n) {
+  long double r = 1.0L;
+  for (int i = 2; i <= n; ++i) r *= (long double)i;
+  return r;
+}
+
+// Wigner 3j symbol by the Racah formula (all factorials exact in long double
+// for the orders used here, j <= 12).
+static double wigner3j(int j1, int j2, int j3, int m1, int m2, int m3) {
+  if (m1 + m2 + m3 != 0) return 0.0;
+  if (j3 < std::abs(j1 - j2) || j3 > j1 + j2) return 0.0;
+  if (std::abs(m1) > j1 || std::abs(m2) > j2 || std::abs(m3) > j3) return 0.0;
+  long double tri = lfact(j1 + j2 - j3) * lfact(j1 - j2 + j3) * lfact(-j1 + j2 + j3) /
+                    lfact(j1 + j2 + j3 + 1);
+  long double pre = std::sqrt(tri * lfact(j1 + m1) * lfact(j1 - m1) * lfact(j2 + m2) *
+                              lfact(j2 - m2) * lfact(j3 + m3) * lfact(j3 - m3));
+  int kmin = std::max(0, std::max(j2 - j3 - m1, j1 - j3 + m2));
+  int kmax = std::min(j1 + j2 - j3, std::min(j1 - m1, j2 + m2));
+  long double s = 0.0L;
+  for (int k = kmin; k <= kmax; ++k) {
+    long double den = lfact(k) * lfact(j1 + j2 - j3 - k) * lfact(j1 - m1 - k) *
+                      lfact(j2 + m2 - k) * lfact(j3 - j2 + m1 + k) * lfact(j3 - j1 - m2 + k);
+    s += ((k & 1) ? -1.0L : 1.0L) / den;
+  }
+  int e = j1 - j2 - m3;
+  long double sign = ((e % 2) + 2) % 2 ? -1.0L : 1.0L;
+  return (double)(sign * pre * s);
+}
+
+// i^e as (re, im)
+static void ipow(int e, double& re, double& im) {
+  switch (((e % 4) + 4) % 4) {
+    case 0: re = 1; im = 0; break;
+    case 1: re = 0; im = 1; break;
+    case 2: re = -1; im = 0; break;
+    default: re = 0; im = -1; break;
+  }
+}
+
+static long double dfact(int n) {  // double factorial, (-1)!! = 0!! = 1
+  long double r = 1.0L;
+  for (int i = n; i > 1; i -= 2) r *= (long double)i;
+  return r;
+}
+
+// Normalised associated Legendre function at x = 0, no Condon-Shortley phase:
+// P_q^mu(0) = (-1)^((q-mu)/2) (q+mu-1)!!/(q-mu)!! for q+mu even, else 0.
+static double pbar_at_zero(int q, int mu) {
+  if (mu > q || ((q + mu) & 1)) return 0.0;
+  long double p = dfact(q + mu - 1) / dfact(q - mu);
+  if (((q - mu) / 2) & 1) p = -p;
+  long double nrm = std::sqrt((2.0L * q + 1.0L) / 2.0L * lfact(q - mu) / lfact(q + mu));
+  return (double)(nrm * p);
+}
+
+static void plm_of(int n, int lmax, int& p, int& l, int& m) {
+  int half = lmax * (lmax + 2);
+  p = n / half;
+  int r = n % half;  // = l(l+1) - 1 + m
+  l = 1;
+  while ((l + 1) * (l + 2) - 1 - (l + 1) <= r) ++l;  // first index of l+1 is (l+1)^2-1
+  m = r - (l * (l + 1) - 1);
+}
+
+void host_slot_maps(int lmax, Geometry& g, SlotMaps& mp) {
+  g.L = 2 * lmax * (lmax + 2);
+  g.cls_of.assign(g.L, 0);
+  g.slot_of.assign(g.L, 0);
+  for (int c = 0; c < NCLASS; ++c) g.n_of[c].assign(SLOTS, -1);
+  int cnt[NCLASS] = {0, 0};
+  for (int n = 0; n < g.L; ++n) {
+    int p, l, m;
+    plm_of(n, lmax, p, l, m);
+    int c = (((l + m + p) % 2) + 2) % 2;
+    g.cls_of[n] = c;
+    g.slot_of[n] = cnt[c];
+    g.n_of[c][cnt[c]] = n;
+    cnt[c]++;
+  }
+  mp = SlotMaps{};
+  mp.L = g.L;
+  mp.lmax = lmax;
+  for (int n = 0; n < g.L; ++n) {
+    mp.cls_of[n] = g.cls_of[n];
+    mp.slot_of[n] = g.slot_of[n];
+  }
+  for (int c = 0; c < NCLASS; ++c)
+    for (int s = 0; s < SLOTS; ++s) mp.n_of[c][s] = g.n_of[c][s];
+}
+
+// Host constants: coef[c][i][j][q] (i target slot, j source slot) and
+// dm[c][i][j] = m_src - m_tgt, sig[c][i] = (-1)^(l+p).
+static void host_table_constants(const Geometry& g, std::vector<double>& coef,
+                                 std::vector<int>& dm, std::vector<int>& sig) {
+  const int Q = QMAX + 1;
+  coef.assign((size_t)NCLASS * SLOTS * SLOTS * Q * 2, 0.0);
+  dm.assign((size_t)NCLASS * SLOTS * SLOTS, 0);
+  sig.assign((size_t)NCLASS * SLOTS, 0);
+  for (int c = 0; c < NCLASS; ++c) {
+    for (int i = 0; i < SLOTS; ++i) {
+      int nv = g.n_of[c][i];
+      if (nv >= 0) {
+        int pp, lp, mp;
+        plm_of(nv, g.lmax, pp, lp, mp);
+        sig[c * SLOTS + i] = ((lp + pp) & 1) ? -1 : 1;
+      }
+      for (int j = 0; j < SLOTS; ++j) {
+        int nu = g.n_of[c][j];
+        if (nu < 0 || nv < 0) continue;
+        int p, l, m, pp, lp, mp;
+        plm_of(nu, g.lmax, p, l, m);
+        plm_of(nv, g.lmax, pp, lp, mp);
+        dm[(c * SLOTS + i) * SLOTS + j] = m - mp;
+        double root = std::sqrt((2.0 * l + 1) * (2.0 * lp + 1) /
+                                (2.0 * l * (l + 1) * lp * (lp + 1)));
+        double sgn = ((std::abs(m - mp)) & 1) ? -1.0 : 1.0;  // (-1)^(m-m')
+        for (int q = std::abs(l - lp); q <= l + lp; ++q) {
+          double w1 = wigner3j(l, lp, q, m, -mp, mp - m);
+          double val;
+          if (p == pp) {
+            double wa = wigner3j(l, lp, q, 0, 0, 0);
+            val = (l * (l + 1) + lp * (lp + 1) - q * (q + 1)) * std::sqrt(2.0 * q + 1) * w1 * wa;
+          } else {
+            if (q < 1) continue;
+            double wb = wigner3j(l, lp, q - 1, 0, 0, 0);
+            double arg = (double)(l + lp + 1 + q) * (l + lp + 1 - q) * (q + l - lp) * (q - l + lp) *
+                         (2 * q + 1);
+            if (arg <= 0) continue;
+            val = std::sqrt(arg) * w1 * wb;
+          }
+          val *= root * sgn * pbar_at_zero(q, std::abs(m - mp));
+          double re, im;
+          ipow(std::abs(m - mp) - std::abs(m) - std::abs(mp) + lp - l + q, re, im);
+          size_t o = ((((size_t)c * SLOTS + i) * SLOTS + j) * Q + q) * 2;
+          coef[o] = re * val;
+          coef[o + 1] = im * val;
+        }
+      }
+    }
+  }
+}
+
+// Spherical Hankel functions h_0..h_qmax of the first kind by upward
+// recurrence h_{q+1} = (2q+1)/x h_q - h_{q-1} from h_0 = -i e^{ix}/x,
+// h_1 = -e^{ix}(x + i)/x^2 (stable for h: the growing y_q dominates).
+__device__ inline void hankel_up(double x, int qmax, double* hr, double* hi) {
+  double s, c;
+  sincos(x, &s, &c);
+  double ix = 1.0 / x;
+  hr[0] = s * ix;   // -i (c + i s)/x = (s - i c)/x
+  hi[0] = -c * ix;
+  // -(c + i s)(x + i)/x^2 = -(c x - s + i(s x + c))/x^2
+  hr[1] = -(c * x - s) * ix * ix;
+  hi[1] = -(s * x + c) * ix * ix;
+  for (int q = 1; q < qmax; ++q) {
+    double f = (2 * q + 1) * ix;
+    hr[q + 1] = f * hr[q] - hr[q - 1];
+    hi[q + 1] = f * hi[q] - hi[q - 1];
+  }
+}
+
+// One workgroup per displacement; threads = (class, target slot, source slot).
+__global__ __launch_bounds__(512) void build_table_kernel(
+    const double* __restrict__ coef, const int* __restrict__ dm, const int* __restrict__ sig,
+    c128* __restrict__ tab64, c64* __restrict__ tab32, int tnx, int tny, double pitch, double k,
+    int qmax, int transpose) {
+  const long long d = blockIdx.x;
+  const int c = threadIdx.x >> 8;
+  int i = (threadIdx.x >> 4) & 15;
+  int j = threadIdx.x & 15;
+  const int wx = 2 * tnx - 1;
+  const int dx = (int)(d % wx) - (tnx - 1);
+  const int dy = (int)(d / wx) - (tny - 1);
+  const size_t out = ((size_t)d * NCLASS + c) * SLOTS * SLOTS + (size_t)i * SLOTS + j;
+  double re = 0.0, im = 0.0;
+  if (dx != 0 || dy != 0) {
+    // transposed table: MT[i][j] = sig_i sig_j M[j][i]
+    int ii = transpose ? j : i, jj = transpose ? i : j;
+    const double X = pitch * dx, Y = pitch * dy;
+    const double r = sqrt(X * X + Y * Y);
+    const double phi = atan2(Y, X);
+    double hr[QMAX + 1], hi[QMAX + 1];
+    hankel_up(k * r, qmax, hr, hi);
+    const int Q = QMAX + 1;
+    const double* cf = coef + ((((size_t)c * SLOTS + ii) * SLOTS + jj) * Q) * 2;
+    double sr = 0.0, si = 0.0;
+    for (int q = 0; q <= qmax; ++q) {
+      const double ar = cf[2 * q], ai = cf[2 * q + 1];
+      sr += ar * hr[q] - ai * hi[q];
+      si += ar * hi[q] + ai * hr[q];
+    }
+    double ps, pc;
+    sincos((double)dm[(c * SLOTS + ii) * SLOTS + jj] * phi, &ps, &pc);
+    re = sr * pc - si * ps;
+    im = sr * ps + si * pc;
+    if (transpose) {
+      const double sg = (double)(sig[c * SLOTS + i] * sig[c * SLOTS + j]);
+      re *= sg;
+      im *= sg;
+    }
+  }
+  tab64[out] = c128{re, im};
+  tab32[out] = c64{(float)re, (float)im};
+}
+
+static int build_impl(tm_ctx* c, DevBuf& t64, DevBuf& t32, int transpose) {
+  const Geometry& g = c->g;
+  std::vector<double> coef;
+  std::vector<int> dm, sig;
+  host_table_constants(g, coef, dm, sig);
+  const long long D = g.n_disp();
+  const size_t blk = (size_t)NCLASS * SLOTS * SLOTS;
+  int rc;
+  if ((rc = ensure(c, t64, (size_t)D * blk * sizeof(c128))) != TM_OK) return rc;
+  if ((rc = ensure(c, t32, (size_t)D * blk * sizeof(c64))) != TM_OK) return rc;
+  double* dcoef = nullptr;
+  int *ddm = nullptr, *dsig = nullptr;
+  TM_HIP(c, hipMalloc((void**)&dcoef, coef.size() * sizeof(double)));
+  TM_HIP(c, hipMalloc((void**)&ddm, dm.size() * sizeof(int)));
+  TM_HIP(c, hipMalloc((void**)&dsig, sig.size() * sizeof(int)));
+  TM_HIP(c, hipMemcpyAsync(dcoef, coef.data(), coef.size() * sizeof(double),
+                           hipMemcpyHostToDevice, c->stream));
+  TM_HIP(c, hipMemcpyAsync(ddm, dm.data(), dm.size() * sizeof(int), hipMemcpyHostToDevice,
+                           c->stream));
+  TM_HIP(c, hipMemcpyAsync(dsig, sig.data(), sig.size() * sizeof(int), hipMemcpyHostToDevice,
+                           c->stream));
+  hipLaunchKernelGGL(build_table_kernel, dim3((unsigned)D), dim3(512), 0, c->stream, dcoef, ddm,
+                     dsig, (c128*)t64.p, (c64*)t32.p, g.tnx, g.tny, g.pitch, g.k, 2 * g.lmax,
+                     transpose);
+  TM_HIP(c, hipGetLastError());
+  // the host vectors above are read by the async copies; wait before they go
+  TM_HIP(c, hipStreamSynchronize(c->stream));
+  TM_HIP(c, hipFree(dcoef));
+  TM_HIP(c, hipFree(ddm));
+  TM_HIP(c, hipFree(dsig));
+  return TM_OK;
+}
+
+int build_tables(tm_ctx* c) { return build_impl(c, c->tab64, c->tab32, 0); }
+
+int build_transposed_tables(tm_ctx* c) {
+  int rc = build_impl(c, c->tabT64, c->tabT32, 1);
+  if (rc == TM_OK) c->have_tabT = true;
+  return rc;
+}
+
+}  // namespace tmh

@@ -1,0 +1,271 @@
+"""Python binding of libtmhip (ctypes; argument marshalling only).
+
+Every method forwards to the C entry point of the same name in
+include/tmhip.h; all computation happens in the library's HIP kernels.  Device
+arrays are torch tensors on the context's GPU (complex128 / float64,
+contiguous); host arrays are numpy arrays.  torch is imported before the
+library is loaded so that the library binds to the HIP runtime torch already
+uses (one runtime per process); loading fails loudly if the library is
+missing or a second HIP runtime would be mapped.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtmhip.so")
+
+TM_OK = 0
+TM_NOT_CONVERGED = 1
+TM_PREC_FP64 = 0
+TM_PREC_MIXED = 1
+OPS = {"forward": 0, "coupling": 1, "adjoint": 2, "coupling_t": 3}
+PRECISIONS = {"fp64": TM_PREC_FP64, "mixed": TM_PREC_MIXED, TM_PREC_FP64: 0, TM_PREC_MIXED: 1}
+
+
+class TmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"tmhip status {code}: {msg}")
+        self.code = code
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("max_iter", ctypes.c_int),
+                ("precision", ctypes.c_int), ("inner_tol", ctypes.c_double), ("use_x0", ctypes.c_int)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("iters", ctypes.c_int), ("cycles", ctypes.c_int),
+                ("matvecs_fp64", ctypes.c_int), ("matvecs_lowp", ctypes.c_int),
+                ("rel_residual", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def _hip_runtimes_mapped():
+    paths = set()
+    with open("/proc/self/maps") as f:
+        for line in f:
+            if "libamdhip64" in line:
+                paths.add(os.path.realpath(line.split()[-1]))
+    return paths
+
+
+def load():
+    """Load libtmhip.so (once).  Raises if it is missing or not loadable."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with python -m paper_2107_09879_amd.build")
+    lib = ctypes.CDLL(LIB_PATH, mode=ctypes.RTLD_GLOBAL)
+    runtimes = _hip_runtimes_mapped()
+    if len(runtimes) > 1:
+        raise ImportError(f"two HIP runtimes mapped in one process: {sorted(runtimes)}")
+    P, I, D, L = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_longlong
+    sig = {
+        "tm_create": (I, [ctypes.POINTER(P), I, P]),
+        "tm_destroy": (None, [P]),
+        "tm_status_string": (ctypes.c_char_p, [I]),
+        "tm_last_error": (ctypes.c_char_p, [P]),
+        "tm_coeff_count": (I, [I]),
+        "tm_abi_version": (I, []),
+        "tm_set_geometry": (I, [P, I, P, D, I]),
+        "tm_get_lattice": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(D)]),
+        "tm_set_spheres": (I, [P, P, D, D]),
+        "tm_set_tmatrix_diag": (I, [P, P]),
+        "tm_get_tmatrix_diag": (I, [P, P, P]),
+        "tm_plane_wave_rhs": (I, [P, I, P, P, P]),
+        "tm_default_opts": (None, [ctypes.POINTER(SolveOpts)]),
+        "tm_solve": (I, [P, I, P, P, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo)]),
+        "tm_adjoint_solve": (I, [P, I, P, P, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo)]),
+        "tm_apply_operator": (I, [P, I, P, P, I, I]),
+        "tm_near_field": (I, [P, I, P, I, P, P, I]),
+        "tm_far_field": (I, [P, I, P, I, P, P]),
+        "tm_detector_vector": (I, [P, P, P, P]),
+        "tm_grad_radius": (I, [P, I, P, P, P, P]),
+        "tm_profile_enable": (I, [P, I]),
+        "tm_profile_query": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(L), ctypes.POINTER(D)]),
+        "tm_profile_reset": (I, [P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _dev(t, dtype, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA/HIP torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+class Context:
+    """One tm_ctx on a device, enqueuing on torch's current stream."""
+
+    def __init__(self, device=0, stream=None):
+        self.lib = load()
+        self.device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        self._check(self.lib.tm_create(ctypes.byref(h), device, ctypes.c_void_p(stream.cuda_stream)))
+        self.h = h
+        self.n = 0
+        self.lmax = 0
+        self.L = 0
+
+    def _check(self, rc, allow=(TM_OK,)):
+        if rc not in allow:
+            msg = ""
+            if getattr(self, "h", None):
+                msg = self.lib.tm_last_error(self.h).decode()
+            raise TmError(rc, f"{self.lib.tm_status_string(rc).decode()}: {msg}")
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.tm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- set-up
+    def set_geometry(self, positions, k, lmax):
+        pos = np.ascontiguousarray(positions, dtype=np.float64)
+        self._check(self.lib.tm_set_geometry(self.h, len(pos), pos.ctypes.data_as(ctypes.c_void_p),
+                                             float(k), int(lmax)))
+        self.n, self.lmax, self.L = len(pos), int(lmax), self.lib.tm_coeff_count(int(lmax))
+        self.k = float(k)
+
+    def get_lattice(self):
+        nx, ny, p = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        self._check(self.lib.tm_get_lattice(self.h, ctypes.byref(nx), ctypes.byref(ny), ctypes.byref(p)))
+        return nx.value, ny.value, p.value
+
+    def set_spheres(self, radii, n_rel):
+        r = _dev(radii, torch.float64, "radii")
+        n_rel = complex(n_rel)
+        self._check(self.lib.tm_set_spheres(self.h, _ptr(r), n_rel.real, n_rel.imag))
+
+    def set_tmatrix_diag(self, t):
+        t = _dev(t, torch.complex128, "t")
+        self._check(self.lib.tm_set_tmatrix_diag(self.h, _ptr(t)))
+
+    def get_tmatrix_diag(self):
+        t = torch.empty(self.n, self.L, dtype=torch.complex128, device=self.device)
+        dt = torch.empty_like(t)
+        self._check(self.lib.tm_get_tmatrix_diag(self.h, _ptr(t), _ptr(dt)))
+        return t, dt
+
+    def plane_wave_rhs(self, khat, pol):
+        kh = np.ascontiguousarray(np.atleast_2d(khat), dtype=np.float64)
+        po = np.ascontiguousarray(np.atleast_2d(pol), dtype=np.complex128)
+        R = kh.shape[0]
+        a0 = torch.empty(R, self.n, self.L, dtype=torch.complex128, device=self.device)
+        self._check(self.lib.tm_plane_wave_rhs(self.h, R, kh.ctypes.data_as(ctypes.c_void_p),
+                                               po.ctypes.data_as(ctypes.c_void_p), _ptr(a0)))
+        return a0
+
+    # ---- solve
+    @staticmethod
+    def make_opts(tol=1e-8, restart=50, max_iter=2000, precision="fp64", inner_tol=1e-4, use_x0=False):
+        o = SolveOpts()
+        load().tm_default_opts(ctypes.byref(o))
+        o.tol, o.restart, o.max_iter = tol, restart, max_iter
+        o.precision = PRECISIONS[precision]
+        o.inner_tol, o.use_x0 = inner_tol, int(bool(use_x0))
+        return o
+
+    def _solve(self, fn, rhs, x0, **kw):
+        rhs = _dev(rhs, torch.complex128, "rhs")
+        R = rhs.shape[0] if rhs.dim() == 3 else 1
+        out = x0.clone() if x0 is not None else torch.zeros_like(rhs)
+        o = self.make_opts(use_x0=x0 is not None, **kw)
+        infos = (SolveInfo * R)()
+        self._check(fn(self.h, R, _ptr(rhs), _ptr(out), ctypes.byref(o), infos),
+                    allow=(TM_OK, TM_NOT_CONVERGED))
+        return out, [i.as_dict() for i in infos]
+
+    def solve(self, a0, x0=None, **kw):
+        return self._solve(self.lib.tm_solve, a0, x0, **kw)
+
+    def adjoint_solve(self, v, x0=None, **kw):
+        return self._solve(self.lib.tm_adjoint_solve, v, x0, **kw)
+
+    def apply_operator(self, x, op="forward", precision="fp64"):
+        x = _dev(x, torch.complex128, "x")
+        R = x.shape[0] if x.dim() == 3 else 1
+        y = torch.empty_like(x)
+        self._check(self.lib.tm_apply_operator(self.h, R, _ptr(x), _ptr(y), PRECISIONS[precision],
+                                               OPS[op]))
+        return y
+
+    # ---- readout
+    def near_field(self, s, pts, precision="fp64"):
+        s = _dev(s, torch.complex128, "s")
+        pts = _dev(pts, torch.float64, "pts")
+        R = s.shape[0] if s.dim() == 3 else 1
+        E = torch.empty(R, pts.shape[0], 3, dtype=torch.complex128, device=self.device)
+        self._check(self.lib.tm_near_field(self.h, R, _ptr(s), pts.shape[0], _ptr(pts), _ptr(E),
+                                           PRECISIONS[precision]))
+        return E
+
+    def far_field(self, s, dirs):
+        s = _dev(s, torch.complex128, "s")
+        dirs = _dev(dirs, torch.float64, "dirs")
+        R = s.shape[0] if s.dim() == 3 else 1
+        F = torch.empty(R, dirs.shape[0], 3, dtype=torch.complex128, device=self.device)
+        self._check(self.lib.tm_far_field(self.h, R, _ptr(s), dirs.shape[0], _ptr(dirs), _ptr(F)))
+        return F
+
+    # ---- sensitivities
+    def detector_vector(self, xd, w):
+        xd = np.ascontiguousarray(xd, dtype=np.float64)
+        w = np.ascontiguousarray(w, dtype=np.complex128)
+        v = torch.empty(self.n, self.L, dtype=torch.complex128, device=self.device)
+        self._check(self.lib.tm_detector_vector(self.h, xd.ctypes.data_as(ctypes.c_void_p),
+                                                w.ctypes.data_as(ctypes.c_void_p), _ptr(v)))
+        return v
+
+    def grad_radius(self, mu, s, a0):
+        for t, nm in ((mu, "mu"), (s, "s"), (a0, "a0")):
+            _dev(t, torch.complex128, nm)
+        R = mu.shape[0] if mu.dim() == 3 else 1
+        g = torch.empty(R, self.n, dtype=torch.float64, device=self.device)
+        self._check(self.lib.tm_grad_radius(self.h, R, _ptr(mu), _ptr(s), _ptr(a0), _ptr(g)))
+        return g
+
+    # ---- profiling
+    def profile_enable(self, on=True):
+        self._check(self.lib.tm_profile_enable(self.h, int(bool(on))))
+
+    def profile_reset(self):
+        self._check(self.lib.tm_profile_reset(self.h))
+
+    def profile_query(self, which):
+        ms, n, fl = ctypes.c_double(), ctypes.c_longlong(), ctypes.c_double()
+        self._check(self.lib.tm_profile_query(self.h, int(which), ctypes.byref(ms), ctypes.byref(n),
+                                              ctypes.byref(fl)))
+        return ms.value, n.value, fl.value

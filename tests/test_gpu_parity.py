@@ -1,0 +1,247 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU FP64 oracle.
+
+Tolerances (normwise relative unless stated):
+  FP64 operator / tables ......... 1e-12  (sum of <= N*225 terms, rounding ~1e-16 each)
+  complex64 operator ............. 2e-5   (FP32 table + input rounding ~6e-8, sums of
+                                            ~1e4 terms with FP32 accumulation)
+  FP64 solve at tol 1e-12 ........ 1e-10  (error <= cond(B) * residual, cond ~ 10)
+  mixed solve refined to 1e-12 ... 1e-10
+  mixed solve stopped at 1e-6 .... 1e-5
+  readout / Mie / RHS (FP64) ..... 1e-11
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import oracle  # noqa: E402
+import workloads as wl  # noqa: E402
+from paper_2107_09879_amd import tmhip  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+K = wl.K
+DEV = torch.device("cuda", 0)
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel())
+
+
+def to_dev(a, dtype=torch.complex128):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def make_ctx(nx, ny, lmax, radii=None, seed=0, lo=0.15, hi=0.25):
+    pos = wl.lattice_positions(nx, ny)
+    if radii is None:
+        radii = wl.uniform_radii(nx * ny, lo, hi, seed)
+    ctx = tmhip.Context(0)
+    ctx.set_geometry(pos, K, lmax)
+    ctx.set_spheres(to_dev(radii, torch.float64), wl.N_REL)
+    return ctx, pos, radii
+
+
+def rand_vec(rng, R, N, L):
+    return rng.normal(size=(R, N, L)) + 1j * rng.normal(size=(R, N, L))
+
+
+# ----------------------------------------------------------------- operator
+SHAPES = [(1, 1, 2), (5, 4, 2), (20, 18, 3), (37, 5, 3), (1, 9, 2), (33, 33, 3)]
+
+
+@pytest.mark.parametrize("nx,ny,lmax", SHAPES)
+def test_coupling_operator_fp64_and_c64(nx, ny, lmax):
+    print(f"[case] coupling nx={nx} ny={ny} lmax={lmax}", flush=True)
+    rng = np.random.default_rng(nx * 100 + ny)
+    ctx, pos, radii = make_ctx(nx, ny, lmax)
+    L = oracle.n_coeffs(lmax)
+    x = rand_vec(rng, 2, nx * ny, L)
+    lc = oracle.LatticeCoupling(nx, ny, wl.PITCH, K, lmax)
+    ref = np.stack([lc.apply(x[r]) for r in range(2)])
+    refT = np.stack([lc.apply(x[r], transpose=True) for r in range(2)])
+    xd = to_dev(x)
+    if nx * ny == 1:
+        assert np.abs(host(ctx.apply_operator(xd, "coupling"))).max() == 0.0
+        return
+    y64 = host(ctx.apply_operator(xd, "coupling", "fp64"))
+    y32 = host(ctx.apply_operator(xd, "coupling", "mixed"))
+    assert rel(y64, ref) < 1e-12
+    assert rel(y32, ref) < 2e-5
+    yT = host(ctx.apply_operator(xd, "coupling_t", "fp64"))
+    assert rel(yT, refT) < 1e-12
+    # forward and adjoint operators: x - t A x, x - A^T (t x)
+    t, _ = oracle.mie_tmatrix_diag_many(lmax, K, radii, wl.N_REL)
+    f = host(ctx.apply_operator(xd, "forward", "fp64"))
+    assert rel(f, x - t[None] * ref) < 1e-12
+    fa = host(ctx.apply_operator(xd, "adjoint", "mixed"))
+    refa = np.stack([x[r] - lc.apply(t * x[r], transpose=True) for r in range(2)])
+    assert rel(fa, refa) < 2e-5
+    ctx.close()
+
+
+def test_operator_is_deterministic():
+    rng = np.random.default_rng(3)
+    ctx, _, _ = make_ctx(24, 24, 3)
+    xd = to_dev(rand_vec(rng, 1, 576, 30))
+    a = host(ctx.apply_operator(xd, "forward", "mixed"))
+    b = host(ctx.apply_operator(xd, "forward", "mixed"))
+    assert np.array_equal(a, b)
+    ctx.close()
+
+
+# ----------------------------------------------------------------- set-up kernels
+def test_mie_and_plane_wave_match_oracle():
+    ctx, pos, radii = make_ctx(7, 6, 3, lo=0.12, hi=0.28, seed=5)
+    t, dt = ctx.get_tmatrix_diag()
+    tr, dtr = oracle.mie_tmatrix_diag_many(3, K, radii, wl.N_REL)
+    assert rel(host(t), tr) < 1e-12
+    assert rel(host(dt), dtr) < 1e-11
+    kh, po = wl.incidences(["x", "y", "p10", "s10"])
+    a0 = host(ctx.plane_wave_rhs(kh, po))
+    for r in range(4):
+        assert rel(a0[r], oracle.plane_wave_coeffs(3, K, kh[r], po[r], pos)) < 1e-12
+    ctx.close()
+
+
+def test_lossy_sphere_mie():
+    pos = wl.lattice_positions(3, 1)
+    radii = np.array([0.1, 0.2, 0.25])
+    ctx = tmhip.Context(0)
+    ctx.set_geometry(pos, K, 3)
+    m = 1.5 + 0.3j
+    ctx.set_spheres(to_dev(radii, torch.float64), m)
+    t, dt = ctx.get_tmatrix_diag()
+    tr, dtr = oracle.mie_tmatrix_diag_many(3, K, radii, m)
+    assert rel(host(t), tr) < 1e-12 and rel(host(dt), dtr) < 1e-11
+    ctx.close()
+
+
+# ----------------------------------------------------------------- solve
+def _c1():
+    pos, radii, kh, po, cfg = wl.config_inputs("c1")
+    n = cfg["nx"]
+    ctx, _, _ = make_ctx(n, n, cfg["lmax"], radii=radii)
+    return ctx, pos, radii, kh, po, cfg
+
+
+def test_solve_c1_fp64_and_mixed_vs_dense_lu():
+    ctx, pos, radii, kh, po, cfg = _c1()
+    lmax = cfg["lmax"]
+    t, _ = oracle.mie_tmatrix_diag_many(lmax, K, radii, wl.N_REL)
+    a0r = oracle.plane_wave_coeffs(lmax, K, kh[0], po[0], pos)
+    s_ref = oracle.solve_dense(pos, K, lmax, t, a0r)
+    a0 = ctx.plane_wave_rhs(kh, po)
+    s64, info = ctx.solve(a0, tol=1e-12, precision="fp64")
+    assert info[0]["status"] == 0 and info[0]["rel_residual"] <= 1e-12
+    assert rel(host(s64)[0], s_ref) < 1e-10
+    smx, info = ctx.solve(a0, tol=1e-12, precision="mixed", inner_tol=1e-4)
+    assert info[0]["status"] == 0 and info[0]["matvecs_lowp"] > 0
+    assert rel(host(smx)[0], s_ref) < 1e-10
+    sf, info = ctx.solve(a0, tol=1e-6, precision="mixed", inner_tol=1e-4)
+    assert rel(host(sf)[0], s_ref) < 1e-5
+    # far field and optical theorem through the GPU path
+    dirs = np.array([[0, 0, 1.0], [0.6, 0, 0.8], [0, -0.6, -0.8]])
+    F = host(ctx.far_field(s64, to_dev(dirs, torch.float64)))[0]
+    Fr = oracle.far_field(s_ref, pos, K, lmax, dirs)
+    assert rel(F, Fr) < 1e-10
+    ctx.close()
+
+
+def test_solve_multi_rhs_and_x0_and_adjoint():
+    rng = np.random.default_rng(8)
+    ctx, pos, radii = make_ctx(6, 5, 3, seed=8)
+    t, _ = oracle.mie_tmatrix_diag_many(3, K, radii, wl.N_REL)
+    B, A, T = oracle.system_dense(pos, K, 3, t)
+    kh, po = wl.incidences(["x", "p10"])
+    a0 = ctx.plane_wave_rhs(kh, po)
+    s, info = ctx.solve(a0, tol=1e-12)
+    a0h = host(a0)
+    for r in range(2):
+        ref = np.linalg.solve(B, (t * a0h[r]).ravel()).reshape(30, 30)
+        assert rel(host(s)[r], ref) < 1e-10
+    # warm start from the answer converges immediately
+    s2, info2 = ctx.solve(a0, x0=s, tol=1e-10)
+    assert info2[0]["iters"] == 0
+    # adjoint (I - A^T T) mu = v
+    v = rand_vec(rng, 1, 30, 30)
+    mu, info = ctx.adjoint_solve(to_dev(v), tol=1e-12)
+    Badj = np.eye(900) - A.T @ T
+    assert rel(host(mu)[0], np.linalg.solve(Badj, v.ravel()).reshape(30, 30)) < 1e-10
+    ctx.close()
+
+
+# ----------------------------------------------------------------- readout + adjoint
+def test_near_field_and_detector():
+    rng = np.random.default_rng(4)
+    ctx, pos, radii = make_ctx(6, 4, 3)
+    s = rand_vec(rng, 2, 24, 30) * 0.1
+    pts = np.array([[0.3, 0.3, 5.0], [1.0, -2.0, 0.7], [1.5, 0.9, -3.0], [0.6, 0.6, 0.45]])
+    E64 = host(ctx.near_field(to_dev(s), to_dev(pts, torch.float64), "fp64"))
+    E32 = host(ctx.near_field(to_dev(s), to_dev(pts, torch.float64), "mixed"))
+    for r in range(2):
+        ref = oracle.near_field(s[r], pos, K, 3, pts)
+        assert rel(E64[r], ref) < 1e-11
+        assert rel(E32[r], ref) < 1e-4
+    xd = np.array([0.9, 1.1, 4.0])
+    w = np.array([1.0 + 0.5j, -0.3j, 0.2])
+    v = host(ctx.detector_vector(xd, w))
+    vr = np.einsum('c,cil->il', w, oracle.detector_vectors(pos, K, 3, xd))
+    assert rel(v, vr) < 1e-12
+    ctx.close()
+
+
+def test_gradient_vs_oracle_adjoint():
+    nx, ny, lmax = 4, 3, 2
+    pos = wl.lattice_positions(nx, ny)
+    radii = wl.uniform_radii(nx * ny, 0.12, 0.28, 21)
+    kh, po = wl.incidence("x")
+    xd = np.array([0.9, 0.6, 3.0])
+    O, g_ref, s_ref, mu_ref = oracle.objective_and_gradient_dense(pos, K, lmax, radii, wl.N_REL,
+                                                                  kh, po, xd)
+    ctx = tmhip.Context(0)
+    ctx.set_geometry(pos, K, lmax)
+    ctx.set_spheres(to_dev(radii, torch.float64), wl.N_REL)
+    a0 = ctx.plane_wave_rhs(kh, po)
+    s, _ = ctx.solve(a0, tol=1e-13)
+    vc = [ctx.detector_vector(xd, np.eye(3)[c]) for c in range(3)]
+    z = np.array([np.sum(host(vc[c]) * host(s)[0]) for c in range(3)])
+    Et = po * np.exp(1j * K * kh @ xd) + z
+    w = ctx.detector_vector(xd, np.conj(Et))
+    mu, _ = ctx.adjoint_solve(w[None].contiguous(), tol=1e-13)
+    g = host(ctx.grad_radius(mu, s, a0))[0]
+    assert rel(g, g_ref) < 1e-9
+    ctx.close()
+
+
+# ----------------------------------------------------------------- errors
+def test_error_paths():
+    ctx = tmhip.Context(0)
+    pos = wl.lattice_positions(4, 4)
+    with pytest.raises(tmhip.TmError) as e:
+        bad = pos.copy()
+        bad[5, 0] += 0.01
+        ctx.set_geometry(bad, K, 3)
+    assert e.value.code == -3
+    ctx.set_geometry(pos, K, 3)
+    with pytest.raises(tmhip.TmError) as e:
+        ctx.set_spheres(to_dev(np.full(16, 0.31), torch.float64), 2.0)
+    assert e.value.code == -2
+    r = np.full(16, 0.2)
+    r[3] = np.nan
+    with pytest.raises(tmhip.TmError) as e:
+        ctx.set_spheres(to_dev(r, torch.float64), 2.0)
+    assert e.value.code == -6
+    ctx.set_spheres(to_dev(np.full(16, 0.2), torch.float64), 2.0)
+    a0 = ctx.plane_wave_rhs(*wl.incidence("x"))
+    s, info = ctx.solve(a0, tol=1e-14, max_iter=3)
+    assert info[0]["status"] == 1 and info[0]["iters"] == 3
+    ctx.close()
