@@ -13,7 +13,7 @@
 //   k = input slot; the 16 slots are consumed as four K-steps s, lane l
 //   supplying slot 4*(l/16) + s, so each lane reads 4 consecutive complex
 //   slots of one block row (A) and of one source vector (B) -- contiguous
-//   32/64-byte loads -- and writes 4 consecutive output slots (D).
+//   32/64-byte loads -- and writes the 4 output slots its accumulator holds.
 // Complex arithmetic uses four real products: Yr += Mr Xr - Mi Xi,
 // Yi += Mr Xi + Mi Xr (16 MFMAs per 16 targets per displacement).
 //
@@ -32,12 +32,17 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 template <typename T>
 struct Mfma;
+// Output layout of the 16x16 result: accumulator element v of lane l holds
+// row out_row(l/16, v), column l%16.  The FP32 instruction keeps four
+// consecutive rows per lane group; the FP64 one interleaves them (row
+// 4*v + l/16), as measured on gfx950.
 template <>
 struct Mfma<float> {
   using acc_t = f32x4;
   __device__ static inline acc_t mma(float a, float b, acc_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
+  __device__ static inline int out_row(int kq, int v) { return 4 * kq + v; }
 };
 template <>
 struct Mfma<double> {
@@ -45,6 +50,7 @@ struct Mfma<double> {
   __device__ static inline acc_t mma(double a, double b, acc_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
+  __device__ static inline int out_row(int kq, int v) { return 4 * v + kq; }
 };
 
 __device__ inline void load4(const c64* __restrict__ p, float* re, float* im) {
@@ -150,9 +156,9 @@ __global__ __launch_bounds__(256) void block_matvec_kernel(MvArgs a) {
     for (int g = 0; g < 4; ++g) {
       const int tx = X0 + 4 * g + lx;
       if (tx >= nx) continue;
-      C* o = out + ((size_t)ty * nx + tx) * SLOTS + 4 * kq;
+      C* o = out + ((size_t)ty * nx + tx) * SLOTS;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) o[v] = C{accr[g][v], acci[g][v]};
+      for (int v = 0; v < 4; ++v) o[M::out_row(kq, v)] = C{accr[g][v], acci[g][v]};
     }
   }
 }
