@@ -197,6 +197,22 @@ int tm_detector_vector(tm_ctx* ctx, const double* xd, const tm_c128* w, tm_c128*
 int tm_grad_radius(tm_ctx* ctx, int n_rhs, const tm_c128* mu, const tm_c128* s,
                    const tm_c128* a0, double* grad);
 
+/* ---- matvec launch configuration (autotuner) ----------------------------- */
+
+/* Kernel variant and work split of the block matvec for one precision.
+ * variant 0..7: bit 0 = complex products from three real matrix-core products
+ * (else four), bit 1 = operands of the next displacement loaded during the
+ * current one's products, bit 2 = register budget for 4 (else 2) waves per
+ * SIMD.  items: target work items per (rhs, class) pair, 0 = default.  All
+ * variants compute the same product. */
+int tm_set_matvec_config(tm_ctx* ctx, int precision, int variant, int items);
+int tm_get_matvec_config(tm_ctx* ctx, int precision, int* variant, int* items);
+
+/* Time every variant with a few work-item counts on the current geometry for
+ * n_rhs right-hand sides and keep the fastest for `precision`.  Synchronises;
+ * best_ms (host, nullable) receives the best block-matvec time. */
+int tm_autotune(tm_ctx* ctx, int n_rhs, int precision, double* best_ms);
+
 /* ---- profiling ------------------------------------------------------------ */
 
 /* When enabled, the block-matvec launches are bracketed by HIP events on the

@@ -285,7 +285,8 @@ void tm_destroy(tm_ctx* c) {
   hipStreamSynchronize(c->stream);
   for (tmh::DevBuf* b : {&c->tab64, &c->tab32, &c->tabT64, &c->tabT32, &c->t64, &c->t32, &c->dt64,
                         &c->partial, &c->xlow, &c->work_a, &c->work_b, &c->work_c, &c->basis,
-                        &c->dots, &c->dotpart, &c->scal})
+                        &c->dots, &c->dotpart, &c->scal, &c->plan_items[0], &c->plan_items[1],
+                        &c->plan_ibeg[0], &c->plan_ibeg[1]})
     tmh::release(*b);
   if (c->host_pinned) hipHostFree(c->host_pinned);
   for (int w = 0; w < 2; ++w)
@@ -342,6 +343,7 @@ int tm_set_geometry(tm_ctx* c, int n, const double* pos, double k, int lmax) {
   g.tny = ny;
   tmh::host_slot_maps(lmax, g, c->maps);
   c->have_geom = c->have_t = c->have_dt = c->have_tabT = false;
+  c->plan_R[0] = c->plan_R[1] = -1;
   int rc;
   if ((rc = tmh::build_tables(c)) != TM_OK) return rc;
   const size_t vb = (size_t)g.vec_len();
@@ -554,6 +556,35 @@ int tm_grad_radius(tm_ctx* c, int R, const tm_c128* mu, const tm_c128* s, const 
   tmh::k_add(c->stream, a_sl, a_sl, as_sl, (long long)R * len);
   tmh::pack_slots(c->stream, g, c->maps, R, mu, s_sl);
   return tmh::launch_grad(c, R, s_sl, a_sl, grad);
+}
+
+int tm_set_matvec_config(tm_ctx* c, int precision, int variant, int items) {
+  CHECK_CTX(c);
+  if ((precision != TM_PREC_FP64 && precision != TM_PREC_MIXED) || variant < 0 || variant > 7 ||
+      items < 0)
+    return tmh::set_err(c, TM_ERR_INVALID_ARG, "bad matvec configuration");
+  const int w = precision == TM_PREC_MIXED ? 1 : 0;
+  c->mv_variant[w] = variant;
+  c->mv_items[w] = items;
+  return TM_OK;
+}
+
+int tm_get_matvec_config(tm_ctx* c, int precision, int* variant, int* items) {
+  CHECK_CTX(c);
+  if (precision != TM_PREC_FP64 && precision != TM_PREC_MIXED)
+    return tmh::set_err(c, TM_ERR_INVALID_ARG, "bad precision");
+  const int w = precision == TM_PREC_MIXED ? 1 : 0;
+  if (variant) *variant = c->mv_variant[w];
+  if (items) *items = c->mv_items[w];
+  return TM_OK;
+}
+
+int tm_autotune(tm_ctx* c, int n_rhs, int precision, double* best_ms) {
+  CHECK_CTX(c);
+  if (!c->have_geom) return tmh::set_err(c, TM_ERR_STATE, "set geometry first");
+  if (n_rhs < 1 || (precision != TM_PREC_FP64 && precision != TM_PREC_MIXED))
+    return tmh::set_err(c, TM_ERR_INVALID_ARG, "bad arguments");
+  return tmh::autotune(c, n_rhs, precision, best_ms);
 }
 
 int tm_profile_enable(tm_ctx* c, int enable) {

@@ -342,23 +342,49 @@ __global__ __launch_bounds__(256) void near_field_kernel(
 // F(d) = (1/k) sum_i e^{-ik d.x_i} sum_n s_{i,n} F_n(d), with
 // F_n = (-i)^{l+1} [i pi th - tau ph] e^{im phi} (p = 0), (-i)^l [tau th + i pi ph] e^{im phi}
 // (p = 1), times 1/sqrt(2l(l+1)): the h_l(x) ~ (-i)^{l+1} e^{ix}/x limit.
-__global__ void far_field_kernel(const tm_c128* __restrict__ s, int R, int N, int L, int lmax,
-                                 int nx, double x0, double y0, double pitch, double k,
-                                 const double* __restrict__ dirs, int D,
-                                 tm_c128* __restrict__ F) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= R * D) return;
+// One workgroup per (rhs, direction): threads stride over scatterers to form
+// c_n = sum_i e^{-ik d.x_i} s_{i,n}, then a fixed-order wave + LDS reduction.
+constexpr int FF_THREADS = 256;
+__global__ __launch_bounds__(FF_THREADS) void far_field_kernel(
+    const tm_c128* __restrict__ s, int R, int N, int L, int lmax, int nx, double x0, double y0,
+    double pitch, double k, const double* __restrict__ dirs, int D, tm_c128* __restrict__ F) {
+  constexpr int LM = 2 * LMAX_SUPPORTED * (LMAX_SUPPORTED + 2);
+  __shared__ double red[FF_THREADS / 64][2 * LM];
+  const int e = blockIdx.x;
   const int r = e / D, id = e % D;
   const double ux = dirs[3 * id], uy = dirs[3 * id + 1], uz = dirs[3 * id + 2];
-  cx<double> cn[2 * LMAX_SUPPORTED * (LMAX_SUPPORTED + 2)];
-  for (int i = 0; i < N; ++i) {
+  double cr[LM], ci[LM];
+#pragma unroll
+  for (int n = 0; n < LM; ++n) cr[n] = ci[n] = 0.0;
+  for (int i = threadIdx.x; i < N; i += FF_THREADS) {
     const double xi = x0 + pitch * (double)(i % nx), yi = y0 + pitch * (double)(i / nx);
     double sp, cp;
     sincos(-k * (ux * xi + uy * yi), &sp, &cp);
-    const cx<double> ph(cp, sp);
     const tm_c128* si = s + ((size_t)r * N + i) * L;
-    for (int n = 0; n < L; ++n) cn[n] = cn[n] + ph * cx<double>(si[n].re, si[n].im);
+#pragma unroll
+    for (int n = 0; n < LM; ++n) {
+      if (n < L) {
+        const tm_c128 v = si[n];
+        cr[n] += cp * v.re - sp * v.im;
+        ci[n] += cp * v.im + sp * v.re;
+      }
+    }
   }
+  const int w = threadIdx.x >> 6, ln = threadIdx.x & 63;
+#pragma unroll
+  for (int n = 0; n < LM; ++n) {
+    double a = cr[n], b = ci[n];
+    for (int o = 32; o > 0; o >>= 1) {
+      a += __shfl_xor(a, o, 64);
+      b += __shfl_xor(b, o, 64);
+    }
+    if (ln == 0) {
+      red[w][2 * n] = a;
+      red[w][2 * n + 1] = b;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
   const double rho = sqrt(ux * ux + uy * uy);
   const double ct = uz, st = rho;
   double cf = 1.0, sf = 0.0;
@@ -368,6 +394,11 @@ __global__ void far_field_kernel(const tm_c128* __restrict__ s, int R, int N, in
   }
   cx<double> Ft, Fp;
   for (int n = 0; n < L; ++n) {
+    double a = 0.0, b = 0.0;
+    for (int q = 0; q < FF_THREADS / 64; ++q) {
+      a += red[q][2 * n];
+      b += red[q][2 * n + 1];
+    }
     int p, l, m;
     plm_of_n(n, lmax, p, l, m);
     double Pb, U, tau;
@@ -377,7 +408,7 @@ __global__ void far_field_kernel(const tm_c128* __restrict__ s, int R, int N, in
     sincos((double)m * atan2(sf, cf), &sm, &cm);
     const cx<double> em(cm, sm);
     const double nrm = 1.0 / sqrt(2.0 * l * (l + 1));
-    const cx<double> c = nrm * (cn[n] * em);
+    const cx<double> c = nrm * (cx<double>(a, b) * em);
     if (p == 0) {
       const cx<double> f = ipow<double>(-(l + 1)) * c;  // (-i)^{l+1} = i^{-(l+1)}
       Ft = Ft + mul_i(pi * f);
@@ -538,8 +569,8 @@ int launch_near_field(tm_ctx* c, int R, const tm_c128* s, int P, const double* p
 
 int launch_far_field(tm_ctx* c, int R, const tm_c128* s, int D, const double* dirs, tm_c128* F) {
   const Geometry& g = c->g;
-  hipLaunchKernelGGL(far_field_kernel, dim3(nblk((long long)R * D, 64)), dim3(64), 0, c->stream,
-                     s, R, g.n, g.L, g.lmax, g.nx, g.x0, g.y0, g.pitch, g.k, dirs, D, F);
+  hipLaunchKernelGGL(far_field_kernel, dim3((unsigned)((long long)R * D)), dim3(FF_THREADS), 0,
+                     c->stream, s, R, g.n, g.L, g.lmax, g.nx, g.x0, g.y0, g.pitch, g.k, dirs, D, F);
   TM_HIP(c, hipGetLastError());
   return TM_OK;
 }

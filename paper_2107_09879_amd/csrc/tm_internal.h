@@ -86,8 +86,12 @@ struct tm_ctx {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   tmh::ProfAcc prof_acc[2];
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pending[2];
-  // matvec launch configuration (tuned)
-  int chunks_override = 0;
+  // matvec launch configuration per precision slot (0 = FP64, 1 = complex64):
+  // kernel variant, target work items per (rhs, class), and the cached plan
+  int mv_variant[2] = {0, 0};
+  int mv_items[2] = {0, 0};
+  tmh::DevBuf plan_items[2], plan_ibeg[2];
+  int plan_R[2] = {-1, -1}, plan_target[2] = {0, 0}, plan_nitems[2] = {0, 0};
 };
 
 namespace tmh {
@@ -133,6 +137,7 @@ enum class Op { Forward = 0, Coupling = 1, Adjoint = 2, CouplingT = 3 };
 // x, y in slot layout FP64, R right-hand sides contiguous (stride vec_len).
 int apply_op(tm_ctx* c, Op op, int prec, int R, const c128* x, c128* y);
 double matvec_flops(const Geometry& g);
+int autotune(tm_ctx* c, int R, int prec, double* best_ms);
 
 // Krylov kernels (tm_krylov.hip)
 void k_multidot(hipStream_t st, const c128* V, long long stride, int nvec, const c128* w,

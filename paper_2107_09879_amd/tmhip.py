@@ -90,6 +90,9 @@ def load():
         "tm_far_field": (I, [P, I, P, I, P, P]),
         "tm_detector_vector": (I, [P, P, P, P]),
         "tm_grad_radius": (I, [P, I, P, P, P, P]),
+        "tm_set_matvec_config": (I, [P, I, I, I]),
+        "tm_get_matvec_config": (I, [P, I, ctypes.POINTER(I), ctypes.POINTER(I)]),
+        "tm_autotune": (I, [P, I, I, ctypes.POINTER(D)]),
         "tm_profile_enable": (I, [P, I]),
         "tm_profile_query": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(L), ctypes.POINTER(D)]),
         "tm_profile_reset": (I, [P]),
@@ -256,6 +259,21 @@ class Context:
         g = torch.empty(R, self.n, dtype=torch.float64, device=self.device)
         self._check(self.lib.tm_grad_radius(self.h, R, _ptr(mu), _ptr(s), _ptr(a0), _ptr(g)))
         return g
+
+    # ---- matvec configuration / autotuner
+    def set_matvec_config(self, precision, variant, items=0):
+        self._check(self.lib.tm_set_matvec_config(self.h, PRECISIONS[precision], int(variant), int(items)))
+
+    def get_matvec_config(self, precision):
+        v, i = ctypes.c_int(), ctypes.c_int()
+        self._check(self.lib.tm_get_matvec_config(self.h, PRECISIONS[precision], ctypes.byref(v),
+                                                  ctypes.byref(i)))
+        return v.value, i.value
+
+    def autotune(self, n_rhs=1, precision="mixed"):
+        ms = ctypes.c_double()
+        self._check(self.lib.tm_autotune(self.h, int(n_rhs), PRECISIONS[precision], ctypes.byref(ms)))
+        return ms.value, self.get_matvec_config(precision)
 
     # ---- profiling
     def profile_enable(self, on=True):

@@ -245,3 +245,33 @@ def test_error_paths():
     s, info = ctx.solve(a0, tol=1e-14, max_iter=3)
     assert info[0]["status"] == 1 and info[0]["iters"] == 3
     ctx.close()
+
+
+@pytest.mark.parametrize("variant", range(8))
+def test_every_matvec_variant_matches_oracle(variant):
+    """All kernel variants the autotuner may pick compute the same product."""
+    print(f"[case] variant {variant}", flush=True)
+    rng = np.random.default_rng(40 + variant)
+    nx, ny, lmax = 29, 21, 3
+    ctx, pos, radii = make_ctx(nx, ny, lmax)
+    x = rand_vec(rng, 2, nx * ny, 30)
+    lc = oracle.LatticeCoupling(nx, ny, wl.PITCH, K, lmax)
+    ref = np.stack([lc.apply(x[r]) for r in range(2)])
+    for prec, tol in (("fp64", 1e-12), ("mixed", 2e-5)):
+        for items in (0, 7, 300):
+            ctx.set_matvec_config(prec, variant, items)
+            y = host(ctx.apply_operator(to_dev(x), "coupling", prec))
+            assert rel(y, ref) < tol, (prec, items)
+    ctx.close()
+
+
+def test_autotune_keeps_a_correct_configuration():
+    rng = np.random.default_rng(77)
+    ctx, pos, radii = make_ctx(40, 24, 3)
+    x = rand_vec(rng, 1, 960, 30)
+    ref = oracle.LatticeCoupling(40, 24, wl.PITCH, K, 3).apply(x[0])
+    for prec, tol in (("mixed", 2e-5), ("fp64", 1e-12)):
+        ms, (v, items) = ctx.autotune(1, prec)
+        assert ms > 0 and 0 <= v < 8
+        assert rel(host(ctx.apply_operator(to_dev(x), "coupling", prec))[0], ref) < tol
+    ctx.close()
