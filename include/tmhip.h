@@ -166,6 +166,32 @@ enum {
 int tm_apply_operator(tm_ctx* ctx, int n_rhs, const tm_c128* x, tm_c128* y, int precision,
                       int op);
 
+/* ---- batched subregions --------------------------------------------------- */
+
+/* A rectangular subregion of the current lattice: sites (ix, iy) with
+ * origin_x <= ix < origin_x + side_x, origin_y <= iy < origin_y + side_y. */
+typedef struct {
+  int origin_x, origin_y, side_x, side_y;
+} tm_subregion;
+
+/* Solve every subregion alone (scatterers outside it are ignored: the
+ * subregion-plus-padding decomposition of the paper's distribution strategy)
+ * for n_rhs plane waves (khat/pol: host [R][3], as tm_plane_wave_rhs), all
+ * (subregion, rhs) systems advancing together: one block-matvec launch per
+ * Arnoldi step covers every system, each restart cycle is replayed from a
+ * captured hipGraph when use_graph != 0, converged systems leave the batch.
+ * Geometry (the full lattice) and T must be set.  subs: host [S];
+ * s_out: device, the subregions' [R][N_k][L] coefficient blocks concatenated
+ * in subregion order (site index within a subregion ly*side_x + lx);
+ * info: host [S][R].  opts->use_x0 must be 0.  1 <= n_rhs <= 8. */
+int tm_solve_batched(tm_ctx* ctx, int n_sub, const tm_subregion* subs, int n_rhs,
+                     const double* khat, const tm_c128* pol, tm_c128* s_out,
+                     const tm_solve_opts* opts, tm_solve_info* info, int use_graph);
+
+/* 1 if the last tm_solve_batched replayed its restart cycles from a
+ * captured hipGraph, 0 if it ran them eagerly. */
+int tm_batch_graph_used(const tm_ctx* ctx);
+
 /* ---- readout ------------------------------------------------------------- */
 
 /* Scattered field E_sca(x) = sum_i s_i^T Phi(k(x - x_i)) (App. I.C, eq.
@@ -200,11 +226,12 @@ int tm_grad_radius(tm_ctx* ctx, int n_rhs, const tm_c128* mu, const tm_c128* s,
 /* ---- matvec launch configuration (autotuner) ----------------------------- */
 
 /* Kernel variant and work split of the block matvec for one precision.
- * variant 0..7: bit 0 = complex products from three real matrix-core products
- * (else four), bit 1 = operands of the next displacement loaded during the
- * current one's products, bit 2 = register budget for 4 (else 2) waves per
- * SIMD.  items: target work items per (rhs, class) pair, 0 = default.  All
- * variants compute the same product. */
+ * variant 0..7 (operands read from global memory): bit 0 = complex products
+ * from three real matrix-core products (else four), bit 1 = operands of the
+ * next displacement loaded during the current one's products, bit 2 =
+ * register budget for 4 (else 2) waves per SIMD; variant 8: source windows
+ * staged in LDS per block of displacements.  items: target work items per
+ * (rhs, class) pair, 0 = default.  All variants compute the same product. */
 int tm_set_matvec_config(tm_ctx* ctx, int precision, int variant, int items);
 int tm_get_matvec_config(tm_ctx* ctx, int precision, int* variant, int* items);
 

@@ -55,7 +55,7 @@ void release(DevBuf& b) {
   b.bytes = 0;
 }
 
-static int ensure_pinned(tm_ctx* c, size_t bytes) {
+int ensure_pinned(tm_ctx* c, size_t bytes) {
   if (c->host_pinned_bytes >= bytes) return TM_OK;
   if (c->host_pinned) hipHostFree(c->host_pinned);
   c->host_pinned = nullptr;
@@ -560,7 +560,7 @@ int tm_grad_radius(tm_ctx* c, int R, const tm_c128* mu, const tm_c128* s, const 
 
 int tm_set_matvec_config(tm_ctx* c, int precision, int variant, int items) {
   CHECK_CTX(c);
-  if ((precision != TM_PREC_FP64 && precision != TM_PREC_MIXED) || variant < 0 || variant > 7 ||
+  if ((precision != TM_PREC_FP64 && precision != TM_PREC_MIXED) || variant < 0 || variant > 8 ||
       items < 0)
     return tmh::set_err(c, TM_ERR_INVALID_ARG, "bad matvec configuration");
   const int w = precision == TM_PREC_MIXED ? 1 : 0;

@@ -50,6 +50,21 @@ struct SlotMaps {
   int L, lmax;
 };
 
+// One subregion of a batched solve: its lattice, the offset of its
+// [R][2][N_k][16] block in the packed vector, and its origin in the full
+// lattice (for T and positions).
+struct SubParams {
+  int nx, ny, tiles_x, ox;
+  int oy, pad0;
+  long long vec_off;
+};
+
+// Work item of the LDS-staged block matvec: a target tile of a (sub)lattice
+// and a range [b0, b1) of its displacement blocks.
+struct LdsItem {
+  int tile, b0, b1, sub;
+};
+
 // Workspace buffer that grows on demand.
 struct DevBuf {
   void* p = nullptr;
@@ -92,6 +107,7 @@ struct tm_ctx {
   int mv_items[2] = {0, 0};
   tmh::DevBuf plan_items[2], plan_ibeg[2];
   int plan_R[2] = {-1, -1}, plan_target[2] = {0, 0}, plan_nitems[2] = {0, 0};
+  int last_batch_graphed = 0;
 };
 
 namespace tmh {
@@ -107,6 +123,7 @@ int set_err(tm_ctx* c, int code, const std::string& msg);
   } while (0)
 
 int ensure(tm_ctx* c, DevBuf& b, size_t bytes);
+int ensure_pinned(tm_ctx* c, size_t bytes);
 void release(DevBuf& b);
 
 // ---- launchers implemented in the .hip files ------------------------------

@@ -246,6 +246,12 @@ __global__ __launch_bounds__(256, OCC) void block_matvec_kernel(MvArgs a) {
   }
 }
 
+template <typename T>
+int lds_apply(tm_ctx* c, int which, int R, const void* table, const void* xin, const c128* x,
+              c128* y, int op, int items_target, hipEvent_t e0, hipEvent_t e1);
+constexpr int LDS_VARIANT = 8;
+constexpr int N_VARIANTS = 9;
+
 using MvKernel = void (*)(MvArgs);
 template <typename T>
 static MvKernel mv_kernel(int variant) {
@@ -415,7 +421,6 @@ static int apply_impl(tm_ctx* c, Op op, int R, const c128* x, c128* y) {
     if ((rc = build_transposed_tables(c)) != TM_OK) return rc;
   }
   const int which = std::is_same<T, double>::value ? 0 : 1;
-  if ((rc = ensure_plan(c, R, which)) != TM_OK) return rc;
   const void* table = std::is_same<T, double>::value
                           ? (transposed ? c->tabT64.p : c->tab64.p)
                           : (transposed ? c->tabT32.p : c->tab32.p);
@@ -432,6 +437,21 @@ static int apply_impl(tm_ctx* c, Op op, int R, const c128* x, c128* y) {
                        total);
     xin = (const cplx<T>*)c->xlow.p;
   }
+  if (c->mv_variant[which] == LDS_VARIANT) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->prof) {
+      TM_HIP(c, hipEventCreate(&e0));
+      TM_HIP(c, hipEventCreate(&e1));
+    }
+    const int tgt = c->mv_items[which] > 0 ? c->mv_items[which] : default_items(R);
+    rc = lds_apply<T>(c, which, R, table, xin, x, y, (int)op, tgt, e0, e1);
+    if (c->prof && rc == TM_OK) {
+      c->prof_pending[which].push_back({e0, e1});
+      c->prof_acc[which].flops = matvec_flops(g) * R;
+    }
+    return rc;
+  }
+  if ((rc = ensure_plan(c, R, which)) != TM_OK) return rc;
   const int tiles_x = (g.nx + 15) / 16;
   const int nitems = c->plan_nitems[which];
   if ((rc = ensure(c, c->partial, (size_t)nitems * 2 * R * 256 * SLOTS * sizeof(cplx<T>))) != TM_OK)
@@ -479,16 +499,34 @@ static int autotune_impl(tm_ctx* c, int R, double* best_ms) {
   int rc;
   if ((rc = ensure(c, c->xlow, (size_t)total * sizeof(cplx<T>))) != TM_OK) return rc;
   TM_HIP(c, hipMemsetAsync(c->xlow.p, 0, (size_t)total * sizeof(cplx<T>), c->stream));
-  const int wg_targets[] = {1024, 1536, 2048, 3072, 4096};
+  const int wg_targets[] = {1024, 2048, 3072, 4096, 6144, 8192};
   hipEvent_t e0, e1;
   TM_HIP(c, hipEventCreate(&e0));
   TM_HIP(c, hipEventCreate(&e1));
   double best = 1e300;
   int bv = c->mv_variant[which], bi = c->mv_items[which];
-  for (int v = 0; v < 8; ++v) {
+  for (int v = 0; v < N_VARIANTS; ++v) {
     for (int wt : wg_targets) {
       c->mv_variant[which] = v;
       c->mv_items[which] = std::max(1, wt / (2 * R));
+      if (v == LDS_VARIANT) {
+        double tmin = 1e300;
+        for (int rep = 0; rep < 3; ++rep) {
+          rc = lds_apply<T>(c, which, R, std::is_same<T, double>::value ? c->tab64.p : c->tab32.p,
+                            c->xlow.p, nullptr, nullptr, 0, c->mv_items[which], e0, e1);
+          if (rc != TM_OK) return rc;
+          TM_HIP(c, hipEventSynchronize(e1));
+          float ms = 0.f;
+          TM_HIP(c, hipEventElapsedTime(&ms, e0, e1));
+          if (rep > 0) tmin = std::min(tmin, (double)ms);
+        }
+        if (tmin < best) {
+          best = tmin;
+          bv = v;
+          bi = c->mv_items[which];
+        }
+        continue;
+      }
       if ((rc = ensure_plan(c, R, which)) != TM_OK) return rc;
       const int nitems = c->plan_nitems[which];
       if ((rc = ensure(c, c->partial, (size_t)nitems * 2 * R * 256 * SLOTS * sizeof(cplx<T>))) !=
@@ -528,7 +566,7 @@ static int autotune_impl(tm_ctx* c, int R, double* best_ms) {
   c->mv_variant[which] = bv;
   c->mv_items[which] = bi;
   if (best_ms) *best_ms = best;
-  return ensure_plan(c, R, which);
+  return TM_OK;
 }
 
 int autotune(tm_ctx* c, int R, int prec, double* best_ms) {

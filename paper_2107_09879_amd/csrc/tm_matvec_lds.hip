@@ -1,0 +1,508 @@
+// Block matvec with the source vectors staged in LDS.
+//
+// Same product as tm_matvec.hip (z_t = sum_{s != t} M(t - s) x_s over the
+// lattice, one 16x16 complex block per displacement and z-mirror class,
+// App. I.C / App. I.D), reorganised like a 2-D convolution: a workgroup owns
+// a target tile of (4*GX) x 16 sites and walks its displacement range in
+// blocks of BX x BY displacements.  For each block the (4*GX + BX - 1) x
+// (16 + BY - 1) window of source sites is copied once from HBM/L2 into LDS
+// (zeros outside the lattice), and every displacement of the block then reads
+// its B operands from LDS: no per-lane bounds tests, no re-fetch through the
+// vector-memory path.  The A operand (the translation block) streams from the
+// table in global memory; both operands of the next displacement are fetched
+// while the current one's MFMAs run.
+//
+// K ordering: the 16 input slots are consumed as four MFMA K-steps; lane group
+// kq = lane/16 at step s supplies slot sigma(kq, s).  FP32: sigma = 2kq+s for
+// s < 2 and 8+2kq+s-2 otherwise, so each lane reads two 16-byte chunks (two
+// complex64 slots each); FP64: sigma = 4s+kq, four 16-byte chunks (one
+// complex128 each).  A and B use the same sigma, so the product is unchanged.
+//
+// LDS layout: window site (wx, wy) holds its 16 slots as 16-byte chunks;
+// logical chunk h is stored at physical chunk h ^ g(wx, wy), with g chosen so
+// that the 16 sites of a 4x4 group land in distinct bank groups
+// (conflict-free 128-bit reads for every lane group).
+#include <algorithm>
+#include <cmath>
+#include <type_traits>
+
+#include "tm_internal.h"
+
+namespace tmh {
+
+typedef float lf32x4 __attribute__((ext_vector_type(4)));
+typedef double lf64x4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct LdsT;
+template <>
+struct LdsT<float> {
+  using acc_t = lf32x4;
+  static constexpr int CH = 8;  // 16-byte chunks per site (16 complex64)
+  __device__ static inline acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int out_row(int kq, int v) { return 4 * kq + v; }
+  // window sites are 128 B: bank half = site parity (window width odd) and
+  // g distinguishes the 8 sites of equal parity in a 4x4 patch
+  __device__ static inline int swz(int h, int wx, int wy) {
+    return h ^ (((wx >> 1) & 1) | ((wy & 3) << 1));
+  }
+};
+template <>
+struct LdsT<double> {
+  using acc_t = lf64x4;
+  static constexpr int CH = 16;  // 16 complex128
+  __device__ static inline acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int out_row(int kq, int v) { return 4 * v + kq; }
+  __device__ static inline int swz(int h, int wx, int wy) { return h ^ ((wx & 3) | ((wy & 3) << 2)); }
+};
+
+struct LdsArgs {
+  const void* table;  // [D][2][16][16]
+  const void* x;      // [R][2][N][16] (or packed per subregion)
+  void* partial;      // [item][R*2][tile sites][16]
+  const LdsItem* items;
+  int nx, ny, tnx, tny;
+  int tiles_x, R;
+  long long n_sites;
+  // batched subregions (null for one lattice): per-subregion lattice and the
+  // offset of its [R][2][N_k][16] block in the packed vector; a system
+  // (subregion, rhs) whose flag is 0 is skipped; a nonzero *done skips all
+  const SubParams* subs;
+  const int* active;
+  const int* done;
+};
+
+// A operand of one displacement: 4 (re, im) pairs in sigma order.
+__device__ inline void load_a(const c64* __restrict__ blk, int jt, int kq, float* ar, float* ai) {
+  const float4 p = *reinterpret_cast<const float4*>(blk + jt * SLOTS + 2 * kq);
+  const float4 q = *reinterpret_cast<const float4*>(blk + jt * SLOTS + 8 + 2 * kq);
+  ar[0] = p.x; ai[0] = p.y; ar[1] = p.z; ai[1] = p.w;
+  ar[2] = q.x; ai[2] = q.y; ar[3] = q.z; ai[3] = q.w;
+}
+__device__ inline void load_a(const c128* __restrict__ blk, int jt, int kq, double* ar, double* ai) {
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const double2 p = *reinterpret_cast<const double2*>(blk + jt * SLOTS + 4 * s + kq);
+    ar[s] = p.x;
+    ai[s] = p.y;
+  }
+}
+
+// B operand of one source site from LDS (chunk base of the site given).
+__device__ inline void read_b(const float4* __restrict__ win, int base, int wx, int wy, int kq,
+                              float* br, float* bi) {
+  const float4 p = win[base + LdsT<float>::swz(kq, wx, wy)];
+  const float4 q = win[base + LdsT<float>::swz(4 + kq, wx, wy)];
+  br[0] = p.x; bi[0] = p.y; br[1] = p.z; bi[1] = p.w;
+  br[2] = q.x; bi[2] = q.y; br[3] = q.z; bi[3] = q.w;
+}
+__device__ inline void read_b(const float4* __restrict__ win, int base, int wx, int wy, int kq,
+                              double* br, double* bi) {
+  const double2* w2 = reinterpret_cast<const double2*>(win);
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const double2 p = w2[base + LdsT<double>::swz(4 * s + kq, wx, wy)];
+    br[s] = p.x;
+    bi[s] = p.y;
+  }
+}
+
+template <typename T, int GX, int BX, int BY>
+struct LdsCfg {
+  static constexpr int TW = 4 * GX;  // tile width in sites
+  static constexpr int WX = TW - 1 + BX, WY = 16 - 1 + BY;
+  static constexpr int CH = LdsT<T>::CH;
+  static constexpr int CHUNKS = WX * WY * CH;
+  static constexpr size_t BYTES = (size_t)CHUNKS * 16;
+};
+
+// Complex products by three real MFMA products (T1 = Mr Xr, T2 = Mi Xi,
+// T3 = (Mr + Mi)(Xr + Xi); Yr = T1 - T2, Yi = T3 - T1 - T2).
+template <typename T, int GX, int BX, int BY>
+__global__ __launch_bounds__(256, 2) void block_matvec_lds_kernel(LdsArgs a) {
+  using L = LdsT<T>;
+  using Cfg = LdsCfg<T, GX, BX, BY>;
+  using acc_t = typename L::acc_t;
+  using C = cplx<T>;
+  constexpr int TW = Cfg::TW, WX = Cfg::WX, WY = Cfg::WY, CH = Cfg::CH;
+  __shared__ float4 win[Cfg::CHUNKS];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int jt = lane & 15;
+  const int kq = lane >> 4;
+  const int lx = jt & 3, ly = jt >> 2;
+  if (a.done && *a.done) return;
+  const LdsItem it = a.items[blockIdx.x];
+  const int rc = blockIdx.y;
+  const int r = rc >> 1, c = rc & 1;
+  int nx = a.nx, ny = a.ny, tiles_x = a.tiles_x;
+  size_t N = (size_t)a.n_sites, voff = 0;
+  if (a.subs) {
+    const SubParams sp = a.subs[it.sub];
+    if (a.active && !a.active[it.sub * a.R + r]) return;
+    nx = sp.nx;
+    ny = sp.ny;
+    tiles_x = sp.tiles_x;
+    N = (size_t)sp.nx * sp.ny;
+    voff = (size_t)sp.vec_off;
+  }
+  const int X0 = (it.tile % tiles_x) * TW;
+  const int Y0 = (it.tile / tiles_x) * 16;
+  const int gy0 = Y0 + 4 * wave;
+  const int ty = gy0 + ly;
+  const C* __restrict__ xin =
+      reinterpret_cast<const C*>(a.x) + voff + ((size_t)r * NCLASS + c) * N * SLOTS;
+  const C* __restrict__ tab = reinterpret_cast<const C*>(a.table);
+  const int wxt = 2 * a.tnx - 1;
+  // the tile's displacement range and its block grid
+  const int dxlo = X0 - (nx - 1), dxhi = min(X0 + TW - 1, nx - 1);
+  const int dylo = Y0 - (ny - 1), dyhi = min(Y0 + 15, ny - 1);
+  const int nbx = (dxhi - dxlo + BX) / BX;
+  // this wave's valid dy (its rows must reach a source row)
+  const int wdylo = gy0 - (ny - 1), wdyhi = min(gy0 + 3, ny - 1);
+  const bool wave_live = gy0 < ny;
+
+  acc_t t1[GX], t2[GX], t3[GX];
+#pragma unroll
+  for (int g = 0; g < GX; ++g) {
+    t1[g] = acc_t{0, 0, 0, 0};
+    t2[g] = acc_t{0, 0, 0, 0};
+    t3[g] = acc_t{0, 0, 0, 0};
+  }
+
+  for (int b = it.b0; b < it.b1; ++b) {
+    const int bx0 = dxlo + (b % nbx) * BX;
+    const int by0 = dylo + (b / nbx) * BY;
+    // window origin: source site of target (X0, Y0) at displacement (bx0+BX-1, by0+BY-1)
+    const int wx0 = X0 - (bx0 + BX - 1), wy0 = Y0 - (by0 + BY - 1);
+    __syncthreads();  // every wave is done with the previous window
+    for (int q = threadIdx.x; q < Cfg::CHUNKS; q += 256) {
+      const int h = q % CH;
+      const int site = q / CH;
+      const int wx = site % WX, wy = site / WX;
+      const int gx = wx0 + wx, gy = wy0 + wy;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (gx >= 0 && gx < nx && gy >= 0 && gy < ny)
+        v = *reinterpret_cast<const float4*>(xin + ((size_t)gy * nx + gx) * SLOTS + h * (SLOTS / CH));
+      win[site * CH + L::swz(h, wx, wy)] = v;
+    }
+    __syncthreads();
+    if (!wave_live) continue;
+    const int dyb = max(by0, max(dylo, wdylo)), dye = min(by0 + BY - 1, min(dyhi, wdyhi));
+    const int dxb = max(bx0, dxlo), dxe = min(bx0 + BX - 1, dxhi);
+    if (dyb > dye || dxb > dxe) continue;
+    const int ndx = dxe - dxb + 1;
+    const int nq = (dye - dyb + 1) * ndx;
+    // operand pipeline: A (global) and B (LDS, all groups) of the next
+    // displacement are fetched while the current one's MFMAs run
+    T ar[4], ai[4], nar[4], nai[4];
+    T br[GX][4], bi[GX][4], nbr[GX][4], nbi[GX][4];
+    auto blk_of = [&](int dx, int dy) {
+      return tab + (((size_t)(dy + a.tny - 1) * wxt + (dx + a.tnx - 1)) * NCLASS + c) * (SLOTS * SLOTS);
+    };
+    auto read_all_b = [&](int dx, int dy, T (*r_)[4], T (*i_)[4]) {
+      const int wy = (ty - Y0) - (dy - by0) + BY - 1;
+#pragma unroll
+      for (int g = 0; g < GX; ++g) {
+        const int wx = 4 * g + lx - (dx - bx0) + BX - 1;
+        read_b(win, (wy * WX + wx) * CH, wx, wy, kq, r_[g], i_[g]);
+      }
+    };
+    load_a(blk_of(dxb, dyb), jt, kq, ar, ai);
+    read_all_b(dxb, dyb, br, bi);
+    int dx = dxb, dy = dyb;
+    for (int q = 0; q < nq; ++q) {
+      int ndxv = dx + 1, ndyv = dy;
+      if (ndxv > dxe) {
+        ndxv = dxb;
+        ++ndyv;
+      }
+      const bool more = q + 1 < nq;
+      if (more) {
+        load_a(blk_of(ndxv, ndyv), jt, kq, nar, nai);
+        read_all_b(ndxv, ndyv, nbr, nbi);
+      }
+      T ms[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) ms[s] = ar[s] + ai[s];
+#pragma unroll
+      for (int g = 0; g < GX; ++g) {
+        const int gx0 = X0 + 4 * g;
+        if (gx0 >= nx || gx0 + 3 - dx < 0 || gx0 - dx >= nx) continue;  // wave-uniform
+        T xs[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) xs[s] = br[g][s] + bi[g][s];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          t1[g] = L::mma(ar[s], br[g][s], t1[g]);
+          t2[g] = L::mma(ai[s], bi[g][s], t2[g]);
+          t3[g] = L::mma(ms[s], xs[s], t3[g]);
+        }
+      }
+      if (more) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          ar[s] = nar[s];
+          ai[s] = nai[s];
+#pragma unroll
+          for (int g = 0; g < GX; ++g) {
+            br[g][s] = nbr[g][s];
+            bi[g][s] = nbi[g][s];
+          }
+        }
+      }
+      dx = ndxv;
+      dy = ndyv;
+    }
+  }
+  // this item's partial sums for every valid target of the tile
+  C* out = reinterpret_cast<C*>(a.partial) + ((size_t)blockIdx.x * (2 * a.R) + rc) * (TW * 16 * SLOTS);
+  if (ty < ny) {
+#pragma unroll
+    for (int g = 0; g < GX; ++g) {
+      const int tx = X0 + 4 * g + lx;
+      if (tx >= nx) continue;
+      C* o = out + (size_t)((ty - Y0) * TW + (tx - X0)) * SLOTS;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const T yr = t1[g][v] - t2[g][v];
+        const T yi = t3[g][v] - t1[g][v] - t2[g][v];
+        o[L::out_row(kq, v)] = C{yr, yi};
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- host side
+// Work of every displacement block of every tile (MFMA units plus the window
+// copy), used by the planner to cut each tile's block list into equal-work
+// items.
+double lds_block_work(int nx, int ny, int TW, int BX, int BY, int win_cost,
+                      std::vector<std::vector<double>>& wb) {
+  const int tiles_x = (nx + TW - 1) / TW, tiles_y = (ny + 15) / 16;
+  const int tiles = tiles_x * tiles_y;
+  const int GX = TW / 4;
+  wb.assign(tiles, {});
+  double total = 0.0;
+  for (int t = 0; t < tiles; ++t) {
+    const int X0 = (t % tiles_x) * TW, Y0 = (t / tiles_x) * 16;
+    const int dxlo = X0 - (nx - 1), dxhi = std::min(X0 + TW - 1, nx - 1);
+    const int dylo = Y0 - (ny - 1), dyhi = std::min(Y0 + 15, ny - 1);
+    const int nbx = (dxhi - dxlo + BX) / BX, nby = (dyhi - dylo + BY) / BY;
+    wb[t].assign((size_t)nbx * nby, 0.0);
+    for (int b = 0; b < nbx * nby; ++b) {
+      const int bx0 = dxlo + (b % nbx) * BX, by0 = dylo + (b / nbx) * BY;
+      double w = win_cost;
+      for (int dy = by0; dy < std::min(by0 + BY, dyhi + 1); ++dy) {
+        int waves = 0;
+        for (int wv = 0; wv < 4; ++wv) {
+          const int gy0 = Y0 + 4 * wv;
+          if (gy0 < ny && dy >= gy0 - (ny - 1) && dy <= std::min(gy0 + 3, ny - 1)) ++waves;
+        }
+        if (!waves) continue;
+        for (int dx = bx0; dx < std::min(bx0 + BX, dxhi + 1); ++dx) {
+          int groups = 0;
+          for (int q = 0; q < GX; ++q) {
+            const int gx0 = X0 + 4 * q;
+            if (gx0 < nx && gx0 + 3 - dx >= 0 && gx0 - dx < nx) ++groups;
+          }
+          w += waves * (12.0 * groups + 4.0);
+        }
+      }
+      wb[t][b] = w;
+      total += w;
+    }
+  }
+  return total;
+}
+
+// Cut every tile's blocks into items of about `per` work; appends to items
+// and ibeg (ibeg gets one entry per tile, the caller closes the list).
+void lds_split(const std::vector<std::vector<double>>& wb, double per, int sub,
+               std::vector<LdsItem>& items, std::vector<int>& ibeg) {
+  for (int t = 0; t < (int)wb.size(); ++t) {
+    ibeg.push_back((int)items.size());
+    const int nb = (int)wb[t].size();
+    double wt = 0.0;
+    for (double v : wb[t]) wt += v;
+    int nch = std::max(1, std::min(nb, (int)std::llround(wt / per)));
+    double acc = 0.0;
+    int start = 0, k = 1;
+    for (int b = 0; b < nb; ++b) {
+      acc += wb[t][b];
+      if (k < nch && acc >= k * wt / nch && b < nb - 1) {
+        items.push_back(LdsItem{t, start, b + 1, sub});
+        start = b + 1;
+        ++k;
+      }
+    }
+    items.push_back(LdsItem{t, start, nb, sub});
+  }
+}
+
+static void lds_plan(const Geometry& g, int TW, int BX, int BY, int win_cost, int target,
+                     std::vector<LdsItem>& items, std::vector<int>& ibeg) {
+  std::vector<std::vector<double>> wb;
+  const double total = lds_block_work(g.nx, g.ny, TW, BX, BY, win_cost, wb);
+  items.clear();
+  ibeg.clear();
+  lds_split(wb, total / std::max(1, target), 0, items, ibeg);
+  ibeg.push_back((int)items.size());
+}
+
+// y = x - t * z (Forward) etc., z = sum of the partials of the items covering
+// the site's tile, added in item order.
+template <typename T>
+__global__ void lds_combine_kernel(const cplx<T>* __restrict__ partial, const int* __restrict__ ibeg,
+                                   int R, int nx, int tiles_x, int TW, long long N,
+                                   const c128* __restrict__ x, const c128* __restrict__ t,
+                                   c128* __restrict__ y, long long vec, long long total, int mode) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int slot = (int)(idx % SLOTS);
+  const long long site = (idx / SLOTS) % N;
+  const int rc = (int)(idx / (SLOTS * N));
+  const int sx = (int)(site % nx), sy = (int)(site / nx);
+  const int tile = (sy >> 4) * tiles_x + sx / TW;
+  const int ls = (sy & 15) * TW + (sx % TW);
+  double sr = 0.0, si = 0.0;
+  for (int i = ibeg[tile]; i < ibeg[tile + 1]; ++i) {
+    const cplx<T> v = partial[(((size_t)i * (2 * R) + rc) * (TW * 16) + ls) * SLOTS + slot];
+    sr += (double)v.re;
+    si += (double)v.im;
+  }
+  c128 o;
+  if (mode == (int)Op::Forward) {
+    const c128 tv = t[idx % vec];
+    const c128 xv = x[idx];
+    o.re = xv.re - (tv.re * sr - tv.im * si);
+    o.im = xv.im - (tv.re * si + tv.im * sr);
+  } else if (mode == (int)Op::Adjoint) {
+    const c128 xv = x[idx];
+    o.re = xv.re - sr;
+    o.im = xv.im - si;
+  } else {
+    o.re = sr;
+    o.im = si;
+  }
+  y[idx] = o;
+}
+
+// Configurations: FP32 16x16 tile with 16x4 displacement blocks (75 KB of
+// LDS, two workgroups per CU); FP64 8x16 tile with 8x4 blocks (73 KB).
+template <typename T>
+struct LdsChoice;
+template <>
+struct LdsChoice<float> {
+  static constexpr int GX = 4, BX = 16, BY = 4;
+};
+template <>
+struct LdsChoice<double> {
+  static constexpr int GX = 2, BX = 8, BY = 4;
+};
+
+template <typename T>
+int lds_apply(tm_ctx* c, int which, int R, const void* table, const void* xin, const c128* x,
+              c128* y, int op, int items_target, hipEvent_t e0, hipEvent_t e1) {
+  using Ch = LdsChoice<T>;
+  using Cfg = LdsCfg<T, Ch::GX, Ch::BX, Ch::BY>;
+  const Geometry& g = c->g;
+  const int TW = Cfg::TW;
+  const long long vec = g.vec_len(), total = vec * R;
+  const int key = 1000 + items_target;  // plan cache key (distinct from the direct kernel's)
+  int rc;
+  if (c->plan_R[which] != R || c->plan_target[which] != key) {
+    std::vector<LdsItem> items;
+    std::vector<int> ibeg;
+    lds_plan(g, TW, Ch::BX, Ch::BY, 64, items_target, items, ibeg);
+    if ((rc = ensure(c, c->plan_items[which], items.size() * sizeof(LdsItem))) != TM_OK) return rc;
+    if ((rc = ensure(c, c->plan_ibeg[which], ibeg.size() * sizeof(int))) != TM_OK) return rc;
+    TM_HIP(c, hipMemcpy(c->plan_items[which].p, items.data(), items.size() * sizeof(LdsItem),
+                        hipMemcpyHostToDevice));
+    TM_HIP(c, hipMemcpy(c->plan_ibeg[which].p, ibeg.data(), ibeg.size() * sizeof(int),
+                        hipMemcpyHostToDevice));
+    c->plan_R[which] = R;
+    c->plan_target[which] = key;
+    c->plan_nitems[which] = (int)items.size();
+  }
+  const int nitems = c->plan_nitems[which];
+  if ((rc = ensure(c, c->partial, (size_t)nitems * 2 * R * TW * 16 * SLOTS * sizeof(cplx<T>))) != TM_OK)
+    return rc;
+  LdsArgs a;
+  a.table = table;
+  a.x = xin;
+  a.partial = c->partial.p;
+  a.items = (const LdsItem*)c->plan_items[which].p;
+  a.nx = g.nx;
+  a.ny = g.ny;
+  a.tnx = g.tnx;
+  a.tny = g.tny;
+  a.tiles_x = (g.nx + TW - 1) / TW;
+  a.R = R;
+  a.n_sites = g.n;
+  a.subs = nullptr;
+  a.active = nullptr;
+  a.done = nullptr;
+  auto kern = block_matvec_lds_kernel<T, Ch::GX, Ch::BX, Ch::BY>;
+  if (e0) TM_HIP(c, hipEventRecord(e0, c->stream));
+  hipLaunchKernelGGL(kern, dim3(nitems, 2 * R), dim3(256), 0, c->stream, a);
+  if (e1) TM_HIP(c, hipEventRecord(e1, c->stream));
+  if (y) {
+    const int nb = (int)((total + 255) / 256);
+    hipLaunchKernelGGL(lds_combine_kernel<T>, dim3(nb), dim3(256), 0, c->stream,
+                       (const cplx<T>*)c->partial.p, (const int*)c->plan_ibeg[which].p, R, g.nx,
+                       a.tiles_x, TW, (long long)g.n, x, (const c128*)c->t64.p, y, vec, total, op);
+  }
+  TM_HIP(c, hipGetLastError());
+  return TM_OK;
+}
+
+template <typename T>
+void lds_geometry(int& TW, int& BX, int& BY) {
+  TW = 4 * LdsChoice<T>::GX;
+  BX = LdsChoice<T>::BX;
+  BY = LdsChoice<T>::BY;
+}
+template void lds_geometry<float>(int&, int&, int&);
+template void lds_geometry<double>(int&, int&, int&);
+
+// Launch the LDS kernel over a batched item list (no allocation, no host
+// synchronisation: safe under stream capture).
+template <typename T>
+int lds_launch(tm_ctx* c, const void* table, const void* xin, void* partial, const LdsItem* items,
+               int nitems, int R, const SubParams* subs, const int* active, const int* done) {
+  using Ch = LdsChoice<T>;
+  LdsArgs a;
+  a.table = table;
+  a.x = xin;
+  a.partial = partial;
+  a.items = items;
+  a.nx = c->g.nx;
+  a.ny = c->g.ny;
+  a.tnx = c->g.tnx;
+  a.tny = c->g.tny;
+  a.tiles_x = 0;
+  a.R = R;
+  a.n_sites = 0;
+  a.subs = subs;
+  a.active = active;
+  a.done = done;
+  hipLaunchKernelGGL((block_matvec_lds_kernel<T, Ch::GX, Ch::BX, Ch::BY>), dim3(nitems, 2 * R),
+                     dim3(256), 0, c->stream, a);
+  return TM_OK;
+}
+template int lds_launch<float>(tm_ctx*, const void*, const void*, void*, const LdsItem*, int, int,
+                               const SubParams*, const int*, const int*);
+template int lds_launch<double>(tm_ctx*, const void*, const void*, void*, const LdsItem*, int, int,
+                                const SubParams*, const int*, const int*);
+
+template int lds_apply<float>(tm_ctx*, int, int, const void*, const void*, const c128*, c128*, int,
+                              int, hipEvent_t, hipEvent_t);
+template int lds_apply<double>(tm_ctx*, int, int, const void*, const void*, const c128*, c128*, int,
+                               int, hipEvent_t, hipEvent_t);
+
+}  // namespace tmh

@@ -45,6 +45,11 @@ class SolveInfo(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class Subregion(ctypes.Structure):
+    _fields_ = [("origin_x", ctypes.c_int), ("origin_y", ctypes.c_int), ("side_x", ctypes.c_int),
+                ("side_y", ctypes.c_int)]
+
+
 _lib = None
 
 
@@ -90,6 +95,9 @@ def load():
         "tm_far_field": (I, [P, I, P, I, P, P]),
         "tm_detector_vector": (I, [P, P, P, P]),
         "tm_grad_radius": (I, [P, I, P, P, P, P]),
+        "tm_solve_batched": (I, [P, I, P, I, P, P, P, ctypes.POINTER(SolveOpts),
+                                 ctypes.POINTER(SolveInfo), I]),
+        "tm_batch_graph_used": (I, [P]),
         "tm_set_matvec_config": (I, [P, I, I, I]),
         "tm_get_matvec_config": (I, [P, I, ctypes.POINTER(I), ctypes.POINTER(I)]),
         "tm_autotune": (I, [P, I, I, ctypes.POINTER(D)]),
@@ -216,6 +224,31 @@ class Context:
 
     def adjoint_solve(self, v, x0=None, **kw):
         return self._solve(self.lib.tm_adjoint_solve, v, x0, **kw)
+
+    def solve_batched(self, subs, khat, pol, use_graph=True, **kw):
+        """subs: [(origin_x, origin_y, side_x, side_y)]; returns ([s_k [R, N_k, L]], infos [S][R])."""
+        S = len(subs)
+        arr = (Subregion * S)(*[Subregion(*map(int, q)) for q in subs])
+        kh = np.ascontiguousarray(np.atleast_2d(khat), dtype=np.float64)
+        po = np.ascontiguousarray(np.atleast_2d(pol), dtype=np.complex128)
+        R = kh.shape[0]
+        sizes = [R * q[2] * q[3] * self.L for q in subs]
+        out = torch.empty(sum(sizes), dtype=torch.complex128, device=self.device)
+        o = self.make_opts(**kw)
+        infos = (SolveInfo * (S * R))()
+        self._check(self.lib.tm_solve_batched(self.h, S, arr, R, kh.ctypes.data_as(ctypes.c_void_p),
+                                              po.ctypes.data_as(ctypes.c_void_p), _ptr(out),
+                                              ctypes.byref(o), infos, int(bool(use_graph))),
+                    allow=(TM_OK, TM_NOT_CONVERGED))
+        res, off = [], 0
+        for q, n in zip(subs, sizes):
+            res.append(out[off:off + n].view(R, q[2] * q[3], self.L))
+            off += n
+        info = [[infos[k * R + r].as_dict() for r in range(R)] for k in range(S)]
+        return res, info
+
+    def batch_graph_used(self):
+        return bool(self.lib.tm_batch_graph_used(self.h))
 
     def apply_operator(self, x, op="forward", precision="fp64"):
         x = _dev(x, torch.complex128, "x")

@@ -247,7 +247,7 @@ def test_error_paths():
     ctx.close()
 
 
-@pytest.mark.parametrize("variant", range(8))
+@pytest.mark.parametrize("variant", range(9))
 def test_every_matvec_variant_matches_oracle(variant):
     """All kernel variants the autotuner may pick compute the same product."""
     print(f"[case] variant {variant}", flush=True)
@@ -272,6 +272,48 @@ def test_autotune_keeps_a_correct_configuration():
     ref = oracle.LatticeCoupling(40, 24, wl.PITCH, K, 3).apply(x[0])
     for prec, tol in (("mixed", 2e-5), ("fp64", 1e-12)):
         ms, (v, items) = ctx.autotune(1, prec)
-        assert ms > 0 and 0 <= v < 8
+        assert ms > 0 and 0 <= v < 9
         assert rel(host(ctx.apply_operator(to_dev(x), "coupling", prec))[0], ref) < tol
+    ctx.close()
+
+
+# ----------------------------------------------------------------- batched subregions
+SUBS = [(0, 0, 12, 9), (5, 3, 20, 16), (30, 20, 10, 10), (7, 7, 1, 1), (0, 0, 40, 30), (13, 2, 17, 5)]
+
+
+@pytest.mark.parametrize("precision,use_graph", [("fp64", False), ("fp64", True), ("mixed", True)])
+def test_batched_subregions_match_single_solves(precision, use_graph):
+    """Every (subregion, rhs) of a batch equals the same subregion solved on
+    its own (scatterers outside it ignored), for graph replay and eager runs."""
+    print(f"[case] batched {precision} graph={use_graph}", flush=True)
+    nx, ny, lmax = 40, 30, 3
+    pos = wl.lattice_positions(nx, ny)
+    radii = wl.lens_radii(nx, ny)
+    kh, po = wl.incidences(["x", "p10"])
+    ctx = tmhip.Context(0)
+    ctx.set_geometry(pos, K, lmax)
+    ctx.set_spheres(to_dev(radii, torch.float64), wl.N_REL)
+    sb, info = ctx.solve_batched(SUBS, kh, po, use_graph=use_graph, tol=1e-11, precision=precision)
+    if use_graph:
+        assert ctx.batch_graph_used()
+    for k, (ox, oy, sx, sy) in enumerate(SUBS):
+        ix, iy = np.meshgrid(np.arange(ox, ox + sx), np.arange(oy, oy + sy))
+        idx = (iy * nx + ix).ravel()
+        single = tmhip.Context(0)
+        single.set_geometry(pos[idx], K, lmax)
+        single.set_spheres(to_dev(radii[idx], torch.float64), wl.N_REL)
+        a0 = single.plane_wave_rhs(kh, po)
+        s_ref, _ = single.solve(a0, tol=1e-13)
+        for r in range(2):
+            assert info[k][r]["status"] == 0 and info[k][r]["rel_residual"] <= 1e-11
+            assert rel(host(sb[k])[r], host(s_ref)[r]) < 1e-9, (k, r)
+        single.close()
+    # a small subregion against the oracle's dense LU directly
+    ox, oy, sx, sy = SUBS[0]
+    ix, iy = np.meshgrid(np.arange(ox, ox + sx), np.arange(oy, oy + sy))
+    idx = (iy * nx + ix).ravel()
+    t, _ = oracle.mie_tmatrix_diag_many(lmax, K, radii[idx], wl.N_REL)
+    s_or = oracle.solve_dense(pos[idx], K, lmax, t,
+                              oracle.plane_wave_coeffs(lmax, K, kh[1], po[1], pos[idx]))
+    assert rel(host(sb[0])[1], s_or) < 1e-9
     ctx.close()
