@@ -44,11 +44,18 @@ def main():
     ap.add_argument("--matvec-reps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--subregions", type=int, default=0, help="c3: use only the first K subregions")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(subregions shard independently; see the design notes). Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
+
+    if args.config == "c3":
+        return bench_batched(args)
+    if args.config == "c4":
+        return bench_adjoint(args)
 
     import torch
 
@@ -66,6 +73,15 @@ def main():
     ctx = tmhip.Context(0)
     radii_d = torch.tensor(radii, dtype=torch.float64, device=dev)
     dirs = torch.tensor([[0.0, 0.0, 1.0], [0.0, 0.0, -1.0]], dtype=torch.float64, device=dev)
+
+    # set-up outside the timed region: kernel variant / work split per precision
+    ctx.set_geometry(pos, wl.K, lmax)
+    tuned = {}
+    if not args.no_autotune:
+        for prec in ("mixed", "fp64"):
+            ms, conf = ctx.autotune(len(kh), prec)
+            tuned[prec] = {"block_matvec_ms": ms, "variant": conf[0], "items": conf[1]}
+            log(f"[bench] autotune {prec}: {ms:.3f} ms, variant {conf[0]}, items {conf[1]}")
 
     def step(precision):
         ctx.set_geometry(pos, wl.K, lmax)
@@ -101,7 +117,7 @@ def main():
 
     # block-matvec throughput (HIP events on the library stream)
     rng = np.random.default_rng(0)
-    x = torch.tensor(rng.normal(size=(1, N, ctx.L)) + 1j * rng.normal(size=(1, N, ctx.L)),
+    x = torch.tensor(rng.normal(size=(len(kh), N, ctx.L)) + 1j * rng.normal(size=(len(kh), N, ctx.L)),
                      dtype=torch.complex128, device=dev)
     mv = {}
     for which, prec, peak in ((1, "mixed", PEAK_FP32_MFMA), (0, "fp64", PEAK_FP64_MFMA)):
@@ -126,8 +142,11 @@ def main():
     gbs = alg_bytes / (mv["mixed"]["avg_launch_ms"] / 1e3) / 1e9
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.config == "c2":
         cpu = cpu_baseline(pos, radii, kh, po, cfg, infos[-1][0])
+    extra = {}
+    if args.config == "c5":
+        extra["near_field"] = near_field_plane(ctx, s, cfg)
 
     out = {
         "metric": "time-to-solution at 1e-8 residual + translation-matvec GB/s, 1e4-1e5 scatterers",
@@ -145,6 +164,7 @@ def main():
         "config": {"workload": cfg["name"], "scatterers": N, "lmax": lmax, "unknowns": N * L,
                    "rhs": len(kh), "tol": tol, "restart": restart, "precision": "mixed"},
         "solve_info": infos[-1][0],
+        "autotuned": tuned,
         "fp64_gmres": fp64,
         "matvec": mv,
         "matvec_algorithmic_GBps": gbs,
@@ -152,7 +172,128 @@ def main():
                      "unit": "TFLOP/s", "frac": mv["mixed"]["frac"], "traffic": None,
                      "kernel": "block_matvec_kernel<float>"},
         "cpu_baseline": cpu,
+        **extra,
     }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+def near_field_plane(ctx, s, cfg):
+    """Scattered field on the n x n plane of the workload (FP32 basis, FP64
+    phase reduction), timed with HIP events around the readout call."""
+    import torch
+
+    import workloads as wl
+
+    n_side, extent, z = cfg["plane"]
+    pts = torch.tensor(wl.near_field_plane(n_side, extent, z), dtype=torch.float64, device="cuda")
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ctx.near_field(s, pts[:1024], "mixed")
+    ev0.record()
+    E = ctx.near_field(s, pts, "mixed")
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    pairs = pts.shape[0] * ctx.n * s.shape[0]
+    log(f"[bench] near field {n_side}x{n_side}: {ms:.1f} ms, {pairs / ms / 1e6:.3g} G pair-rhs/s")
+    return {"points": pts.shape[0], "ms": ms, "pair_rhs_per_s": pairs / ms * 1e3,
+            "max_abs": float(E.abs().max())}
+
+
+def bench_batched(args):
+    """48 overlapping square subregions (side 20-80 plus a 10-site buffer) of
+    a 300 x 300 lens layout, 4 right-hand sides each, solved as one batch."""
+    import torch
+
+    import workloads as wl
+    from paper_2107_09879_amd import tmhip
+
+    cfg = wl.CONFIGS["c3"]
+    pos, radii, kh, po, _ = wl.config_inputs("c3")
+    subs = [(ox, oy, sd, sd) for ox, oy, sd in wl.subregions(seed=cfg["seed"])]
+    if args.subregions:
+        subs = subs[:args.subregions]
+    ctx = tmhip.Context(0)
+    ctx.set_geometry(pos, wl.K, cfg["lmax"])
+    ctx.set_spheres(torch.tensor(radii, dtype=torch.float64, device="cuda"), wl.N_REL)
+    res = {}
+    for prec in (["mixed"] if args.no_fp64 else ["mixed", "fp64"]):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sb, info = ctx.solve_batched(subs, kh, po, use_graph=True, tol=cfg["tol"],
+                                     restart=cfg["restart"], precision=prec, max_iter=4000)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        flat = [i for row in info for i in row]
+        res[prec] = {"time_s": dt, "graph": ctx.batch_graph_used(),
+                     "iters_max": max(i["iters"] for i in flat),
+                     "iters_mean": float(np.mean([i["iters"] for i in flat])),
+                     "converged": sum(i["status"] == 0 for i in flat), "systems": len(flat),
+                     "max_rel_residual": max(i["rel_residual"] for i in flat)}
+        log(f"[bench] batched {prec}: {dt:.2f} s {res[prec]}")
+    sites = sum(q[2] * q[3] for q in subs)
+    out = {"metric": "time-to-solution at 1e-8 residual + translation-matvec GB/s, 1e4-1e5 scatterers",
+           "value": res["mixed"]["time_s"], "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0,
+           "ms_per_step": res["mixed"]["time_s"] * 1e3, "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "dtype": "c64 matvec (fp32 accum) + f64 refinement", "data": "synthetic",
+           "config": {"workload": cfg["name"], "subregions": len(subs), "sites": sites,
+                      "rhs": len(kh), "systems": len(subs) * len(kh)},
+           "batched": res}
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+def bench_adjoint(args):
+    """150 x 150 lattice: forward solve, detector objective |E|^2 50 wavelengths
+    above the centre, adjoint solve and radius gradient; central differences
+    on a few seeded radii from warm-started FP64 solves."""
+    import torch
+
+    import workloads as wl
+    from paper_2107_09879_amd import tmhip
+
+    pos, radii, kh, po, cfg = wl.config_inputs("c4")
+    xd = np.array(cfg["detector"])
+    ctx = tmhip.Context(0)
+    ctx.set_geometry(pos, wl.K, cfg["lmax"])
+    rd = torch.tensor(radii, dtype=torch.float64, device="cuda")
+
+    def objective(r_dev, tol, x0=None):
+        ctx.set_spheres(r_dev, wl.N_REL)
+        a0 = ctx.plane_wave_rhs(kh, po)
+        s, info = ctx.solve(a0, x0=x0, tol=tol, precision="fp64", max_iter=6000)
+        z = np.array([torch.sum(ctx.detector_vector(xd, np.eye(3)[c]) * s[0]).item() for c in range(3)])
+        Et = po[0] * np.exp(1j * wl.K * kh[0] @ xd) + z
+        return float(np.sum(np.abs(Et) ** 2)), s, a0, Et, info
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    O, s, a0, Et, info_f = objective(rd, 1e-12)
+    w = ctx.detector_vector(xd, np.conj(Et))
+    mu, info_a = ctx.adjoint_solve(w[None].contiguous(), tol=1e-12, precision="fp64", max_iter=6000)
+    g = ctx.grad_radius(mu, s, a0)[0].cpu().numpy()
+    torch.cuda.synchronize()
+    t_grad = time.perf_counter() - t0
+    log(f"[bench] forward+adjoint+gradient {t_grad:.2f} s, O={O:.6e}, fwd {info_f[0]}, adj {info_a[0]}")
+    idx = np.random.default_rng(5).choice(len(radii), 20, replace=False)[: max(1, args.steps)]
+    fd = []
+    h = 1e-6
+    for i in idx:
+        vals = []
+        for sg in (1, -1):
+            r2 = rd.clone()
+            r2[i] += sg * h
+            vals.append(objective(r2, 1e-13, x0=s)[0])
+        fd.append((vals[0] - vals[1]) / (2 * h))
+        log(f"[bench] FD radius {i}: adjoint {g[i]:.8e} fd {fd[-1]:.8e}")
+    fd = np.array(fd)
+    err = float(np.max(np.abs(fd - g[idx])) / np.max(np.abs(g)))
+    out = {"metric": "time-to-solution at 1e-8 residual + translation-matvec GB/s, 1e4-1e5 scatterers",
+           "value": t_grad, "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": t_grad * 1e3,
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic", "config": {"workload": cfg["name"], "scatterers": len(radii)},
+           "objective": O, "forward": info_f[0], "adjoint": info_a[0],
+           "fd_check": {"indices": idx.tolist(), "step": h, "max_err_rel_to_max_grad": err}}
     print(json.dumps(out), flush=True)
     ctx.close()
 

@@ -269,74 +269,187 @@ __device__ inline void hankel_set(T x, T c, T s, int lmax, cx<T>* h) {
 
 constexpr int NF_MAXR = 4;
 
-template <typename T>
-__global__ __launch_bounds__(256) void near_field_kernel(
-    const tm_c128* __restrict__ s, int R, int N, int L, int lmax, int nx, double x0, double y0,
-    double pitch, double k, const double* __restrict__ pts, int P, tm_c128* __restrict__ E) {
+// Near field with compile-time lmax and RHS count (all basis values in
+// registers).  Each workgroup stages the coefficients of CH spheres at a time
+// in LDS (every thread reads the same entries: broadcast) and each thread
+// accumulates the field of one point.  The +-m terms of one (l, |m|) share
+// P, U, tau and conj(e^{i|m|phi}), so they are folded:
+//   sMe = s_M(+m) e + s_M(-m) e*,  dMe = s_M(+m) e - s_M(-m) e*  (same for N),
+//   E_r += c_l P sNe,  E_th += i|m| U a_l dMe + tau b_l sNe,
+//   E_ph += -tau a_l sMe + i|m| U b_l dNe,
+// with a_l = h_l/sqrt(2l(l+1)), b_l = (x h_{l-1} - l h_l)/x /sqrt(2l(l+1)),
+// c_l = l(l+1) h_l/x /sqrt(2l(l+1)).  Distances and k r are formed in FP64
+// (k r reduced modulo 2 pi before the FP32 sine/cosine).
+template <typename T, int LMAX, int R>
+__global__ __launch_bounds__(256) void near_field_v2(
+    const tm_c128* __restrict__ s, int N, int nx, double x0, double y0, double pitch, double k,
+    const double* __restrict__ pts, int P, tm_c128* __restrict__ E) {
+  constexpr int L = 2 * LMAX * (LMAX + 2), H = LMAX * (LMAX + 2);
+  constexpr int CHN = 32;
+  __shared__ cplx<T> sh[CHN][R][L];
   const int ip = blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = ip < P;
   const double px = live ? pts[3 * ip] : 0.0, py = live ? pts[3 * ip + 1] : 0.0,
                pz = live ? pts[3 * ip + 2] : 1.0;
-  cx<T> acc[NF_MAXR][3];
+  cx<T> acc[R][3];
   const double twopi = 6.283185307179586476925286766559;
-  for (int i = 0; i < N; ++i) {
-    const double dx = px - (x0 + pitch * (double)(i % nx));
-    const double dy = py - (y0 + pitch * (double)(i / nx));
-    const double dz = pz;
-    const double rho2 = dx * dx + dy * dy;
-    const double rr = sqrt(rho2 + dz * dz);
-    const double kr = k * rr;
-    const double red = kr - twopi * rint(kr / twopi);
-    T sn, cs;
-    sincos_t((T)red, &sn, &cs);
-    const T x = (T)kr;
-    const T ct = (T)(dz / rr), st = (T)(sqrt(rho2) / rr);
-    T cf = 1, sf = 0;
-    if (rho2 > 0.0) {
-      const double rh = sqrt(rho2);
-      cf = (T)(dx / rh);
-      sf = (T)(dy / rh);
+  // normalisation constants sqrt((2l+1)/2 (l-m)!/(l+m)!)
+  T nlm[LMAX + 1][LMAX + 1];
+#pragma unroll
+  for (int l = 0; l <= LMAX; ++l)
+#pragma unroll
+    for (int am = 0; am <= LMAX; ++am) {
+      double v = (2.0 * l + 1.0) / 2.0;
+      for (int q = l - am + 1; q <= l + am; ++q) v /= (double)q;
+      nlm[l][am] = (T)sqrt(v);
     }
-    cx<T> h[LMAX_SUPPORTED + 1];
-    hankel_set<T>(x, cs, sn, lmax, h);
-    cx<T> Er[NF_MAXR], Et[NF_MAXR], Ep[NF_MAXR];
-    for (int l = 1; l <= lmax; ++l) {
-      const cx<T> dh((x * h[l - 1].re - (T)l * h[l].re) / x, (x * h[l - 1].im - (T)l * h[l].im) / x);
-      const T nrm = (T)1 / sqrt((T)(2 * l * (l + 1)));
-      const cx<T> hr = ((T)(l * (l + 1)) / x) * h[l];
-      for (int am = 0; am <= l; ++am) {
-        T Pb, U, tau;
-        legendre_one<T>(l, am, ct, st, Pb, U, tau);
-        // e^{i am phi}
-        cx<T> e(1, 0);
-        for (int q = 0; q < am; ++q) e = e * cx<T>(cf, sf);
-        for (int sg = (am == 0 ? 1 : -1); sg <= 1; sg += 2) {
-          const int m = sg * am;
-          const cx<T> em = (sg > 0) ? e : cx<T>(e.re, -e.im);
-          const T pi = (T)m * U;
-          const int n0 = n_of_plm(0, l, m, lmax), n1 = n_of_plm(1, l, m, lmax);
+  for (int i0 = 0; i0 < N; i0 += CHN) {
+    const int nch = min(CHN, N - i0);
+    __syncthreads();
+    for (int q = threadIdx.x; q < nch * R * L; q += blockDim.x) {
+      const int n = q % L, rr = (q / L) % R, ii = q / (L * R);
+      const tm_c128 v = s[((size_t)rr * N + (i0 + ii)) * L + n];
+      sh[ii][rr][n] = cplx<T>{(T)v.re, (T)v.im};
+    }
+    __syncthreads();
+    for (int ii = 0; ii < nch; ++ii) {
+      const int i = i0 + ii;
+      const double dx = px - (x0 + pitch * (double)(i % nx));
+      const double dy = py - (y0 + pitch * (double)(i / nx));
+      const double dz = pz;
+      const double rho2 = dx * dx + dy * dy;
+      const double r2 = rho2 + dz * dz;
+      const double rr = sqrt(r2);
+      const double kr = k * rr;
+      const double red = kr - twopi * rint(kr / twopi);
+      T sn, cs;
+      sincos_t((T)red, &sn, &cs);
+      const T x = (T)kr;
+      const T ix = (T)1 / x;
+      const T irr = (T)(1.0 / rr);
+      const T ct = (T)dz * irr;
+      const T rho = (T)sqrt(rho2);
+      const T st = rho * irr;
+      T cf = 1, sf = 0;
+      if (rho2 > 0.0) {
+        const T ir = (T)1 / rho;
+        cf = (T)dx * ir;
+        sf = (T)dy * ir;
+      }
+      // Hankel h_0..h_LMAX
+      cx<T> h[LMAX + 1];
+      h[0] = cx<T>(sn * ix, -cs * ix);
+      if (LMAX >= 1) h[1] = cx<T>(-(cs * x - sn) * ix * ix, -(sn * x + cs) * ix * ix);
+#pragma unroll
+      for (int q = 1; q < LMAX; ++q) {
+        const T f = (T)(2 * q + 1) * ix;
+        h[q + 1] = cx<T>(f * h[q].re - h[q - 1].re, f * h[q].im - h[q - 1].im);
+      }
+      // u_l^m = P_l^m / sin (m >= 1), P_l^0, and u_l^1 for tau_l^0
+      T u[LMAX + 2][LMAX + 1];
+#pragma unroll
+      for (int am = 1; am <= LMAX; ++am) {
+        T um = 1;
+#pragma unroll
+        for (int q = 1; q <= 2 * am - 1; q += 2) um *= (T)q;
+#pragma unroll
+        for (int q = 0; q < am - 1; ++q) um *= st;
+        u[am - 1][am] = 0;
+        u[am][am] = um;
+#pragma unroll
+        for (int l = am + 1; l <= LMAX; ++l)
+          u[l][am] = ((T)(2 * l - 1) * ct * u[l - 1][am] - (T)(l + am - 1) * (l - 2 >= am ? u[l - 2][am] : (T)0)) /
+                     (T)(l - am);
+      }
+      T p0[LMAX + 1];
+      p0[0] = 1;
+      if (LMAX >= 1) p0[1] = ct;
+#pragma unroll
+      for (int l = 2; l <= LMAX; ++l)
+        p0[l] = ((T)(2 * l - 1) * ct * p0[l - 1] - (T)(l - 1) * p0[l - 2]) / (T)l;
+      cx<T> e[LMAX + 1];
+      e[0] = cx<T>(1, 0);
+#pragma unroll
+      for (int am = 1; am <= LMAX; ++am) e[am] = e[am - 1] * cx<T>(cf, sf);
+      cx<T> Er[R], Et[R], Ep[R];
+#pragma unroll
+      for (int l = 1; l <= LMAX; ++l) {
+        const T nrm = (T)1 / sqrt((T)(2 * l * (l + 1)));
+        const cx<T> al = nrm * h[l];
+        const cx<T> bl = nrm * cx<T>((x * h[l - 1].re - (T)l * h[l].re) * ix, (x * h[l - 1].im - (T)l * h[l].im) * ix);
+        const cx<T> cl = (nrm * (T)(l * (l + 1)) * ix) * h[l];
+#pragma unroll
+        for (int am = 0; am <= l; ++am) {
+          T Pb, Ub, tau;
+          if (am == 0) {
+            Pb = nlm[l][0] * p0[l];
+            Ub = 0;
+            tau = -nlm[l][0] * st * u[l][1];
+          } else {
+            Pb = nlm[l][am] * st * u[l][am];
+            Ub = nlm[l][am] * (T)am * u[l][am];
+            tau = nlm[l][am] * ((T)l * ct * u[l][am] - (T)(l + am) * u[l - 1][am]);
+          }
+          const int np = l * (l + 1) - 1 + am, nm = l * (l + 1) - 1 - am;
+#pragma unroll
           for (int r = 0; r < R; ++r) {
-            const tm_c128 a = s[((size_t)r * N + i) * L + n0];
-            const tm_c128 b = s[((size_t)r * N + i) * L + n1];
-            const cx<T> sM = nrm * (cx<T>((T)a.re, (T)a.im) * em);
-            const cx<T> sN = nrm * (cx<T>((T)b.re, (T)b.im) * em);
-            Er[r] = Er[r] + (Pb * (hr * sN));
-            Et[r] = Et[r] + mul_i(pi * (h[l] * sM)) + tau * (dh * sN);
-            Ep[r] = Ep[r] - tau * (h[l] * sM) + mul_i(pi * (dh * sN));
+            cx<T> sMe, dMe, sNe, dNe;
+            if (am == 0) {
+              sMe = cx<T>(sh[ii][r][np].re, sh[ii][r][np].im);
+              sNe = cx<T>(sh[ii][r][H + np].re, sh[ii][r][H + np].im);
+            } else {
+              const cx<T> ep = e[am], em = cx<T>(e[am].re, -e[am].im);
+              const cx<T> a1 = cx<T>(sh[ii][r][np].re, sh[ii][r][np].im) * ep;
+              const cx<T> a2 = cx<T>(sh[ii][r][nm].re, sh[ii][r][nm].im) * em;
+              const cx<T> b1 = cx<T>(sh[ii][r][H + np].re, sh[ii][r][H + np].im) * ep;
+              const cx<T> b2 = cx<T>(sh[ii][r][H + nm].re, sh[ii][r][H + nm].im) * em;
+              sMe = a1 + a2;
+              dMe = a1 - a2;
+              sNe = b1 + b2;
+              dNe = b1 - b2;
+            }
+            Er[r] = Er[r] + Pb * (cl * sNe);
+            Et[r] = Et[r] + mul_i(Ub * (al * dMe)) + tau * (bl * sNe);
+            Ep[r] = Ep[r] - tau * (al * sMe) + mul_i(Ub * (bl * dNe));
           }
         }
       }
-    }
-    for (int r = 0; r < R; ++r) {
-      acc[r][0] = acc[r][0] + (st * cf) * Er[r] + (ct * cf) * Et[r] - sf * Ep[r];
-      acc[r][1] = acc[r][1] + (st * sf) * Er[r] + (ct * sf) * Et[r] + cf * Ep[r];
-      acc[r][2] = acc[r][2] + ct * Er[r] - st * Et[r];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        acc[r][0] = acc[r][0] + (st * cf) * Er[r] + (ct * cf) * Et[r] - sf * Ep[r];
+        acc[r][1] = acc[r][1] + (st * sf) * Er[r] + (ct * sf) * Et[r] + cf * Ep[r];
+        acc[r][2] = acc[r][2] + ct * Er[r] - st * Et[r];
+      }
     }
   }
   if (!live) return;
+#pragma unroll
   for (int r = 0; r < R; ++r)
+#pragma unroll
     for (int q = 0; q < 3; ++q)
       E[((size_t)r * P + ip) * 3 + q] = tm_c128{(double)acc[r][q].re, (double)acc[r][q].im};
+}
+
+template <typename T, int LMAX>
+static void nf_dispatch_r(int R, dim3 g, hipStream_t st, const tm_c128* s, int N, int nx, double x0,
+                          double y0, double pitch, double k, const double* pts, int P, tm_c128* E) {
+  switch (R) {
+    case 1: hipLaunchKernelGGL((near_field_v2<T, LMAX, 1>), g, dim3(256), 0, st, s, N, nx, x0, y0, pitch, k, pts, P, E); break;
+    case 2: hipLaunchKernelGGL((near_field_v2<T, LMAX, 2>), g, dim3(256), 0, st, s, N, nx, x0, y0, pitch, k, pts, P, E); break;
+    case 3: hipLaunchKernelGGL((near_field_v2<T, LMAX, 3>), g, dim3(256), 0, st, s, N, nx, x0, y0, pitch, k, pts, P, E); break;
+    default: hipLaunchKernelGGL((near_field_v2<T, LMAX, 4>), g, dim3(256), 0, st, s, N, nx, x0, y0, pitch, k, pts, P, E); break;
+  }
+}
+
+template <typename T>
+static void nf_dispatch(int lmax, int R, dim3 g, hipStream_t st, const tm_c128* s, int N, int nx,
+                        double x0, double y0, double pitch, double k, const double* pts, int P,
+                        tm_c128* E) {
+  switch (lmax) {
+    case 1: nf_dispatch_r<T, 1>(R, g, st, s, N, nx, x0, y0, pitch, k, pts, P, E); break;
+    case 2: nf_dispatch_r<T, 2>(R, g, st, s, N, nx, x0, y0, pitch, k, pts, P, E); break;
+    default: nf_dispatch_r<T, 3>(R, g, st, s, N, nx, x0, y0, pitch, k, pts, P, E); break;
+  }
 }
 
 // F(d) = (1/k) sum_i e^{-ik d.x_i} sum_n s_{i,n} F_n(d), with
@@ -557,11 +670,11 @@ int launch_near_field(tm_ctx* c, int R, const tm_c128* s, int P, const double* p
     const tm_c128* sr = s + (size_t)r0 * g.n * g.L;
     tm_c128* Er = E + (size_t)r0 * P * 3;
     if (precision == TM_PREC_MIXED)
-      hipLaunchKernelGGL(near_field_kernel<float>, dim3(nblk(P)), dim3(256), 0, c->stream, sr, nr,
-                         g.n, g.L, g.lmax, g.nx, g.x0, g.y0, g.pitch, g.k, pts, P, Er);
+      nf_dispatch<float>(g.lmax, nr, dim3(nblk(P)), c->stream, sr, g.n, g.nx, g.x0, g.y0, g.pitch,
+                         g.k, pts, P, Er);
     else
-      hipLaunchKernelGGL(near_field_kernel<double>, dim3(nblk(P)), dim3(256), 0, c->stream, sr,
-                         nr, g.n, g.L, g.lmax, g.nx, g.x0, g.y0, g.pitch, g.k, pts, P, Er);
+      nf_dispatch<double>(g.lmax, nr, dim3(nblk(P)), c->stream, sr, g.n, g.nx, g.x0, g.y0,
+                          g.pitch, g.k, pts, P, Er);
   }
   TM_HIP(c, hipGetLastError());
   return TM_OK;

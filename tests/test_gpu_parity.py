@@ -180,21 +180,24 @@ def test_solve_multi_rhs_and_x0_and_adjoint():
 
 
 # ----------------------------------------------------------------- readout + adjoint
-def test_near_field_and_detector():
+@pytest.mark.parametrize("R,lmax", [(2, 3), (1, 2), (3, 3), (5, 1)])
+def test_near_field_and_detector(R, lmax):
     rng = np.random.default_rng(4)
-    ctx, pos, radii = make_ctx(6, 4, 3)
-    s = rand_vec(rng, 2, 24, 30) * 0.1
-    pts = np.array([[0.3, 0.3, 5.0], [1.0, -2.0, 0.7], [1.5, 0.9, -3.0], [0.6, 0.6, 0.45]])
+    ctx, pos, radii = make_ctx(6, 4, lmax)
+    L = oracle.n_coeffs(lmax)
+    s = rand_vec(rng, R, 24, L) * 0.1
+    pts = np.array([[0.3, 0.3, 5.0], [1.0, -2.0, 0.7], [1.5, 0.9, -3.0], [0.6, 0.6, 0.45],
+                    [0.0, 0.0, 0.5], [40.0, 30.0, 2.0]])
     E64 = host(ctx.near_field(to_dev(s), to_dev(pts, torch.float64), "fp64"))
     E32 = host(ctx.near_field(to_dev(s), to_dev(pts, torch.float64), "mixed"))
-    for r in range(2):
-        ref = oracle.near_field(s[r], pos, K, 3, pts)
+    for r in range(R):
+        ref = oracle.near_field(s[r], pos, K, lmax, pts)
         assert rel(E64[r], ref) < 1e-11
         assert rel(E32[r], ref) < 1e-4
     xd = np.array([0.9, 1.1, 4.0])
     w = np.array([1.0 + 0.5j, -0.3j, 0.2])
     v = host(ctx.detector_vector(xd, w))
-    vr = np.einsum('c,cil->il', w, oracle.detector_vectors(pos, K, 3, xd))
+    vr = np.einsum('c,cil->il', w, oracle.detector_vectors(pos, K, lmax, xd))
     assert rel(v, vr) < 1e-12
     ctx.close()
 
