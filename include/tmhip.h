@@ -86,6 +86,15 @@ int tm_set_geometry(tm_ctx* ctx, int n, const double* pos, double k, int lmax);
 /* Lattice dimensions of the current geometry (host outputs). */
 int tm_get_lattice(const tm_ctx* ctx, int* nx, int* ny, double* pitch);
 
+/* Mie T-matrix of one homogeneous sphere (the sphere case of App. I.B),
+ * computed on the current HIP device, no context needed: t_out host
+ * [2][lmax] with t_out[p*lmax + l-1] = -b_l (p = 0, M-type) or -a_l (p = 1,
+ * N-type); dtdr_out host [2][lmax] or NULL: d t / d radius.  Requires
+ * 1 <= lmax <= 3, k > 0, radius > 0, n_im >= 0 and k radius |n| <= 12.
+ * Synchronous; allocates and frees a small device buffer. */
+int tm_mie(int lmax, double k, double radius, double n_re, double n_im, tm_c128* t_out,
+           tm_c128* dtdr_out);
+
 /* Homogeneous spheres (Mie T-matrices, the sphere case of App. I.B):
  * radii: device, [N] (> 0, finite; neighbouring spheres must not overlap,
  * i.e. r_i + r_j < pitch for lattice neighbours, else TM_ERR_OVERLAP);
@@ -202,6 +211,16 @@ int tm_batch_graph_used(const tm_ctx* ctx);
 int tm_near_field(tm_ctx* ctx, int n_rhs, const tm_c128* s, int n_pts, const double* pts,
                   tm_c128* E, int precision);
 
+/* Transpose (not conjugate transpose) of the near-field map s -> E_sca:
+ * v[r][i][n] = sum_p sum_c w[r][p][c] Phi_n(k(x_p - x_i))_c, so that
+ * sum_{p,c} w[r][p][c] E_sca[r][p][c] = sum_{i,n} v[r][i][n] s[r][i][n].
+ * It turns a field-space weight into the adjoint source of App. IV (the
+ * multi-point form of tm_detector_vector).  pts: device [P][3] (outside every
+ * enclosing sphere); w: device [R][P][3]; v: device [R][N][L]; FP64.
+ * P = 0 writes zeros.  1 <= n_rhs <= 65535. */
+int tm_near_field_adjoint(tm_ctx* ctx, int n_rhs, int n_pts, const double* pts, const tm_c128* w,
+                          tm_c128* v);
+
 /* Far-field amplitude F(d) = lim_r r e^{-ikr} E_sca(r d): dirs device [D][3]
  * unit vectors; F device [R][D][3]. */
 int tm_far_field(tm_ctx* ctx, int n_rhs, const tm_c128* s, int n_dir, const double* dirs,
@@ -229,8 +248,9 @@ int tm_grad_radius(tm_ctx* ctx, int n_rhs, const tm_c128* mu, const tm_c128* s,
  * variant 0..7 (operands read from global memory): bit 0 = complex products
  * from three real matrix-core products (else four), bit 1 = operands of the
  * next displacement loaded during the current one's products, bit 2 =
- * register budget for 4 (else 2) waves per SIMD; variant 8: source windows
- * staged in LDS per block of displacements.  items: target work items per
+ * register budget for 4 (else 2) waves per SIMD; variants 8, 9, 10: source
+ * windows staged in LDS per block of displacements, translation blocks
+ * fetched 1, 2, 3 displacements ahead.  items: target work items per
  * (rhs, class) pair, 0 = default.  All variants compute the same product. */
 int tm_set_matvec_config(tm_ctx* ctx, int precision, int variant, int items);
 int tm_get_matvec_config(tm_ctx* ctx, int precision, int* variant, int* items);

@@ -365,6 +365,29 @@ int tm_get_lattice(const tm_ctx* c, int* nx, int* ny, double* pitch) {
   return TM_OK;
 }
 
+int tm_mie(int lmax, double k, double radius, double n_re, double n_im, tm_c128* t_out,
+           tm_c128* dtdr_out) {
+  if (lmax < 1 || lmax > tmh::LMAX_SUPPORTED || !t_out) return TM_ERR_INVALID_ARG;
+  if (!std::isfinite(k) || !std::isfinite(radius) || !std::isfinite(n_re) || !std::isfinite(n_im))
+    return TM_ERR_NAN;
+  const double nabs = std::hypot(n_re, n_im);
+  if (!(k > 0.0) || !(radius > 0.0) || n_im < 0.0 || k * radius * std::max(1.0, nabs) > 12.0)
+    return TM_ERR_INVALID_ARG;
+  tm_c128* d = nullptr;
+  const size_t bytes = (size_t)4 * lmax * sizeof(tm_c128);
+  if (hipMalloc((void**)&d, bytes) != hipSuccess) return TM_ERR_OOM;
+  int rc = tmh::launch_mie_one(nullptr, radius, k, n_re, n_im, lmax, d);
+  tm_c128 h[4 * tmh::LMAX_SUPPORTED];
+  if (rc == TM_OK && hipMemcpy(h, d, bytes, hipMemcpyDeviceToHost) != hipSuccess) rc = TM_ERR_HIP;
+  if (hipFree(d) != hipSuccess && rc == TM_OK) rc = TM_ERR_HIP;
+  if (rc != TM_OK) return rc;
+  for (int q = 0; q < 2 * lmax; ++q) {
+    t_out[q] = h[q];
+    if (dtdr_out) dtdr_out[q] = h[2 * lmax + q];
+  }
+  return TM_OK;
+}
+
 int tm_set_spheres(tm_ctx* c, const double* radii, double n_re, double n_im) {
   CHECK_CTX(c);
   if (!c->have_geom) return tmh::set_err(c, TM_ERR_STATE, "set geometry first");
@@ -536,6 +559,15 @@ int tm_detector_vector(tm_ctx* c, const double* xd, const tm_c128* w, tm_c128* v
   return tmh::launch_detector(c, xd, w, v);
 }
 
+int tm_near_field_adjoint(tm_ctx* c, int R, int P, const double* pts, const tm_c128* w,
+                          tm_c128* v) {
+  CHECK_CTX(c);
+  if (!c->have_geom) return tmh::set_err(c, TM_ERR_STATE, "set geometry first");
+  if (R < 1 || R > 65535 || P < 0 || !v || (P > 0 && (!pts || !w)))
+    return tmh::set_err(c, TM_ERR_INVALID_ARG, "bad arguments");
+  return tmh::launch_near_field_t(c, R, P, pts, w, v);
+}
+
 int tm_grad_radius(tm_ctx* c, int R, const tm_c128* mu, const tm_c128* s, const tm_c128* a0,
                    double* grad) {
   CHECK_CTX(c);
@@ -560,7 +592,7 @@ int tm_grad_radius(tm_ctx* c, int R, const tm_c128* mu, const tm_c128* s, const 
 
 int tm_set_matvec_config(tm_ctx* c, int precision, int variant, int items) {
   CHECK_CTX(c);
-  if ((precision != TM_PREC_FP64 && precision != TM_PREC_MIXED) || variant < 0 || variant > 8 ||
+  if ((precision != TM_PREC_FP64 && precision != TM_PREC_MIXED) || variant < 0 || variant > 10 ||
       items < 0)
     return tmh::set_err(c, TM_ERR_INVALID_ARG, "bad matvec configuration");
   const int w = precision == TM_PREC_MIXED ? 1 : 0;

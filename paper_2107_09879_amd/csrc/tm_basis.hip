@@ -130,13 +130,10 @@ __device__ inline cx<double> sph_j_series(int l, cx<double> z) {
   return (1.0 / df) * (zl * sum);
 }
 
-__global__ void mie_kernel(const double* __restrict__ radii, int N, double k, double nre,
-                           double nim, int lmax, SlotMaps mp, c128* __restrict__ t64,
-                           c64* __restrict__ t32, c128* __restrict__ dt64) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  const double x = k * radii[i];
-  const cx<double> m(nre, nim);
+// Sphere T entries for l = 1..lmax: t[p][l] (p = 0: -b_l, p = 1: -a_l) and
+// their radius derivatives dt[p][l] = k d t / dx, x = k r, m = relative index.
+__device__ void mie_t_of_l(double x, double k, cx<double> m, int lmax, cx<double> (*t)[LMAX_SUPPORTED + 1],
+                           cx<double> (*dt)[LMAX_SUPPORTED + 1]) {
   const cx<double> X(x, 0.0);
   const cx<double> Y = m * X;
   cx<double> jx[LMAX_SUPPORTED + 1], hx[LMAX_SUPPORTED + 1], jy[LMAX_SUPPORTED + 1];
@@ -179,18 +176,43 @@ __global__ void mie_kernel(const double* __restrict__ radii, int N, double k, do
     const cx<double> a = na / da, b = nb / db;
     const cx<double> dadx = (na_x * da - na * da_x) / (da * da);
     const cx<double> dbdx = (nb_x * db - nb * db_x) / (db * db);
-    for (int mm = -l; mm <= l; ++mm) {
+    t[0][l] = cx<double>(-b.re, -b.im);
+    t[1][l] = cx<double>(-a.re, -a.im);
+    dt[0][l] = (-k) * dbdx;
+    dt[1][l] = (-k) * dadx;
+  }
+}
+
+__global__ void mie_kernel(const double* __restrict__ radii, int N, double k, double nre,
+                           double nim, int lmax, SlotMaps mp, c128* __restrict__ t64,
+                           c64* __restrict__ t32, c128* __restrict__ dt64) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  cx<double> t[2][LMAX_SUPPORTED + 1], dt[2][LMAX_SUPPORTED + 1];
+  mie_t_of_l(k * radii[i], k, cx<double>(nre, nim), lmax, t, dt);
+  for (int l = 1; l <= lmax; ++l)
+    for (int mm = -l; mm <= l; ++mm)
       for (int p = 0; p < 2; ++p) {
         const int n = n_of_plm(p, l, mm, lmax);
         const size_t o = ((size_t)mp.cls_of[n] * N + i) * SLOTS + mp.slot_of[n];
-        const cx<double> t = (p == 0) ? cx<double>(-b.re, -b.im) : cx<double>(-a.re, -a.im);
-        const cx<double> d = (p == 0) ? (-k) * dbdx : (-k) * dadx;
-        t64[o] = c128{t.re, t.im};
-        t32[o] = c64{(float)t.re, (float)t.im};
-        dt64[o] = c128{d.re, d.im};
+        t64[o] = c128{t[p][l].re, t[p][l].im};
+        t32[o] = c64{(float)t[p][l].re, (float)t[p][l].im};
+        dt64[o] = c128{dt[p][l].re, dt[p][l].im};
       }
+}
+
+// one sphere: out[0 .. 2 lmax) = t[p][l], out[2 lmax .. 4 lmax) = dt[p][l],
+// index p * lmax + (l - 1)
+__global__ void mie_one_kernel(double radius, double k, double nre, double nim, int lmax,
+                               tm_c128* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  cx<double> t[2][LMAX_SUPPORTED + 1], dt[2][LMAX_SUPPORTED + 1];
+  mie_t_of_l(k * radius, k, cx<double>(nre, nim), lmax, t, dt);
+  for (int p = 0; p < 2; ++p)
+    for (int l = 1; l <= lmax; ++l) {
+      out[p * lmax + l - 1] = tm_c128{t[p][l].re, t[p][l].im};
+      out[2 * lmax + p * lmax + l - 1] = tm_c128{dt[p][l].re, dt[p][l].im};
     }
-  }
 }
 
 // t (boundary [N][L]) -> slot layouts
@@ -542,17 +564,11 @@ __global__ __launch_bounds__(FF_THREADS) void far_field_kernel(
 }
 
 // v[i][n] = sum_c w_c Phi_n(k(xd - x_i))_c
-__global__ void detector_kernel(double xdx, double xdy, double xdz, double wxr, double wxi,
-                                double wyr, double wyi, double wzr, double wzi, int N, int L,
-                                int lmax, int nx, double x0, double y0, double pitch, double k,
-                                tm_c128* __restrict__ v) {
-  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (long long)N * L) return;
-  const int n = (int)(e % L);
-  const long long i = e / L;
-  const double dx = xdx - (x0 + pitch * (double)(i % nx));
-  const double dy = xdy - (y0 + pitch * (double)(i / nx));
-  const double dz = xdz;
+// Cartesian components of the outgoing function Phi_n(k (dx, dy, dz)), FP64
+// (the same definition as the near-field kernels: spherical components of
+// M / N over sqrt(2l(l+1)), rotated to x, y, z).
+__device__ void outgoing_xyz(int n, int lmax, double dx, double dy, double dz, double k,
+                             cx<double>& Ex, cx<double>& Ey, cx<double>& Ez) {
   const double rho2 = dx * dx + dy * dy;
   const double rr = sqrt(rho2 + dz * dz);
   const double x = k * rr;
@@ -571,9 +587,10 @@ __global__ void detector_kernel(double xdx, double xdy, double xdz, double wxr, 
   double Pb, U, tau;
   legendre_one<double>(l, m < 0 ? -m : m, ct, st, Pb, U, tau);
   const double pi = (double)m * U;
-  double sm, cm;
-  sincos((double)m * atan2(sf, cf), &sm, &cm);
-  const cx<double> em(cm, sm);
+  // e^{i m phi} = (cf + i sf)^m
+  cx<double> em(1.0, 0.0);
+  const cx<double> ef(cf, m < 0 ? -sf : sf);
+  for (int q = 0; q < (m < 0 ? -m : m); ++q) em = em * ef;
   const double nrm = 1.0 / sqrt(2.0 * l * (l + 1));
   cx<double> Er, Et, Ep;
   if (p == 0) {
@@ -588,11 +605,64 @@ __global__ void detector_kernel(double xdx, double xdy, double xdz, double wxr, 
   Er = nrm * (Er * em);
   Et = nrm * (Et * em);
   Ep = nrm * (Ep * em);
-  const cx<double> Ex = (st * cf) * Er + (ct * cf) * Et - sf * Ep;
-  const cx<double> Ey = (st * sf) * Er + (ct * sf) * Et + cf * Ep;
-  const cx<double> Ez = ct * Er - st * Et;
+  Ex = (st * cf) * Er + (ct * cf) * Et - sf * Ep;
+  Ey = (st * sf) * Er + (ct * sf) * Et + cf * Ep;
+  Ez = ct * Er - st * Et;
+}
+
+__global__ void detector_kernel(double xdx, double xdy, double xdz, double wxr, double wxi,
+                                double wyr, double wyi, double wzr, double wzi, int N, int L,
+                                int lmax, int nx, double x0, double y0, double pitch, double k,
+                                tm_c128* __restrict__ v) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)N * L) return;
+  const int n = (int)(e % L);
+  const long long i = e / L;
+  cx<double> Ex, Ey, Ez;
+  outgoing_xyz(n, lmax, xdx - (x0 + pitch * (double)(i % nx)), xdy - (y0 + pitch * (double)(i / nx)),
+               xdz, k, Ex, Ey, Ez);
   const cx<double> o = cx<double>(wxr, wxi) * Ex + cx<double>(wyr, wyi) * Ey + cx<double>(wzr, wzi) * Ez;
   v[e] = tm_c128{o.re, o.im};
+}
+
+// Transpose of the near-field map: v[r][i][n] = sum_p sum_c w[r][p][c]
+// Phi_n(k(x_p - x_i))_c.  One thread per (i, n) and right-hand side
+// (blockIdx.y); points and weights stream through LDS in tiles of NFT_TILE.
+constexpr int NFT_TILE = 256;
+__global__ __launch_bounds__(256) void near_field_t_kernel(
+    const double* __restrict__ pts, const tm_c128* __restrict__ w, int P, int N, int L, int lmax,
+    int nx, double x0, double y0, double pitch, double k, tm_c128* __restrict__ v) {
+  __shared__ double sp[NFT_TILE][3];
+  __shared__ cplx<double> sw[NFT_TILE][3];
+  const int r = blockIdx.y;
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool active = e < (long long)N * L;
+  const int n = active ? (int)(e % L) : 0;
+  const long long i = active ? e / L : 0;
+  const double xi = x0 + pitch * (double)(i % nx), yi = y0 + pitch * (double)(i / nx);
+  cx<double> acc(0.0, 0.0);
+  const tm_c128* wr = w + (size_t)r * P * 3;
+  for (int p0 = 0; p0 < P; p0 += NFT_TILE) {
+    const int np = min(NFT_TILE, P - p0);
+    __syncthreads();
+    for (int t = threadIdx.x; t < np; t += blockDim.x) {
+      for (int c3 = 0; c3 < 3; ++c3) {
+        sp[t][c3] = pts[(size_t)(p0 + t) * 3 + c3];
+        const tm_c128 q = wr[(size_t)(p0 + t) * 3 + c3];
+        sw[t][c3] = cplx<double>{q.re, q.im};
+      }
+    }
+    __syncthreads();
+    if (active) {
+      for (int t = 0; t < np; ++t) {
+        cx<double> Ex, Ey, Ez;
+        outgoing_xyz(n, lmax, sp[t][0] - xi, sp[t][1] - yi, sp[t][2], k, Ex, Ey, Ez);
+        acc = acc + cx<double>(sw[t][0].re, sw[t][0].im) * Ex + cx<double>(sw[t][1].re, sw[t][1].im) * Ey +
+              cx<double>(sw[t][2].re, sw[t][2].im) * Ez;
+      }
+    }
+  }
+  if (active) v[(size_t)r * N * L + e] = tm_c128{acc.re, acc.im};
 }
 
 // grad[r][i] = 2 Re sum_slots mu * dt * aexc   (slot layout inputs)
@@ -624,6 +694,12 @@ int launch_mie(tm_ctx* c, const double* radii, double n_re, double n_im) {
                      (c128*)c->dt64.p);
   TM_HIP(c, hipGetLastError());
   return TM_OK;
+}
+
+int launch_mie_one(hipStream_t st, double radius, double k, double nre, double nim, int lmax,
+                   tm_c128* out) {
+  hipLaunchKernelGGL(mie_one_kernel, dim3(1), dim3(64), 0, st, radius, k, nre, nim, lmax, out);
+  return hipGetLastError() == hipSuccess ? TM_OK : TM_ERR_HIP;
 }
 
 int launch_set_tdiag(tm_ctx* c, const tm_c128* t) {
@@ -693,6 +769,14 @@ int launch_detector(tm_ctx* c, const double* xd, const tm_c128* w, tm_c128* v) {
   hipLaunchKernelGGL(detector_kernel, dim3(nblk((long long)g.n * g.L)), dim3(256), 0, c->stream,
                      xd[0], xd[1], xd[2], w[0].re, w[0].im, w[1].re, w[1].im, w[2].re, w[2].im,
                      g.n, g.L, g.lmax, g.nx, g.x0, g.y0, g.pitch, g.k, v);
+  TM_HIP(c, hipGetLastError());
+  return TM_OK;
+}
+
+int launch_near_field_t(tm_ctx* c, int R, int P, const double* pts, const tm_c128* w, tm_c128* v) {
+  const Geometry& g = c->g;
+  hipLaunchKernelGGL(near_field_t_kernel, dim3(nblk((long long)g.n * g.L), R), dim3(256), 0,
+                     c->stream, pts, w, P, g.n, g.L, g.lmax, g.nx, g.x0, g.y0, g.pitch, g.k, v);
   TM_HIP(c, hipGetLastError());
   return TM_OK;
 }

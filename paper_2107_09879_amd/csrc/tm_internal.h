@@ -141,6 +141,9 @@ int launch_near_field(tm_ctx* c, int R, const tm_c128* s, int P, const double* p
                       int precision);
 int launch_far_field(tm_ctx* c, int R, const tm_c128* s, int D, const double* dirs, tm_c128* F);
 int launch_detector(tm_ctx* c, const double* xd, const tm_c128* w, tm_c128* v);
+int launch_mie_one(hipStream_t st, double radius, double k, double nre, double nim, int lmax,
+                   tm_c128* out);
+int launch_near_field_t(tm_ctx* c, int R, int P, const double* pts, const tm_c128* w, tm_c128* v);
 int launch_grad(tm_ctx* c, int R, const c128* mu_slot, const c128* aexc_slot, double* grad);
 
 // layout conversions (tm_krylov.hip)

@@ -248,9 +248,9 @@ __global__ __launch_bounds__(256, OCC) void block_matvec_kernel(MvArgs a) {
 
 template <typename T>
 int lds_apply(tm_ctx* c, int which, int R, const void* table, const void* xin, const c128* x,
-              c128* y, int op, int items_target, hipEvent_t e0, hipEvent_t e1);
-constexpr int LDS_VARIANT = 8;
-constexpr int N_VARIANTS = 9;
+              c128* y, int op, int items_target, hipEvent_t e0, hipEvent_t e1, int pf);
+constexpr int LDS_VARIANT = 8;  // 8, 9, 10: LDS-staged with A prefetched 1, 2, 3 displacements ahead
+constexpr int N_VARIANTS = 11;
 
 using MvKernel = void (*)(MvArgs);
 template <typename T>
@@ -437,14 +437,15 @@ static int apply_impl(tm_ctx* c, Op op, int R, const c128* x, c128* y) {
                        total);
     xin = (const cplx<T>*)c->xlow.p;
   }
-  if (c->mv_variant[which] == LDS_VARIANT) {
+  if (c->mv_variant[which] >= LDS_VARIANT) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->prof) {
       TM_HIP(c, hipEventCreate(&e0));
       TM_HIP(c, hipEventCreate(&e1));
     }
     const int tgt = c->mv_items[which] > 0 ? c->mv_items[which] : default_items(R);
-    rc = lds_apply<T>(c, which, R, table, xin, x, y, (int)op, tgt, e0, e1);
+    rc = lds_apply<T>(c, which, R, table, xin, x, y, (int)op, tgt, e0, e1,
+                      c->mv_variant[which] - LDS_VARIANT + 1);
     if (c->prof && rc == TM_OK) {
       c->prof_pending[which].push_back({e0, e1});
       c->prof_acc[which].flops = matvec_flops(g) * R;
@@ -509,11 +510,12 @@ static int autotune_impl(tm_ctx* c, int R, double* best_ms) {
     for (int wt : wg_targets) {
       c->mv_variant[which] = v;
       c->mv_items[which] = std::max(1, wt / (2 * R));
-      if (v == LDS_VARIANT) {
+      if (v >= LDS_VARIANT) {
         double tmin = 1e300;
         for (int rep = 0; rep < 3; ++rep) {
           rc = lds_apply<T>(c, which, R, std::is_same<T, double>::value ? c->tab64.p : c->tab32.p,
-                            c->xlow.p, nullptr, nullptr, 0, c->mv_items[which], e0, e1);
+                            c->xlow.p, nullptr, nullptr, 0, c->mv_items[which], e0, e1,
+                            v - LDS_VARIANT + 1);
           if (rc != TM_OK) return rc;
           TM_HIP(c, hipEventSynchronize(e1));
           float ms = 0.f;

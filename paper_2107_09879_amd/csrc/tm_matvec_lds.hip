@@ -122,7 +122,7 @@ struct LdsCfg {
 
 // Complex products by three real MFMA products (T1 = Mr Xr, T2 = Mi Xi,
 // T3 = (Mr + Mi)(Xr + Xi); Yr = T1 - T2, Yi = T3 - T1 - T2).
-template <typename T, int GX, int BX, int BY>
+template <typename T, int GX, int BX, int BY, int PF>
 __global__ __launch_bounds__(256, 2) void block_matvec_lds_kernel(LdsArgs a) {
   using L = LdsT<T>;
   using Cfg = LdsCfg<T, GX, BX, BY>;
@@ -197,11 +197,13 @@ __global__ __launch_bounds__(256, 2) void block_matvec_lds_kernel(LdsArgs a) {
     if (dyb > dye || dxb > dxe) continue;
     const int ndx = dxe - dxb + 1;
     const int nq = (dye - dyb + 1) * ndx;
-    // operand pipeline: A (global) and B (LDS, all groups) of the next
-    // displacement are fetched while the current one's MFMAs run
-    T ar[4], ai[4], nar[4], nai[4];
+    // operand pipeline: A (the translation block, from global memory) is
+    // fetched PF displacements ahead -- table rows mostly miss L2, so the
+    // latency is that of HBM/MALL; B (all groups, from LDS) one ahead
+    T ar[PF + 1][4], ai[PF + 1][4];
     T br[GX][4], bi[GX][4], nbr[GX][4], nbi[GX][4];
-    auto blk_of = [&](int dx, int dy) {
+    auto blk_of = [&](int q) {
+      const int dx = dxb + q % ndx, dy = dyb + q / ndx;
       return tab + (((size_t)(dy + a.tny - 1) * wxt + (dx + a.tnx - 1)) * NCLASS + c) * (SLOTS * SLOTS);
     };
     auto read_all_b = [&](int dx, int dy, T (*r_)[4], T (*i_)[4]) {
@@ -212,7 +214,9 @@ __global__ __launch_bounds__(256, 2) void block_matvec_lds_kernel(LdsArgs a) {
         read_b(win, (wy * WX + wx) * CH, wx, wy, kq, r_[g], i_[g]);
       }
     };
-    load_a(blk_of(dxb, dyb), jt, kq, ar, ai);
+#pragma unroll
+    for (int p = 0; p < PF; ++p)
+      if (p < nq) load_a(blk_of(p), jt, kq, ar[p], ai[p]);
     read_all_b(dxb, dyb, br, bi);
     int dx = dxb, dy = dyb;
     for (int q = 0; q < nq; ++q) {
@@ -222,13 +226,11 @@ __global__ __launch_bounds__(256, 2) void block_matvec_lds_kernel(LdsArgs a) {
         ++ndyv;
       }
       const bool more = q + 1 < nq;
-      if (more) {
-        load_a(blk_of(ndxv, ndyv), jt, kq, nar, nai);
-        read_all_b(ndxv, ndyv, nbr, nbi);
-      }
+      if (q + PF < nq) load_a(blk_of(q + PF), jt, kq, ar[PF], ai[PF]);
+      if (more) read_all_b(ndxv, ndyv, nbr, nbi);
       T ms[4];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) ms[s] = ar[s] + ai[s];
+      for (int s = 0; s < 4; ++s) ms[s] = ar[0][s] + ai[0][s];
 #pragma unroll
       for (int g = 0; g < GX; ++g) {
         const int gx0 = X0 + 4 * g;
@@ -238,22 +240,26 @@ __global__ __launch_bounds__(256, 2) void block_matvec_lds_kernel(LdsArgs a) {
         for (int s = 0; s < 4; ++s) xs[s] = br[g][s] + bi[g][s];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-          t1[g] = L::mma(ar[s], br[g][s], t1[g]);
-          t2[g] = L::mma(ai[s], bi[g][s], t2[g]);
+          t1[g] = L::mma(ar[0][s], br[g][s], t1[g]);
+          t2[g] = L::mma(ai[0][s], bi[g][s], t2[g]);
           t3[g] = L::mma(ms[s], xs[s], t3[g]);
         }
       }
-      if (more) {
+#pragma unroll
+      for (int p = 0; p < PF; ++p)
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-          ar[s] = nar[s];
-          ai[s] = nai[s];
+          ar[p][s] = ar[p + 1][s];
+          ai[p][s] = ai[p + 1][s];
+        }
+      if (more) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
 #pragma unroll
           for (int g = 0; g < GX; ++g) {
             br[g][s] = nbr[g][s];
             bi[g][s] = nbi[g][s];
           }
-        }
       }
       dx = ndxv;
       dy = ndyv;
@@ -405,9 +411,22 @@ struct LdsChoice<double> {
   static constexpr int GX = 2, BX = 8, BY = 4;
 };
 
+template <typename T, int PF>
+static void lds_launch_pf(hipStream_t st, int nitems, int R, const LdsArgs& a) {
+  using Ch = LdsChoice<T>;
+  hipLaunchKernelGGL((block_matvec_lds_kernel<T, Ch::GX, Ch::BX, Ch::BY, PF>), dim3(nitems, 2 * R),
+                     dim3(256), 0, st, a);
+}
+template <typename T>
+static void lds_launch_any(hipStream_t st, int pf, int nitems, int R, const LdsArgs& a) {
+  if (pf <= 1) lds_launch_pf<T, 1>(st, nitems, R, a);
+  else if (pf == 2) lds_launch_pf<T, 2>(st, nitems, R, a);
+  else lds_launch_pf<T, 3>(st, nitems, R, a);
+}
+
 template <typename T>
 int lds_apply(tm_ctx* c, int which, int R, const void* table, const void* xin, const c128* x,
-              c128* y, int op, int items_target, hipEvent_t e0, hipEvent_t e1) {
+              c128* y, int op, int items_target, hipEvent_t e0, hipEvent_t e1, int pf) {
   using Ch = LdsChoice<T>;
   using Cfg = LdsCfg<T, Ch::GX, Ch::BX, Ch::BY>;
   const Geometry& g = c->g;
@@ -447,9 +466,8 @@ int lds_apply(tm_ctx* c, int which, int R, const void* table, const void* xin, c
   a.subs = nullptr;
   a.active = nullptr;
   a.done = nullptr;
-  auto kern = block_matvec_lds_kernel<T, Ch::GX, Ch::BX, Ch::BY>;
   if (e0) TM_HIP(c, hipEventRecord(e0, c->stream));
-  hipLaunchKernelGGL(kern, dim3(nitems, 2 * R), dim3(256), 0, c->stream, a);
+  lds_launch_any<T>(c->stream, pf, nitems, R, a);
   if (e1) TM_HIP(c, hipEventRecord(e1, c->stream));
   if (y) {
     const int nb = (int)((total + 255) / 256);
@@ -475,7 +493,6 @@ template void lds_geometry<double>(int&, int&, int&);
 template <typename T>
 int lds_launch(tm_ctx* c, const void* table, const void* xin, void* partial, const LdsItem* items,
                int nitems, int R, const SubParams* subs, const int* active, const int* done) {
-  using Ch = LdsChoice<T>;
   LdsArgs a;
   a.table = table;
   a.x = xin;
@@ -491,8 +508,8 @@ int lds_launch(tm_ctx* c, const void* table, const void* xin, void* partial, con
   a.subs = subs;
   a.active = active;
   a.done = done;
-  hipLaunchKernelGGL((block_matvec_lds_kernel<T, Ch::GX, Ch::BX, Ch::BY>), dim3(nitems, 2 * R),
-                     dim3(256), 0, c->stream, a);
+  const int w = std::is_same<T, double>::value ? 0 : 1;
+  lds_launch_any<T>(c->stream, std::max(1, c->mv_variant[w] - 7), nitems, R, a);
   return TM_OK;
 }
 template int lds_launch<float>(tm_ctx*, const void*, const void*, void*, const LdsItem*, int, int,
@@ -501,8 +518,8 @@ template int lds_launch<double>(tm_ctx*, const void*, const void*, void*, const 
                                 const SubParams*, const int*, const int*);
 
 template int lds_apply<float>(tm_ctx*, int, int, const void*, const void*, const c128*, c128*, int,
-                              int, hipEvent_t, hipEvent_t);
+                              int, hipEvent_t, hipEvent_t, int);
 template int lds_apply<double>(tm_ctx*, int, int, const void*, const void*, const c128*, c128*, int,
-                               int, hipEvent_t, hipEvent_t);
+                               int, hipEvent_t, hipEvent_t, int);
 
 }  // namespace tmh

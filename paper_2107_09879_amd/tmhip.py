@@ -92,6 +92,8 @@ def load():
         "tm_adjoint_solve": (I, [P, I, P, P, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo)]),
         "tm_apply_operator": (I, [P, I, P, P, I, I]),
         "tm_near_field": (I, [P, I, P, I, P, P, I]),
+        "tm_near_field_adjoint": (I, [P, I, I, P, P, P]),
+        "tm_mie": (I, [I, D, D, D, D, P, P]),
         "tm_far_field": (I, [P, I, P, I, P, P]),
         "tm_detector_vector": (I, [P, P, P, P]),
         "tm_grad_radius": (I, [P, I, P, P, P, P]),
@@ -113,6 +115,20 @@ def load():
     return lib
 
 
+def mie(lmax, k, radius, n_rel):
+    """(t [2][lmax], dt/dr [2][lmax]) of one sphere from tm_mie (host arrays;
+    p = 0 rows hold -b_l, p = 1 rows -a_l)."""
+    lib = load()
+    n = complex(n_rel)
+    t = np.zeros((2, lmax), dtype=np.complex128)
+    d = np.zeros((2, lmax), dtype=np.complex128)
+    rc = lib.tm_mie(int(lmax), float(k), float(radius), n.real, n.imag,
+                    t.ctypes.data_as(ctypes.c_void_p), d.ctypes.data_as(ctypes.c_void_p))
+    if rc != TM_OK:
+        raise TmError(rc, lib.tm_status_string(rc).decode())
+    return t, d
+
+
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
@@ -124,6 +140,11 @@ def _dev(t, dtype, name):
         raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
+    # the library reads raw memory: materialise lazy conjugate / negative views
+    if t.is_conj():
+        t = t.resolve_conj()
+    if t.is_neg():
+        t = t.resolve_neg()
     return t
 
 
@@ -268,6 +289,15 @@ class Context:
                                            PRECISIONS[precision]))
         return E
 
+    def near_field_adjoint(self, pts, w):
+        """v = transpose of the near-field map applied to w [R, P, 3]."""
+        pts = _dev(pts, torch.float64, "pts")
+        w = _dev(w, torch.complex128, "w")
+        R = w.shape[0] if w.dim() == 3 else 1
+        v = torch.empty(R, self.n, self.L, dtype=torch.complex128, device=self.device)
+        self._check(self.lib.tm_near_field_adjoint(self.h, R, pts.shape[0], _ptr(pts), _ptr(w), _ptr(v)))
+        return v
+
     def far_field(self, s, dirs):
         s = _dev(s, torch.complex128, "s")
         dirs = _dev(dirs, torch.float64, "dirs")
@@ -286,8 +316,9 @@ class Context:
         return v
 
     def grad_radius(self, mu, s, a0):
-        for t, nm in ((mu, "mu"), (s, "s"), (a0, "a0")):
-            _dev(t, torch.complex128, nm)
+        mu = _dev(mu, torch.complex128, "mu")
+        s = _dev(s, torch.complex128, "s")
+        a0 = _dev(a0, torch.complex128, "a0")
         R = mu.shape[0] if mu.dim() == 3 else 1
         g = torch.empty(R, self.n, dtype=torch.float64, device=self.device)
         self._check(self.lib.tm_grad_radius(self.h, R, _ptr(mu), _ptr(s), _ptr(a0), _ptr(g)))

@@ -125,6 +125,21 @@ def test_lossy_sphere_mie():
     ctx.close()
 
 
+@pytest.mark.parametrize("lmax,radius,m", [(1, 0.05, 2.0), (3, 0.25, 2.0), (2, 0.3, 1.5 + 0.3j)])
+def test_tm_mie_single_sphere(lmax, radius, m):
+    t, d = tmhip.mie(lmax, K, radius, m)
+    for l in range(1, lmax + 1):
+        a, b, da, db = oracle.mie_ab(l, K * radius, m)
+        assert abs(t[0, l - 1] + b) <= 1e-12 * abs(b) + 1e-300
+        assert abs(t[1, l - 1] + a) <= 1e-12 * abs(a) + 1e-300
+        assert abs(d[0, l - 1] + K * db) <= 1e-11 * abs(K * db) + 1e-300
+        assert abs(d[1, l - 1] + K * da) <= 1e-11 * abs(K * da) + 1e-300
+    with pytest.raises(tmhip.TmError):
+        tmhip.mie(4, K, radius, m)
+    with pytest.raises(tmhip.TmError):
+        tmhip.mie(lmax, K, -radius, m)
+
+
 # ----------------------------------------------------------------- solve
 def _c1():
     pos, radii, kh, po, cfg = wl.config_inputs("c1")
@@ -250,7 +265,7 @@ def test_error_paths():
     ctx.close()
 
 
-@pytest.mark.parametrize("variant", range(9))
+@pytest.mark.parametrize("variant", range(11))
 def test_every_matvec_variant_matches_oracle(variant):
     """All kernel variants the autotuner may pick compute the same product."""
     print(f"[case] variant {variant}", flush=True)
@@ -275,7 +290,7 @@ def test_autotune_keeps_a_correct_configuration():
     ref = oracle.LatticeCoupling(40, 24, wl.PITCH, K, 3).apply(x[0])
     for prec, tol in (("mixed", 2e-5), ("fp64", 1e-12)):
         ms, (v, items) = ctx.autotune(1, prec)
-        assert ms > 0 and 0 <= v < 9
+        assert ms > 0 and 0 <= v < 11
         assert rel(host(ctx.apply_operator(to_dev(x), "coupling", prec))[0], ref) < tol
     ctx.close()
 
@@ -319,4 +334,38 @@ def test_batched_subregions_match_single_solves(precision, use_graph):
     s_or = oracle.solve_dense(pos[idx], K, lmax, t,
                               oracle.plane_wave_coeffs(lmax, K, kh[1], po[1], pos[idx]))
     assert rel(host(sb[0])[1], s_or) < 1e-9
+    ctx.close()
+
+
+# ----------------------------------------------------------------- full-size (100 x 100)
+def test_full_size_c2_sampled_rows_and_solve():
+    """100 x 100 lattice, lmax 3 (the benchmark workload): sampled rows of the
+    FP64 and complex64 operators against the oracle's row-by-row product, and
+    the converged mixed-precision and FP64 solves checked through the oracle's
+    rows of B s - T a0 and against each other."""
+    print("[case] full-size c2", flush=True)
+    pos, radii, kh, po, cfg = wl.config_inputs("c2")
+    n, lmax = cfg["nx"], cfg["lmax"]
+    ctx = tmhip.Context(0)
+    ctx.set_geometry(pos, K, lmax)
+    ctx.set_spheres(to_dev(radii, torch.float64), wl.N_REL)
+    rng = np.random.default_rng(2024)
+    x = rand_vec(rng, 1, n * n, 30)
+    rows = [0, 57, 4950, 5049, 9999]
+    ref = oracle.rows_A(pos, K, lmax, x[0], rows)
+    y64 = host(ctx.apply_operator(to_dev(x), "coupling", "fp64"))[0]
+    y32 = host(ctx.apply_operator(to_dev(x), "coupling", "mixed"))[0]
+    assert rel(y64[rows], ref) < 1e-12
+    assert rel(y32[rows], ref) < 2e-5
+    a0 = ctx.plane_wave_rhs(kh, po)
+    smx, imx = ctx.solve(a0, tol=1e-8, precision="mixed")
+    s64, i64 = ctx.solve(a0, tol=1e-10, precision="fp64")
+    assert imx[0]["status"] == 0 and i64[0]["status"] == 0
+    assert imx[0]["rel_residual"] <= 1e-8
+    assert rel(host(smx)[0], host(s64)[0]) < 1e-6
+    t, _ = oracle.mie_tmatrix_diag_many(lmax, K, radii[rows], wl.N_REL)
+    b = t * host(a0)[0][rows]
+    s = host(s64)[0]
+    r_rows = s[rows] - t * oracle.rows_A(pos, K, lmax, s, rows) - b
+    assert np.linalg.norm(r_rows) / np.linalg.norm(b) < 1e-6
     ctx.close()
