@@ -86,6 +86,18 @@ int tm_set_geometry(tm_ctx* ctx, int n, const double* pos, double k, int lmax);
 /* Lattice dimensions of the current geometry (host outputs). */
 int tm_get_lattice(const tm_ctx* ctx, int* nx, int* ny, double* pitch);
 
+/* General per-scatterer T-matrices (App. I.B, eq. "def_tmatrix": s_i =
+ * T_i a_exc,i with T_i mixing every (p, l, m)): T device [N][L][L]
+ * complex128, row-major per scatterer in the coefficient order above.  The
+ * data are copied (the caller keeps its buffer).  The solves, the operator
+ * and the readout then use T_i in place of the diagonal; the per-scatterer
+ * product runs in FP64 in both precisions.  There is no dT/dr for a dense T
+ * (tm_grad_radius returns TM_ERR_STATE), tm_get_tmatrix_diag returns
+ * TM_ERR_STATE and tm_solve_batched (diagonal T only) returns TM_ERR_STATE
+ * until spheres or a diagonal T are set again.  Entries are not checked for
+ * NaN. */
+int tm_set_tmatrix_dense(tm_ctx* ctx, const tm_c128* T);
+
 /* Mie T-matrix of one homogeneous sphere (the sphere case of App. I.B),
  * computed on the current HIP device, no context needed: t_out host
  * [2][lmax] with t_out[p*lmax + l-1] = -b_l (p = 0, M-type) or -a_l (p = 1,

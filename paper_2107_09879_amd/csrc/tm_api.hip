@@ -284,7 +284,7 @@ void tm_destroy(tm_ctx* c) {
   hipSetDevice(c->device);
   hipStreamSynchronize(c->stream);
   for (tmh::DevBuf* b : {&c->tab64, &c->tab32, &c->tabT64, &c->tabT32, &c->t64, &c->t32, &c->dt64,
-                        &c->partial, &c->xlow, &c->work_a, &c->work_b, &c->work_c, &c->basis,
+                        &c->tden, &c->ttmp, &c->partial, &c->xlow, &c->work_a, &c->work_b, &c->work_c, &c->basis,
                         &c->dots, &c->dotpart, &c->scal, &c->plan_items[0], &c->plan_items[1],
                         &c->plan_ibeg[0], &c->plan_ibeg[1]})
     tmh::release(*b);
@@ -342,7 +342,7 @@ int tm_set_geometry(tm_ctx* c, int n, const double* pos, double k, int lmax) {
   g.tnx = nx;
   g.tny = ny;
   tmh::host_slot_maps(lmax, g, c->maps);
-  c->have_geom = c->have_t = c->have_dt = c->have_tabT = false;
+  c->have_geom = c->have_t = c->have_dt = c->have_tabT = c->t_dense = false;
   c->plan_R[0] = c->plan_R[1] = -1;
   int rc;
   if ((rc = tmh::build_tables(c)) != TM_OK) return rc;
@@ -417,6 +417,7 @@ int tm_set_spheres(tm_ctx* c, const double* radii, double n_re, double n_im) {
   int rc = tmh::launch_mie(c, radii, n_re, n_im);
   if (rc != TM_OK) return rc;
   c->have_t = c->have_dt = true;
+  c->t_dense = false;
   return TM_OK;
 }
 
@@ -429,12 +430,29 @@ int tm_set_tmatrix_diag(tm_ctx* c, const tm_c128* t) {
   TM_HIP(c, hipMemsetAsync(c->dt64.p, 0, c->dt64.bytes, c->stream));
   c->have_t = true;
   c->have_dt = false;
+  c->t_dense = false;
+  return TM_OK;
+}
+
+int tm_set_tmatrix_dense(tm_ctx* c, const tm_c128* T) {
+  CHECK_CTX(c);
+  if (!c->have_geom) return tmh::set_err(c, TM_ERR_STATE, "set geometry first");
+  if (!T) return tmh::set_err(c, TM_ERR_INVALID_ARG, "null T");
+  const tmh::Geometry& g = c->g;
+  const size_t bytes = (size_t)g.n * g.L * g.L * sizeof(tm_c128);
+  int rc;
+  if ((rc = tmh::ensure(c, c->tden, bytes)) != TM_OK) return rc;
+  TM_HIP(c, hipMemcpyAsync(c->tden.p, T, bytes, hipMemcpyDeviceToDevice, c->stream));
+  c->have_t = true;
+  c->have_dt = false;
+  c->t_dense = true;
   return TM_OK;
 }
 
 int tm_get_tmatrix_diag(tm_ctx* c, tm_c128* t, tm_c128* dtdr) {
   CHECK_CTX(c);
   if (!c->have_t) return tmh::set_err(c, TM_ERR_STATE, "T not set");
+  if (c->t_dense) return tmh::set_err(c, TM_ERR_STATE, "T was set dense; it has no diagonal form");
   if (!t) return tmh::set_err(c, TM_ERR_INVALID_ARG, "null output");
   return tmh::launch_get_tdiag(c, t, c->have_dt ? dtdr : nullptr);
 }
@@ -484,7 +502,15 @@ static int solve_common(tm_ctx* c, Op op, int R, const tm_c128* rhs, tm_c128* ou
   c128* bsl = (c128*)c->work_a.p;
   c128* xsl = (c128*)c->work_b.p;
   tmh::pack_slots(c->stream, g, c->maps, R, rhs, bsl);
-  if (op == Op::Forward) tmh::k_mul_t(c->stream, bsl, (const c128*)c->t64.p, bsl, len, R);
+  if (op == Op::Forward) {  // b = T a0
+    if (c->t_dense) {
+      if ((rc = tmh::ensure(c, c->ttmp, (size_t)R * len * sizeof(c128))) != TM_OK) return rc;
+      if ((rc = tmh::launch_tdense(c, R, 0, nullptr, bsl, (c128*)c->ttmp.p)) != TM_OK) return rc;
+      tmh::k_copy(c->stream, bsl, (const c128*)c->ttmp.p, (long long)R * len);
+    } else {
+      tmh::k_mul_t(c->stream, bsl, (const c128*)c->t64.p, bsl, len, R);
+    }
+  }
   if (o->use_x0) tmh::pack_slots(c->stream, g, c->maps, R, out, xsl);
   bool all_ok = true;
   for (int r = 0; r < R; ++r) {

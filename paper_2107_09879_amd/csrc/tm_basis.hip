@@ -228,6 +228,39 @@ __global__ void set_t_kernel(const tm_c128* __restrict__ t, int N, SlotMaps mp,
   t32[o] = c64{(float)v.re, (float)v.im};
 }
 
+// Dense per-scatterer T (boundary order, T[i][n][n']) applied to slot-layout
+// vectors [R][class][site][16].  One thread per output element; pads give 0
+// (modes 0, 2) or x (mode 1, where x's pads are 0).
+__global__ void tdense_kernel(const tm_c128* __restrict__ T, SlotMaps mp, long long N, int mode,
+                              const c128* __restrict__ x, const c128* __restrict__ z,
+                              c128* __restrict__ y, long long total) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const int slot = (int)(e % SLOTS);
+  const long long site = (e / SLOTS) % N;
+  const long long rc = e / (SLOTS * N);
+  const long long r = rc / NCLASS;
+  const int c = (int)(rc % NCLASS);
+  const int n = mp.n_of[c][slot];
+  const int L = mp.L;
+  double ar = 0.0, ai = 0.0;
+  if (n >= 0) {
+    const tm_c128* Ti = T + (size_t)site * L * L;
+    for (int n2 = 0; n2 < L; ++n2) {
+      const c128 zv = z[((size_t)(r * NCLASS + mp.cls_of[n2]) * N + site) * SLOTS + mp.slot_of[n2]];
+      const tm_c128 tv = mode == 2 ? Ti[(size_t)n2 * L + n] : Ti[(size_t)n * L + n2];
+      ar += tv.re * zv.re - tv.im * zv.im;
+      ai += tv.re * zv.im + tv.im * zv.re;
+    }
+  }
+  if (mode == 1) {
+    const c128 xv = x[e];
+    y[e] = c128{xv.re - ar, xv.im - ai};
+  } else {
+    y[e] = c128{ar, ai};
+  }
+}
+
 // ---------------------------------------------------------------- plane wave
 struct PwArgs {
   double khat[3 * 8];
@@ -692,6 +725,15 @@ int launch_mie(tm_ctx* c, const double* radii, double n_re, double n_im) {
   hipLaunchKernelGGL(mie_kernel, dim3(nblk(g.n, 64)), dim3(64), 0, c->stream, radii, g.n, g.k,
                      n_re, n_im, g.lmax, c->maps, (c128*)c->t64.p, (c64*)c->t32.p,
                      (c128*)c->dt64.p);
+  TM_HIP(c, hipGetLastError());
+  return TM_OK;
+}
+
+int launch_tdense(tm_ctx* c, int R, int mode, const c128* x, const c128* z, c128* y) {
+  const Geometry& g = c->g;
+  const long long total = (long long)R * g.vec_len();
+  hipLaunchKernelGGL(tdense_kernel, dim3(nblk(total)), dim3(256), 0, c->stream,
+                     (const tm_c128*)c->tden.p, c->maps, (long long)g.n, mode, x, z, y, total);
   TM_HIP(c, hipGetLastError());
   return TM_OK;
 }

@@ -442,6 +442,29 @@ struct Batch {
   DevBuf b, x, r, w, V, xlow, partial, dots1, dots2, dpart, npart, hn, beta, bnorm, target, y;
   DevBuf H, cs, sn, g, jend, active, live, done;
   hipGraphExec_t graph[2] = {nullptr, nullptr};
+  // graphs are captured and replayed on a private stream (the context stream
+  // may be the legacy null stream, which cannot be captured), ordered with
+  // the context stream by events
+  hipStream_t side = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  DevBuf a0full;
+  hipStream_t ctx_stream = nullptr;
+  // everything the batch allocated is freed here, on every exit path, after
+  // the work queued on its streams has finished
+  ~Batch() {
+    if (ctx_stream) hipStreamSynchronize(ctx_stream);
+    if (side) hipStreamSynchronize(side);
+    for (int w = 0; w < 2; ++w)
+      if (graph[w]) hipGraphExecDestroy(graph[w]);
+    if (side) hipStreamDestroy(side);
+    if (ev_in) hipEventDestroy(ev_in);
+    if (ev_out) hipEventDestroy(ev_out);
+    for (DevBuf* q : {&d_sp[0], &d_sp[1], &d_out_off, &d_items[0], &d_items[1], &d_ibeg[0], &d_ibeg[1],
+                      &d_blocks, &d_sysblk, &b, &x, &r, &w, &V, &xlow, &partial, &dots1, &dots2, &dpart,
+                      &npart, &hn, &beta, &bnorm, &target, &y, &H, &cs, &sn, &g, &jend, &active, &live,
+                      &done, &a0full})
+      release(*q);
+  }
 };
 
 static int ensure_b(tm_ctx* c, DevBuf& b, size_t bytes) { return ensure(c, b, bytes); }
@@ -561,22 +584,37 @@ template <typename T>
 static int run_cycle(tm_ctx* c, Batch& B, bool use_graph, bool& graphed) {
   const int w = std::is_same<T, double>::value ? 0 : 1;
   graphed = false;
+  if (use_graph && !B.side) {
+    if (hipStreamCreateWithFlags(&B.side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&B.ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&B.ev_out, hipEventDisableTiming) != hipSuccess)
+      return set_err(c, TM_ERR_HIP, "stream/event creation for the batch graph failed");
+  }
   if (use_graph) {
     if (!B.graph[w]) {
+      // record the cycle's launches on the private stream: b_step enqueues on
+      // c->stream, so point it there for the capture only
       hipGraph_t gph = nullptr;
-      if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+      const hipStream_t ctx_stream = c->stream;
+      c->stream = B.side;
+      if (hipStreamBeginCapture(B.side, hipStreamCaptureModeThreadLocal) == hipSuccess) {
         int rc = TM_OK;
         for (int j = 0; j < B.m && rc == TM_OK; ++j) rc = b_step<T>(c, B, j);
-        const hipError_t e = hipStreamEndCapture(c->stream, &gph);
+        const hipError_t e = hipStreamEndCapture(B.side, &gph);
         if (rc == TM_OK && e == hipSuccess && gph) {
           if (hipGraphInstantiateWithFlags(&B.graph[w], gph, 0) != hipSuccess) B.graph[w] = nullptr;
         }
         if (gph) hipGraphDestroy(gph);
       }
+      c->stream = ctx_stream;
       (void)hipGetLastError();
     }
     if (B.graph[w]) {
-      TM_HIP(c, hipGraphLaunch(B.graph[w], c->stream));
+      TM_HIP(c, hipEventRecord(B.ev_in, c->stream));
+      TM_HIP(c, hipStreamWaitEvent(B.side, B.ev_in, 0));
+      TM_HIP(c, hipGraphLaunch(B.graph[w], B.side));
+      TM_HIP(c, hipEventRecord(B.ev_out, B.side));
+      TM_HIP(c, hipStreamWaitEvent(c->stream, B.ev_out, 0));
       graphed = true;
       return TM_OK;
     }
@@ -598,6 +636,7 @@ static int batched_impl(tm_ctx* c, int S, const tm_subregion* subs, int R, const
                         tm_solve_info* info, int use_graph) {
   const Geometry& g = c->g;
   Batch B;
+  B.ctx_stream = c->stream;
   B.S = S;
   B.R = R;
   B.nsys = S * R;
@@ -690,7 +729,7 @@ static int batched_impl(tm_ctx* c, int S, const tm_subregion* subs, int R, const
   };
 
   // right-hand side: plane waves on the full lattice, gathered and times T
-  DevBuf a0full;
+  DevBuf& a0full = B.a0full;
   if ((rc = ensure_b(c, a0full, (size_t)R * g.n * g.L * cb)) != TM_OK) return rc;
   if ((rc = launch_plane_wave(c, R, khat, pol, (tm_c128*)a0full.p)) != TM_OK) return rc;
   use_sp(1);
@@ -701,6 +740,10 @@ static int batched_impl(tm_ctx* c, int S, const tm_subregion* subs, int R, const
   if ((rc = b_norms(c, B, (const c128*)B.b.p, nullptr, bn)) != TM_OK) return rc;
   release(a0full);
   hipLaunchKernelGGL(b_fill, dim3(nbk(Lt)), dim3(BT), 0, c->stream, (c128*)B.x.p, Lt);
+  // basis vectors past a system's last Arnoldi step are multiplied by zero
+  // coefficients in x += V y: they must hold finite values, so clear them once
+  hipLaunchKernelGGL(b_fill, dim3(nbk((long long)(m + 1) * Lt)), dim3(BT), 0, c->stream, (c128*)B.V.p,
+                     (long long)(m + 1) * Lt);
   TM_HIP(c, hipMemcpyAsync(B.r.p, B.b.p, Lt * cb, hipMemcpyDeviceToDevice, c->stream));
   std::vector<int> live(ns, 1), iters(ns, 0), cycles(ns, 0), mv64(ns, 0), mvlo(ns, 0);
   std::vector<double> relres(ns, 0.0);
@@ -794,14 +837,6 @@ static int batched_impl(tm_ctx* c, int S, const tm_subregion* subs, int R, const
     if (info[s].status != TM_OK) all_ok = false;
   }
   c->last_batch_graphed = any_graph ? 1 : 0;
-  // free everything (the batch is self-contained)
-  for (int w = 0; w < 2; ++w)
-    if (B.graph[w]) hipGraphExecDestroy(B.graph[w]);
-  for (DevBuf* b : {&B.d_sp[0], &B.d_sp[1], &B.d_out_off, &B.d_items[0], &B.d_items[1], &B.d_ibeg[0], &B.d_ibeg[1],
-                    &B.d_blocks, &B.d_sysblk, &B.b, &B.x, &B.r, &B.w, &B.V, &B.xlow, &B.partial,
-                    &B.dots1, &B.dots2, &B.dpart, &B.npart, &B.hn, &B.beta, &B.bnorm, &B.target,
-                    &B.y, &B.H, &B.cs, &B.sn, &B.g, &B.jend, &B.active, &B.live, &B.done})
-    release(*b);
   return all_ok ? TM_OK : TM_NOT_CONVERGED;
 }
 
@@ -813,6 +848,8 @@ extern "C" int tm_solve_batched(tm_ctx* c, int n_sub, const tm_subregion* subs, 
   if (!c) return TM_ERR_INVALID_ARG;
   hipSetDevice(c->device);
   if (!c->have_geom || !c->have_t) return tmh::set_err(c, TM_ERR_STATE, "geometry and T must be set");
+  if (c->t_dense)
+    return tmh::set_err(c, TM_ERR_STATE, "the batched solver takes diagonal T (spheres or tm_set_tmatrix_diag)");
   if (n_sub < 1 || n_rhs < 1 || n_rhs > 8 || !subs || !khat || !pol || !s_out || !o || !info)
     return tmh::set_err(c, TM_ERR_INVALID_ARG, "bad arguments");
   if (!(o->tol > 0.0) || o->restart < 1 || o->restart > 200 || o->max_iter < 1 ||

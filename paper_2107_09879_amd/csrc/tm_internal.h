@@ -86,11 +86,13 @@ struct tm_ctx {
   tmh::Geometry g;
   tmh::SlotMaps maps{};
   bool have_geom = false, have_t = false, have_dt = false;
+  bool t_dense = false;  // T given as dense per-scatterer blocks (tden), not diagonal
   // translation tables [D][2][16][16]
   tmh::DevBuf tab64, tab32, tabT64, tabT32;
   bool have_tabT = false;
   // T and dT/dr in slot layout [2][N][16]
   tmh::DevBuf t64, t32, dt64;
+  tmh::DevBuf tden, ttmp;  // dense T [N][L][L] (boundary order); its scratch vector
   // workspaces
   tmh::DevBuf partial, xlow, work_a, work_b, work_c, basis, dots, dotpart, scal;
   // host staging (pinned)
@@ -141,6 +143,8 @@ int launch_near_field(tm_ctx* c, int R, const tm_c128* s, int P, const double* p
                       int precision);
 int launch_far_field(tm_ctx* c, int R, const tm_c128* s, int D, const double* dirs, tm_c128* F);
 int launch_detector(tm_ctx* c, const double* xd, const tm_c128* w, tm_c128* v);
+// dense T on slot-layout vectors: mode 0 y = T z, 1 y = x - T z, 2 y = T^T z
+int launch_tdense(tm_ctx* c, int R, int mode, const c128* x, const c128* z, c128* y);
 int launch_mie_one(hipStream_t st, double radius, double k, double nre, double nim, int lmax,
                    tm_c128* out);
 int launch_near_field_t(tm_ctx* c, int R, int P, const double* pts, const tm_c128* w, tm_c128* v);

@@ -576,9 +576,28 @@ int autotune(tm_ctx* c, int R, int prec, double* best_ms) {
   return autotune_impl<double>(c, R, best_ms);
 }
 
-int apply_op(tm_ctx* c, Op op, int prec, int R, const c128* x, c128* y) {
+static int apply_raw(tm_ctx* c, Op op, int prec, int R, const c128* x, c128* y) {
   if (prec == TM_PREC_MIXED) return apply_impl<float>(c, op, R, x, y);
   return apply_impl<double>(c, op, R, x, y);
+}
+
+int apply_op(tm_ctx* c, Op op, int prec, int R, const c128* x, c128* y) {
+  if (!c->t_dense || (op != Op::Forward && op != Op::Adjoint)) return apply_raw(c, op, prec, R, x, y);
+  // dense T: the coupling product, then the (cheap, FP64) per-scatterer block
+  const long long total = (long long)R * c->g.vec_len();
+  int rc;
+  if ((rc = ensure(c, c->ttmp, (size_t)2 * total * sizeof(c128))) != TM_OK) return rc;
+  c128* tmp = (c128*)c->ttmp.p;
+  if (op == Op::Forward) {  // y = x - T (A x)
+    if ((rc = apply_raw(c, Op::Coupling, prec, R, x, tmp)) != TM_OK) return rc;
+    return launch_tdense(c, R, 1, x, tmp, y);
+  }
+  // y = x - A^T (T^T x)
+  c128* tmp2 = tmp + total;
+  if ((rc = launch_tdense(c, R, 2, nullptr, x, tmp)) != TM_OK) return rc;
+  if ((rc = apply_raw(c, Op::CouplingT, prec, R, tmp, tmp2)) != TM_OK) return rc;
+  k_sub(c->stream, y, x, tmp2, total);
+  return TM_OK;
 }
 
 }  // namespace tmh

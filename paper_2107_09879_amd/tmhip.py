@@ -85,6 +85,7 @@ def load():
         "tm_get_lattice": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(D)]),
         "tm_set_spheres": (I, [P, P, D, D]),
         "tm_set_tmatrix_diag": (I, [P, P]),
+        "tm_set_tmatrix_dense": (I, [P, P]),
         "tm_get_tmatrix_diag": (I, [P, P, P]),
         "tm_plane_wave_rhs": (I, [P, I, P, P, P]),
         "tm_default_opts": (None, [ctypes.POINTER(SolveOpts)]),
@@ -204,6 +205,13 @@ class Context:
     def set_tmatrix_diag(self, t):
         t = _dev(t, torch.complex128, "t")
         self._check(self.lib.tm_set_tmatrix_diag(self.h, _ptr(t)))
+
+    def set_tmatrix_dense(self, T):
+        """T [N, L, L] complex128 on the device (row-major per scatterer)."""
+        T = _dev(T, torch.complex128, "T")
+        if tuple(T.shape) != (self.n, self.L, self.L):
+            raise ValueError(f"T must have shape {(self.n, self.L, self.L)}")
+        self._check(self.lib.tm_set_tmatrix_dense(self.h, _ptr(T)))
 
     def get_tmatrix_diag(self):
         t = torch.empty(self.n, self.L, dtype=torch.complex128, device=self.device)
