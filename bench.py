@@ -35,6 +35,58 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def kernel_name(variant, ctype):
+    """Name of the block-matvec kernel a variant launches (as the profiler
+    prints it, template arguments included)."""
+    if variant >= 8:
+        gx, bx, by = (4, 16, 4) if ctype == "float" else (2, 8, 4)
+        return f"block_matvec_lds_kernel<{ctype}, {gx}, {bx}, {by}, {variant - 7}>"
+    gauss, pref, occ = variant & 1, (variant >> 1) & 1, 4 if variant & 4 else 2
+    return f"block_matvec_kernel<{ctype}, {str(bool(gauss)).lower()}, {str(bool(pref)).lower()}, {occ}>"
+
+
+MATVEC_SOURCES = ("paper_2107_09879_amd/csrc/tm_matvec_lds.hip", "paper_2107_09879_amd/csrc/tm_matvec.hip")
+
+
+def kernel_source_digest():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in MATVEC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated against a plain copy), or
+    None when there is none for this kernel and workload or the matvec
+    sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "block_matvec_hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    digest = kernel_source_digest()
+    with open(path) as f:
+        for line in f:
+            cells = [c.strip() for c in line.strip().strip("|").split("|")]
+            if len(cells) >= 4 and cells[0] == kernel and cells[1] == workload and cells[2] == digest:
+                try:
+                    return float(cells[3])
+                except ValueError:
+                    return None
+    return None
+
+
+def copy_calibration(torch, mib=512):
+    """A plain copy of known size for the HBM counters: y = x * 1 over
+    `mib` MiB of float32 reads `mib` MiB and writes `mib` MiB."""
+    x = torch.ones(mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+    y = torch.mul(x, 1.0)
+    torch.cuda.synchronize()
+    del x, y
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,15 +146,30 @@ def main():
     for w in range(args.warmup):
         _, info, _ = step("mixed")
         log(f"[bench] warmup {w}: {info}")
+    copy_calibration(torch)
+    # timed region; the library records HIP events on its own stream around
+    # every block-matvec launch, which gives the kernel's average duration
+    ctx.profile_reset()
+    ctx.profile_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     infos = []
     for k in range(args.steps):
         s, info, F = step("mixed")
         infos.append(info)
+        log(f"[bench] step {k}: {info[0]}")
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
-    log(f"[bench] mixed time-to-solution {dt:.4f} s/step, info {infos[-1]}")
+    ctx.profile_enable(False)
+    live = {}
+    for which, prec, peak in ((1, "mixed", PEAK_FP32_MFMA), (0, "fp64", PEAK_FP64_MFMA)):
+        ms, launches, flops = ctx.profile_query(which)
+        if launches:
+            avg = ms / launches / 1e3
+            live[prec] = {"avg_launch_ms": avg * 1e3, "launches": launches, "flops_per_launch": flops,
+                          "tflops": flops / avg / 1e12, "frac": flops / avg / 1e12 / peak}
+    ctx.profile_reset()
+    log(f"[bench] mixed time-to-solution {dt:.4f} s/step, info {infos[-1]}, matvec {live}")
 
     fp64 = None
     if not args.no_fp64:
@@ -115,7 +182,7 @@ def main():
         d = (s - s64).abs().pow(2).sum().sqrt() / s64.abs().pow(2).sum().sqrt()
         fp64["mixed_vs_fp64_rel_diff"] = float(d)
 
-    # block-matvec throughput (HIP events on the library stream)
+    # block-matvec throughput in isolation (same kernels, back to back)
     rng = np.random.default_rng(0)
     x = torch.tensor(rng.normal(size=(len(kh), N, ctx.L)) + 1j * rng.normal(size=(len(kh), N, ctx.L)),
                      dtype=torch.complex128, device=dev)
@@ -139,7 +206,10 @@ def main():
     L = ctx.L
     D = (2 * n - 1) ** 2
     alg_bytes = D * (L * L // 2) * 8 + 2 * N * L * 8
-    gbs = alg_bytes / (mv["mixed"]["avg_launch_ms"] / 1e3) / 1e9
+    dom = live.get("mixed", mv["mixed"])
+    gbs = alg_bytes / (dom["avg_launch_ms"] / 1e3) / 1e9
+    variant = ctx.get_matvec_config("mixed")[0]
+    kname = kernel_name(variant, "float")
 
     cpu = None
     if not args.no_cpu_baseline and args.config == "c2":
@@ -159,18 +229,22 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64 matvec (fp32 accum) + f64 refinement",
+        "dtype": "c64+f64",
         "data": "synthetic",
         "config": {"workload": cfg["name"], "scatterers": N, "lmax": lmax, "unknowns": N * L,
                    "rhs": len(kh), "tol": tol, "restart": restart, "precision": "mixed"},
         "solve_info": infos[-1][0],
         "autotuned": tuned,
         "fp64_gmres": fp64,
-        "matvec": mv,
+        "matvec_timed_region": live,
+        "matvec_isolated": mv,
         "matvec_algorithmic_GBps": gbs,
-        "roofline": {"bound": "mfma", "achieved": mv["mixed"]["tflops"], "peak": PEAK_FP32_MFMA,
-                     "unit": "TFLOP/s", "frac": mv["mixed"]["frac"], "traffic": None,
-                     "kernel": "block_matvec_kernel<float>"},
+        "roofline": {"bound": "mfma", "achieved": dom["tflops"], "peak": PEAK_FP32_MFMA,
+                     "unit": "TFLOP/s", "frac": dom["tflops"] / PEAK_FP32_MFMA,
+                     "traffic": measured_traffic(kname, cfg["name"]),
+                     "kernel": kname, "avg_launch_ms": dom["avg_launch_ms"],
+                     "flops_per_launch": dom["flops_per_launch"],
+                     "kernel_source_digest": kernel_source_digest()},
         "cpu_baseline": cpu,
         **extra,
     }
