@@ -389,7 +389,7 @@ static void make_plan(const Geometry& g, int target_items, std::vector<MvItem>& 
   ibeg[tiles] = (int)items.size();
 }
 
-static int default_items(int R) { return std::max(1, (2048 + 2 * R - 1) / (2 * R)); }
+static int default_items(int R) { return std::max(1, (16384 + 2 * R - 1) / (2 * R)); }
 
 static int ensure_plan(tm_ctx* c, int R, int which) {
   const int target = c->mv_items[which] > 0 ? c->mv_items[which] : default_items(R);
@@ -500,7 +500,9 @@ static int autotune_impl(tm_ctx* c, int R, double* best_ms) {
   int rc;
   if ((rc = ensure(c, c->xlow, (size_t)total * sizeof(cplx<T>))) != TM_OK) return rc;
   TM_HIP(c, hipMemsetAsync(c->xlow.p, 0, (size_t)total * sizeof(cplx<T>), c->stream));
-  const int wg_targets[] = {1024, 2048, 3072, 4096, 6144, 8192};
+  // workgroup counts (items x 2R); smaller equal-work items keep every CU
+  // busy to the end of the launch, at the price of more partial sums
+  const int wg_targets[] = {2048, 4096, 8192, 16384, 32768};
   hipEvent_t e0, e1;
   TM_HIP(c, hipEventCreate(&e0));
   TM_HIP(c, hipEventCreate(&e1));
@@ -512,7 +514,7 @@ static int autotune_impl(tm_ctx* c, int R, double* best_ms) {
       c->mv_items[which] = std::max(1, wt / (2 * R));
       if (v >= LDS_VARIANT) {
         double tmin = 1e300;
-        for (int rep = 0; rep < 3; ++rep) {
+        for (int rep = 0; rep < 4; ++rep) {
           rc = lds_apply<T>(c, which, R, std::is_same<T, double>::value ? c->tab64.p : c->tab32.p,
                             c->xlow.p, nullptr, nullptr, 0, c->mv_items[which], e0, e1,
                             v - LDS_VARIANT + 1);
@@ -547,7 +549,7 @@ static int autotune_impl(tm_ctx* c, int R, double* best_ms) {
       a.R = R;
       a.n_sites = g.n;
       double tmin = 1e300;
-      for (int rep = 0; rep < 3; ++rep) {
+      for (int rep = 0; rep < 4; ++rep) {
         TM_HIP(c, hipEventRecord(e0, c->stream));
         hipLaunchKernelGGL(mv_kernel<T>(v), dim3(nitems, 2 * R), dim3(256), 0, c->stream, a);
         TM_HIP(c, hipEventRecord(e1, c->stream));

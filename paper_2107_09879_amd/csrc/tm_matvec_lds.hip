@@ -131,12 +131,15 @@ __global__ __launch_bounds__(256, 2) void block_matvec_lds_kernel(LdsArgs a) {
   constexpr int TW = Cfg::TW, WX = Cfg::WX, WY = Cfg::WY, CH = Cfg::CH;
   __shared__ float4 win[Cfg::CHUNKS];
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  // wave-uniform by construction; readfirstlane lets the compiler keep the
+  // per-wave bounds below in scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int jt = lane & 15;
   const int kq = lane >> 4;
   const int lx = jt & 3, ly = jt >> 2;
   if (a.done && *a.done) return;
-  const LdsItem it = a.items[blockIdx.x];
+  const int item = blockIdx.x;
+  const LdsItem it = a.items[item];
   const int rc = blockIdx.y;
   const int r = rc >> 1, c = rc & 1;
   int nx = a.nx, ny = a.ny, tiles_x = a.tiles_x;
@@ -197,76 +200,95 @@ __global__ __launch_bounds__(256, 2) void block_matvec_lds_kernel(LdsArgs a) {
     if (dyb > dye || dxb > dxe) continue;
     const int ndx = dxe - dxb + 1;
     const int nq = (dye - dyb + 1) * ndx;
-    // operand pipeline: A (the translation block, from global memory) is
-    // fetched PF displacements ahead -- table rows mostly miss L2, so the
-    // latency is that of HBM/MALL; B (all groups, from LDS) one ahead
-    T ar[PF + 1][4], ai[PF + 1][4];
-    T br[GX][4], bi[GX][4], nbr[GX][4], nbi[GX][4];
-    auto blk_of = [&](int q) {
-      const int dx = dxb + q % ndx, dy = dyb + q / ndx;
-      return tab + (((size_t)(dy + a.tny - 1) * wxt + (dx + a.tnx - 1)) * NCLASS + c) * (SLOTS * SLOTS);
+    // Operand pipeline, unrolled by U = PF + 1 so that every stage owns its
+    // registers (no copies between stages, and each wait covers exactly the
+    // load that stage consumes): the translation block of step q is fetched
+    // PF steps ahead (table rows mostly miss L2, so the latency is that of
+    // MALL/HBM) into set q % U, the B operands of all groups one step ahead
+    // from LDS into set q % U.  Positions advance row-major over the block's
+    // valid [dxb, dxe] x [dyb, dye].
+    constexpr int U = PF + 1;
+    T ar[U][4], ai[U][4];
+    T br[U][GX][4], bi[U][GX][4];
+    auto advance = [&](int& x, int& y) {
+      if (++x > dxe) {
+        x = dxb;
+        ++y;
+      }
     };
-    auto read_all_b = [&](int dx, int dy, T (*r_)[4], T (*i_)[4]) {
-      const int wy = (ty - Y0) - (dy - by0) + BY - 1;
+    auto table_block = [&](int x, int y) {
+      return tab + (((size_t)(y + a.tny - 1) * wxt + (x + a.tnx - 1)) * NCLASS + c) * (SLOTS * SLOTS);
+    };
+    auto read_all_b = [&](int x, int y, T (*r_)[4], T (*i_)[4]) {
+      const int wy = (ty - Y0) - (y - by0) + BY - 1;
 #pragma unroll
       for (int g = 0; g < GX; ++g) {
-        const int wx = 4 * g + lx - (dx - bx0) + BX - 1;
+        const int wx = 4 * g + lx - (x - bx0) + BX - 1;
         read_b(win, (wy * WX + wx) * CH, wx, wy, kq, r_[g], i_[g]);
       }
     };
+    // The fetch positions stop at the block's last displacement, so fetches
+    // past the end re-read valid data: every fetch is unconditional and the
+    // compiler waits for exactly the operands a step consumes.
+    auto advance_fetch = [&](int& x, int& y) {
+      if (x != dxe || y != dye) advance(x, y);
+    };
+    int adx = dxb, ady = dyb, bdx = dxb, bdy = dyb, cdx = dxb, cdy = dyb;
 #pragma unroll
-    for (int p = 0; p < PF; ++p)
-      if (p < nq) load_a(blk_of(p), jt, kq, ar[p], ai[p]);
-    read_all_b(dxb, dyb, br, bi);
-    int dx = dxb, dy = dyb;
-    for (int q = 0; q < nq; ++q) {
-      int ndxv = dx + 1, ndyv = dy;
-      if (ndxv > dxe) {
-        ndxv = dxb;
-        ++ndyv;
-      }
-      const bool more = q + 1 < nq;
-      if (q + PF < nq) load_a(blk_of(q + PF), jt, kq, ar[PF], ai[PF]);
-      if (more) read_all_b(ndxv, ndyv, nbr, nbi);
+    for (int p = 0; p < PF; ++p) {
+      load_a(table_block(adx, ady), jt, kq, ar[p], ai[p]);
+      advance_fetch(adx, ady);
+    }
+    read_all_b(bdx, bdy, br[0], bi[0]);
+    advance_fetch(bdx, bdy);
+    // step q of the block, with q % U == K known at compile time
+    auto step = [&](auto kc, int q) {
+      constexpr int K = decltype(kc)::value;
+      load_a(table_block(adx, ady), jt, kq, ar[(K + PF) % U], ai[(K + PF) % U]);
+      advance_fetch(adx, ady);
+      read_all_b(bdx, bdy, br[(K + 1) % U], bi[(K + 1) % U]);
+      advance_fetch(bdx, bdy);
       T ms[4];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) ms[s] = ar[0][s] + ai[0][s];
+      for (int s = 0; s < 4; ++s) ms[s] = ar[K][s] + ai[K][s];
 #pragma unroll
       for (int g = 0; g < GX; ++g) {
         const int gx0 = X0 + 4 * g;
-        if (gx0 >= nx || gx0 + 3 - dx < 0 || gx0 - dx >= nx) continue;  // wave-uniform
+        if (gx0 >= nx || gx0 + 3 - cdx < 0 || gx0 - cdx >= nx) continue;  // wave-uniform
         T xs[4];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) xs[s] = br[g][s] + bi[g][s];
+        for (int s = 0; s < 4; ++s) xs[s] = br[K][g][s] + bi[K][g][s];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-          t1[g] = L::mma(ar[0][s], br[g][s], t1[g]);
-          t2[g] = L::mma(ai[0][s], bi[g][s], t2[g]);
+          t1[g] = L::mma(ar[K][s], br[K][g][s], t1[g]);
+          t2[g] = L::mma(ai[K][s], bi[K][g][s], t2[g]);
           t3[g] = L::mma(ms[s], xs[s], t3[g]);
         }
       }
-#pragma unroll
-      for (int p = 0; p < PF; ++p)
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          ar[p][s] = ar[p + 1][s];
-          ai[p][s] = ai[p + 1][s];
-        }
-      if (more) {
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
-#pragma unroll
-          for (int g = 0; g < GX; ++g) {
-            br[g][s] = nbr[g][s];
-            bi[g][s] = nbi[g][s];
-          }
-      }
-      dx = ndxv;
-      dy = ndyv;
+      advance(cdx, cdy);
+    };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using I3 = std::integral_constant<int, 3>;
+    int q = 0;
+    for (; q + U <= nq; q += U) {
+      step(I0{}, q);
+      step(I1{}, q + 1);
+      if constexpr (U > 2) step(I2{}, q + 2);
+      if constexpr (U > 3) step(I3{}, q + 3);
+    }
+    // tail: fewer than U steps, same register sets
+    if (q < nq) step(I0{}, q);
+    if constexpr (U > 2) {
+      if (q + 1 < nq) step(I1{}, q + 1);
+    }
+    if constexpr (U > 3) {
+      if (q + 2 < nq) step(I2{}, q + 2);
     }
   }
   // this item's partial sums for every valid target of the tile
-  C* out = reinterpret_cast<C*>(a.partial) + ((size_t)blockIdx.x * (2 * a.R) + rc) * (TW * 16 * SLOTS);
+  C* out = reinterpret_cast<C*>(a.partial) + ((size_t)item * (2 * a.R) + rc) * (TW * 16 * SLOTS);
   if (ty < ny) {
 #pragma unroll
     for (int g = 0; g < GX; ++g) {
@@ -360,6 +382,7 @@ static void lds_plan(const Geometry& g, int TW, int BX, int BY, int win_cost, in
   ibeg.push_back((int)items.size());
 }
 
+
 // y = x - t * z (Forward) etc., z = sum of the partials of the items covering
 // the site's tile, added in item order.
 template <typename T>
@@ -417,11 +440,18 @@ static void lds_launch_pf(hipStream_t st, int nitems, int R, const LdsArgs& a) {
   hipLaunchKernelGGL((block_matvec_lds_kernel<T, Ch::GX, Ch::BX, Ch::BY, PF>), dim3(nitems, 2 * R),
                      dim3(256), 0, st, a);
 }
+// FP64 stages are twice as wide: depth 3 does not fit two waves' registers,
+// so FP64 runs depth 2 for variant 10
 template <typename T>
 static void lds_launch_any(hipStream_t st, int pf, int nitems, int R, const LdsArgs& a) {
-  if (pf <= 1) lds_launch_pf<T, 1>(st, nitems, R, a);
-  else if (pf == 2) lds_launch_pf<T, 2>(st, nitems, R, a);
-  else lds_launch_pf<T, 3>(st, nitems, R, a);
+  if (pf <= 1) {
+    lds_launch_pf<T, 1>(st, nitems, R, a);
+  } else if constexpr (std::is_same<T, double>::value) {
+    lds_launch_pf<T, 2>(st, nitems, R, a);
+  } else {
+    if (pf == 2) lds_launch_pf<T, 2>(st, nitems, R, a);
+    else lds_launch_pf<T, 3>(st, nitems, R, a);
+  }
 }
 
 template <typename T>
