@@ -98,6 +98,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--subregions", type=int, default=0, help="c3: use only the first K subregions")
+    ap.add_argument("--matvec-config", action="append", default=[], metavar="PREC:VARIANT:ITEMS",
+                    help="fix the block-matvec kernel of a precision (mixed or fp64) instead of "
+                         "autotuning it, e.g. mixed:9:16384")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -129,8 +132,16 @@ def main():
     # set-up outside the timed region: kernel variant / work split per precision
     ctx.set_geometry(pos, wl.K, lmax)
     tuned = {}
-    if not args.no_autotune:
-        for prec in ("mixed", "fp64"):
+    fixed = {}
+    for spec in args.matvec_config:
+        prec, v, items = spec.split(":")
+        fixed[prec] = (int(v), int(items))
+    for prec in ("mixed", "fp64"):
+        if prec in fixed:
+            ctx.set_matvec_config(prec, *fixed[prec])
+            tuned[prec] = {"variant": fixed[prec][0], "items": fixed[prec][1], "fixed": True}
+            log(f"[bench] {prec} matvec fixed: variant {fixed[prec][0]}, items {fixed[prec][1]}")
+        elif not args.no_autotune:
             ms, conf = ctx.autotune(len(kh), prec)
             tuned[prec] = {"block_matvec_ms": ms, "variant": conf[0], "items": conf[1]}
             log(f"[bench] autotune {prec}: {ms:.3f} ms, variant {conf[0]}, items {conf[1]}")
