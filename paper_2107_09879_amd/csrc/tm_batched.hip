@@ -170,28 +170,51 @@ __global__ void b_combine(const cplx<T>* __restrict__ partial, const int* __rest
   y[e] = c128{xv.re - (tv.re * sr - tv.im * si), xv.im - (tv.re * si + tv.im * sr)};
 }
 
-// partial[blk][k] = sum over the block's segment of conj(V_k) w
+// partial[blk][k] = sum over the block's segment of conj(V_k) w, the
+// vectors taken BKC at a time (one LDS reduction per chunk)
+constexpr int BKC = 8;
 __global__ __launch_bounds__(BT) void b_multidot(const c128* __restrict__ V, long long stride,
                                                  int nvec, const c128* __restrict__ w,
                                                  const SegBlock* __restrict__ blocks,
                                                  c128* __restrict__ partial, int ldp,
                                                  const int* __restrict__ active,
                                                  const int* __restrict__ done) {
-  __shared__ double sh[BT / 64];
+  __shared__ double sh[BT / 64][2 * BKC];
   if (done && *done) return;
   const SegBlock bk = blocks[blockIdx.x];
   if (active && !active[bk.sys]) return;
-  for (int k = 0; k < nvec; ++k) {
-    const c128* vk = V + (size_t)k * stride;
-    double sr = 0.0, si = 0.0;
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+  for (int k0 = 0; k0 < nvec; k0 += BKC) {
+    double sr[BKC], si[BKC];
+#pragma unroll
+    for (int i = 0; i < BKC; ++i) sr[i] = si[i] = 0.0;
+    const int nk = min(BKC, nvec - k0);
     for (long long e = bk.lo + threadIdx.x; e < bk.hi; e += BT) {
-      const c128 a = vk[e], b = w[e];
-      sr += a.re * b.re + a.im * b.im;
-      si += a.re * b.im - a.im * b.re;
+      const c128 b = w[e];
+#pragma unroll
+      for (int i = 0; i < BKC; ++i) {
+        if (i < nk) {
+          const c128 a = V[(size_t)(k0 + i) * stride + e];
+          sr[i] += a.re * b.re + a.im * b.im;
+          si[i] += a.re * b.im - a.im * b.re;
+        }
+      }
     }
-    sr = bblock_sum(sr, sh);
-    si = bblock_sum(si, sh);
-    if (threadIdx.x == 0) partial[(size_t)blockIdx.x * ldp + k] = c128{sr, si};
+#pragma unroll
+    for (int i = 0; i < BKC; ++i) {
+      const double r = bwarp_sum(sr[i]), m = bwarp_sum(si[i]);
+      if (ln == 0) {
+        sh[wv][2 * i] = r;
+        sh[wv][2 * i + 1] = m;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * nk) {
+      double s = 0.0;
+      for (int q = 0; q < BT / 64; ++q) s += sh[q][threadIdx.x];
+      reinterpret_cast<double*>(partial + (size_t)blockIdx.x * ldp + k0)[threadIdx.x] = s;
+    }
+    __syncthreads();
   }
 }
 

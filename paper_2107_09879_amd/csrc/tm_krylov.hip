@@ -10,8 +10,8 @@ namespace tmh {
 constexpr int KB = 256;  // threads per block for vector kernels
 
 int krylov_blocks(long long len) {
-  long long b = (len + 4 * KB - 1) / (4 * KB);
-  if (b > 1024) b = 1024;
+  long long b = (len + KB - 1) / KB;
+  if (b > 2048) b = 2048;
   if (b < 1) b = 1;
   return (int)b;
 }
@@ -36,24 +36,51 @@ __device__ inline double block_sum(double v, double* sh) {
 }
 
 // partial[blk][k] = sum over the block's element range of conj(V_k[e]) w[e]
+// partial[blk][k] = sum over the block's segment of conj(V_k) w.  The
+// vectors are taken KC at a time: each thread keeps KC complex sums, loads
+// its w elements once per chunk, and the block reduces the 2*KC sums with one
+// LDS pass (a tall-skinny V^H w, bound by reading V).
+constexpr int KC = 8;
 __global__ __launch_bounds__(KB) void multidot_kernel(const c128* __restrict__ V, long long stride,
                                                       int nvec, const c128* __restrict__ w,
                                                       long long len, c128* __restrict__ partial) {
-  __shared__ double sh[KB / 64];
+  __shared__ double sh[KB / 64][2 * KC];
   const long long per = (len + gridDim.x - 1) / gridDim.x;
   const long long lo = (long long)blockIdx.x * per;
   const long long hi = min(len, lo + per);
-  for (int k = 0; k < nvec; ++k) {
-    const c128* vk = V + (size_t)k * stride;
-    double sr = 0.0, si = 0.0;
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+  for (int k0 = 0; k0 < nvec; k0 += KC) {
+    double sr[KC], si[KC];
+#pragma unroll
+    for (int i = 0; i < KC; ++i) sr[i] = si[i] = 0.0;
+    const int nk = min(KC, nvec - k0);
     for (long long e = lo + threadIdx.x; e < hi; e += blockDim.x) {
-      const c128 a = vk[e], b = w[e];
-      sr += a.re * b.re + a.im * b.im;
-      si += a.re * b.im - a.im * b.re;
+      const c128 b = w[e];
+#pragma unroll
+      for (int i = 0; i < KC; ++i) {
+        if (i < nk) {
+          const c128 a = V[(size_t)(k0 + i) * stride + e];
+          sr[i] += a.re * b.re + a.im * b.im;
+          si[i] += a.re * b.im - a.im * b.re;
+        }
+      }
     }
-    sr = block_sum(sr, sh);
-    si = block_sum(si, sh);
-    if (threadIdx.x == 0) partial[(size_t)blockIdx.x * nvec + k] = c128{sr, si};
+#pragma unroll
+    for (int i = 0; i < KC; ++i) {
+      const double r = warp_sum(sr[i]), m = warp_sum(si[i]);
+      if (ln == 0) {
+        sh[wv][2 * i] = r;
+        sh[wv][2 * i + 1] = m;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * nk) {
+      double s = 0.0;
+      for (int q = 0; q < (int)(blockDim.x >> 6); ++q) s += sh[q][threadIdx.x];
+      double* out = reinterpret_cast<double*>(partial + (size_t)blockIdx.x * nvec + k0);
+      out[threadIdx.x] = s;
+    }
+    __syncthreads();
   }
 }
 
