@@ -40,7 +40,10 @@ def kernel_name(variant, ctype):
     prints it, template arguments included)."""
     if variant >= 8:
         gx, bx, by = (4, 16, 4) if ctype == "float" else (2, 8, 4)
-        return f"block_matvec_lds_kernel<{ctype}, {gx}, {bx}, {by}, {variant - 7}>"
+        pf = variant - 7 if ctype == "float" else min(variant - 7, 2)
+        # regular tiles; rows beyond the last multiple of 16 run a second,
+        # "true" (wide-tile) instance of the same kernel
+        return f"block_matvec_lds_kernel<{ctype}, {gx}, {bx}, {by}, {pf}, false>"
     gauss, pref, occ = variant & 1, (variant >> 1) & 1, 4 if variant & 4 else 2
     return f"block_matvec_kernel<{ctype}, {str(bool(gauss)).lower()}, {str(bool(pref)).lower()}, {occ}>"
 
@@ -98,19 +101,22 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--subregions", type=int, default=0, help="c3: use only the first K subregions")
+    ap.add_argument("--tile-iters", type=int, default=300,
+                    help="c5: Arnoldi steps of the bounded solve used for the extrapolation")
     ap.add_argument("--matvec-config", action="append", default=[], metavar="PREC:VARIANT:ITEMS",
                     help="fix the block-matvec kernel of a precision (mixed or fp64) instead of "
                          "autotuning it, e.g. mixed:9:16384")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(subregions shard independently; see the design notes). Use --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only; there is no multi-GPU path. Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     if args.config == "c3":
         return bench_batched(args)
     if args.config == "c4":
         return bench_adjoint(args)
+    if args.config == "c5":
+        return bench_tile(args)
 
     import torch
 
@@ -226,8 +232,6 @@ def main():
     if not args.no_cpu_baseline and args.config == "c2":
         cpu = cpu_baseline(pos, radii, kh, po, cfg, infos[-1][0])
     extra = {}
-    if args.config == "c5":
-        extra["near_field"] = near_field_plane(ctx, s, cfg)
 
     out = {
         "metric": "time-to-solution at 1e-8 residual + translation-matvec GB/s, 1e4-1e5 scatterers",
@@ -263,6 +267,96 @@ def main():
     ctx.close()
 
 
+def bench_tile(args):
+    """300 x 300 lens tile (9e4 spheres, lmax 3, 2 RHS): translation-table
+    build, block-matvec throughput in both precisions, a bounded
+    mixed-precision solve (its residual history gives an extrapolated
+    time-to-solution, labelled as such), and the scattered field on a
+    1000 x 1000 plane 5 wavelengths above the lattice."""
+    import torch
+
+    import workloads as wl
+    from paper_2107_09879_amd import tmhip
+
+    pos, radii, kh, po, cfg = wl.config_inputs("c5")
+    n, lmax, R = cfg["nx"], cfg["lmax"], len(kh)
+    N = n * n
+    ctx = tmhip.Context(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.set_geometry(pos, wl.K, lmax)
+    torch.cuda.synchronize()
+    t_table = time.perf_counter() - t0
+    ctx.set_spheres(torch.tensor(radii, dtype=torch.float64, device="cuda"), wl.N_REL)
+    log(f"[bench] tile: N={N}, table build {t_table:.2f} s")
+    fixed = {"mixed": (9, 32768 // (2 * R)), "fp64": (8, 16384 // (2 * R))}
+    for spec in args.matvec_config:
+        prec, v, items = spec.split(":")
+        fixed[prec] = (int(v), int(items))
+    rng = np.random.default_rng(0)
+    x = torch.tensor(rng.normal(size=(R, N, ctx.L)) + 1j * rng.normal(size=(R, N, ctx.L)),
+                     dtype=torch.complex128, device="cuda")
+    mv = {}
+    for which, prec, peak in ((1, "mixed", PEAK_FP32_MFMA), (0, "fp64", PEAK_FP64_MFMA)):
+        ctx.set_matvec_config(prec, *fixed[prec])
+        ctx.apply_operator(x, "forward", prec)
+        ctx.profile_reset()
+        ctx.profile_enable(True)
+        for _ in range(3):
+            ctx.apply_operator(x, "forward", prec)
+        ctx.profile_enable(False)
+        ms, launches, flops = ctx.profile_query(which)
+        avg = ms / launches / 1e3
+        mv[prec] = {"variant": fixed[prec][0], "items": fixed[prec][1], "avg_launch_ms": avg * 1e3,
+                    "tflops": flops / avg / 1e12, "frac": flops / avg / 1e12 / peak, "rhs": R}
+        log(f"[bench] tile {prec} block matvec ({R} RHS): {avg*1e3:.1f} ms, {flops/avg/1e12:.2f} TFLOP/s")
+    ctx.profile_reset()
+    del x
+    hist = []
+    t_start = [None]
+
+    def progress(cycles, iters, n_live, worst):
+        hist.append((time.perf_counter() - t_start[0], iters, worst))
+        log(f"[bench] tile solve: cycle {cycles}, iters {iters}, residual {worst:.3e}")
+
+    ctx.set_progress(progress)
+    a0 = ctx.plane_wave_rhs(kh, po)
+    torch.cuda.synchronize()
+    t_start[0] = time.perf_counter()
+    s, info = ctx.solve(a0, tol=cfg["tol"], restart=cfg["restart"], precision="mixed",
+                        max_iter=args.tile_iters)
+    torch.cuda.synchronize()
+    t_solve = time.perf_counter() - t_start[0]
+    ctx.set_progress(None)
+    # residual decade rate over the second half of the bounded run (per RHS the
+    # history restarts; use the last RHS's records)
+    last = [h for h in hist if h[1] > 0][-max(2, len(hist) // 4):]
+    extrap = None
+    if len(last) >= 2 and last[-1][2] < last[0][2]:
+        its = last[-1][1] - last[0][1]
+        decades = np.log10(last[0][2] / last[-1][2])
+        remaining = max(0.0, np.log10(last[-1][2] / cfg["tol"]))
+        it_total = info[-1]["iters"] + remaining / decades * its
+        sec_per_iter = t_solve / max(1, sum(i["iters"] for i in info))
+        extrap = {"iters_per_rhs_est": it_total, "time_to_solution_s_est": it_total * sec_per_iter * R,
+                  "sec_per_iteration": sec_per_iter, "basis": "extrapolated from the bounded run"}
+    log(f"[bench] tile bounded solve {t_solve:.1f} s, info {info}, extrapolation {extrap}")
+    nf = near_field_plane(ctx, s, cfg)
+    out = {"metric": "time-to-solution at 1e-8 residual + translation-matvec GB/s, 1e4-1e5 scatterers",
+           "value": mv["mixed"]["avg_launch_ms"], "unit": "ms per c64 block matvec (2 RHS)",
+           "n_gpus": 1, "steps": 3, "warmup": 1, "ms_per_step": mv["mixed"]["avg_launch_ms"],
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "c64+f64",
+           "data": "synthetic", "config": {"workload": cfg["name"], "scatterers": N, "lmax": lmax, "rhs": R},
+           "table_build_s": t_table, "matvec": mv,
+           "bounded_solve": {"max_iter": args.tile_iters, "time_s": t_solve, "info": info},
+           "time_to_solution_extrapolated": extrap, "near_field": nf,
+           "roofline": {"bound": "mfma", "achieved": mv["mixed"]["tflops"], "peak": PEAK_FP32_MFMA,
+                        "unit": "TFLOP/s", "frac": mv["mixed"]["frac"], "traffic": None,
+                        "kernel": kernel_name(fixed["mixed"][0], "float")}}
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
 def near_field_plane(ctx, s, cfg):
     """Scattered field on the n x n plane of the workload (FP32 basis, FP64
     phase reduction), timed with HIP events around the readout call."""
@@ -286,8 +380,11 @@ def near_field_plane(ctx, s, cfg):
 
 
 def bench_batched(args):
-    """48 overlapping square subregions (side 20-80 plus a 10-site buffer) of
-    a 300 x 300 lens layout, 4 right-hand sides each, solved as one batch."""
+    """Overlapping square subregions (side 20-80 plus a 10-site buffer) of a
+    300 x 300 lens layout, 4 right-hand sides each, solved as one batch
+    (restart cycles replayed from a hipGraph) and, for comparison, one
+    subregion at a time with the single-system solver (tables built outside
+    the timed region).  --subregions K keeps the first K of the 48."""
     import torch
 
     import workloads as wl
@@ -298,15 +395,26 @@ def bench_batched(args):
     subs = [(ox, oy, sd, sd) for ox, oy, sd in wl.subregions(seed=cfg["seed"])]
     if args.subregions:
         subs = subs[:args.subregions]
+    R = len(kh)
+    max_iter = 20000
+
+    def progress(tag):
+        def fn(cycles, iters, n_live, worst):
+            if cycles % 10 == 0:
+                log(f"[bench] {tag}: cycle {cycles}, iters {iters}, live {n_live}, max residual {worst:.2e}")
+        return fn
+
     ctx = tmhip.Context(0)
     ctx.set_geometry(pos, wl.K, cfg["lmax"])
     ctx.set_spheres(torch.tensor(radii, dtype=torch.float64, device="cuda"), wl.N_REL)
     res = {}
-    for prec in (["mixed"] if args.no_fp64 else ["mixed", "fp64"]):
+    precs = ["mixed"] if args.no_fp64 else ["mixed", "fp64"]
+    for prec in precs:
+        ctx.set_progress(progress(f"batched {prec}"))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         sb, info = ctx.solve_batched(subs, kh, po, use_graph=True, tol=cfg["tol"],
-                                     restart=cfg["restart"], precision=prec, max_iter=4000)
+                                     restart=cfg["restart"], precision=prec, max_iter=max_iter)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         flat = [i for row in info for i in row]
@@ -316,16 +424,42 @@ def bench_batched(args):
                      "converged": sum(i["status"] == 0 for i in flat), "systems": len(flat),
                      "max_rel_residual": max(i["rel_residual"] for i in flat)}
         log(f"[bench] batched {prec}: {dt:.2f} s {res[prec]}")
+    ctx.set_progress(None)
+    ctx.close()
+    # the same systems one subregion at a time (R right-hand sides per solve)
+    seq = {"time_s": 0.0, "table_build_s": 0.0, "iters_max": 0}
+    for k, (ox, oy, sx, sy) in enumerate(subs):
+        ix, iy = np.meshgrid(np.arange(ox, ox + sx), np.arange(oy, oy + sy))
+        idx = (iy * cfg["nx"] + ix).ravel()
+        one = tmhip.Context(0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        one.set_geometry(pos[idx], wl.K, cfg["lmax"])
+        torch.cuda.synchronize()
+        seq["table_build_s"] += time.perf_counter() - t0
+        one.set_spheres(torch.tensor(radii[idx], dtype=torch.float64, device="cuda"), wl.N_REL)
+        one.set_progress(progress(f"subregion {k}"))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        a0 = one.plane_wave_rhs(kh, po)
+        _, info = one.solve(a0, tol=cfg["tol"], restart=cfg["restart"], precision="mixed",
+                            max_iter=max_iter)
+        torch.cuda.synchronize()
+        seq["time_s"] += time.perf_counter() - t0
+        seq["iters_max"] = max(seq["iters_max"], max(i["iters"] for i in info))
+        log(f"[bench] subregion {k} ({sx}x{sy}) alone: {time.perf_counter() - t0:.2f} s, "
+            f"iters {[i['iters'] for i in info]}")
+        one.close()
     sites = sum(q[2] * q[3] for q in subs)
     out = {"metric": "time-to-solution at 1e-8 residual + translation-matvec GB/s, 1e4-1e5 scatterers",
            "value": res["mixed"]["time_s"], "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0,
            "ms_per_step": res["mixed"]["time_s"] * 1e3, "higher_is_better": False, "scaling": "weak",
-           "vs_baseline": None, "dtype": "c64 matvec (fp32 accum) + f64 refinement", "data": "synthetic",
+           "vs_baseline": None, "dtype": "c64+f64", "data": "synthetic",
            "config": {"workload": cfg["name"], "subregions": len(subs), "sites": sites,
-                      "rhs": len(kh), "systems": len(subs) * len(kh)},
-           "batched": res}
+                      "rhs": R, "systems": len(subs) * R},
+           "batched": res, "sequential_mixed": seq,
+           "batched_speedup_vs_sequential": seq["time_s"] / res["mixed"]["time_s"]}
     print(json.dumps(out), flush=True)
-    ctx.close()
 
 
 def bench_adjoint(args):
@@ -341,12 +475,22 @@ def bench_adjoint(args):
     xd = np.array(cfg["detector"])
     ctx = tmhip.Context(0)
     ctx.set_geometry(pos, wl.K, cfg["lmax"])
+    for prec in ("mixed", "fp64"):
+        ms, conf = ctx.autotune(1, prec)
+        log(f"[bench] autotune {prec}: {ms:.3f} ms, variant {conf[0]}, items {conf[1]}")
     rd = torch.tensor(radii, dtype=torch.float64, device="cuda")
+    tag = {"name": "forward"}
+
+    def progress(cycles, iters, n_live, worst):
+        if cycles % 10 == 0:
+            log(f"[bench] {tag['name']}: cycle {cycles}, iters {iters}, residual {worst:.2e}")
+
+    ctx.set_progress(progress)
 
     def objective(r_dev, tol, x0=None):
         ctx.set_spheres(r_dev, wl.N_REL)
         a0 = ctx.plane_wave_rhs(kh, po)
-        s, info = ctx.solve(a0, x0=x0, tol=tol, precision="fp64", max_iter=6000)
+        s, info = ctx.solve(a0, x0=x0, tol=tol, precision="mixed", max_iter=20000)
         z = np.array([torch.sum(ctx.detector_vector(xd, np.eye(3)[c]) * s[0]).item() for c in range(3)])
         Et = po[0] * np.exp(1j * wl.K * kh[0] @ xd) + z
         return float(np.sum(np.abs(Et) ** 2)), s, a0, Et, info
@@ -355,7 +499,8 @@ def bench_adjoint(args):
     t0 = time.perf_counter()
     O, s, a0, Et, info_f = objective(rd, 1e-12)
     w = ctx.detector_vector(xd, np.conj(Et))
-    mu, info_a = ctx.adjoint_solve(w[None].contiguous(), tol=1e-12, precision="fp64", max_iter=6000)
+    tag["name"] = "adjoint"
+    mu, info_a = ctx.adjoint_solve(w[None].contiguous(), tol=1e-12, precision="mixed", max_iter=20000)
     g = ctx.grad_radius(mu, s, a0)[0].cpu().numpy()
     torch.cuda.synchronize()
     t_grad = time.perf_counter() - t0
@@ -368,6 +513,7 @@ def bench_adjoint(args):
         for sg in (1, -1):
             r2 = rd.clone()
             r2[i] += sg * h
+            tag["name"] = f"FD radius {i} {'+' if sg > 0 else '-'}"
             vals.append(objective(r2, 1e-13, x0=s)[0])
         fd.append((vals[0] - vals[1]) / (2 * h))
         log(f"[bench] FD radius {i}: adjoint {g[i]:.8e} fd {fd[-1]:.8e}")
@@ -375,8 +521,9 @@ def bench_adjoint(args):
     err = float(np.max(np.abs(fd - g[idx])) / np.max(np.abs(g)))
     out = {"metric": "time-to-solution at 1e-8 residual + translation-matvec GB/s, 1e4-1e5 scatterers",
            "value": t_grad, "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": t_grad * 1e3,
-           "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-           "data": "synthetic", "config": {"workload": cfg["name"], "scatterers": len(radii)},
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "c64+f64",
+           "data": "synthetic", "config": {"workload": cfg["name"], "scatterers": len(radii),
+                                           "solves": "mixed precision, FP64 true residual 1e-12"},
            "objective": O, "forward": info_f[0], "adjoint": info_a[0],
            "fd_check": {"indices": idx.tolist(), "step": h, "max_err_rel_to_max_grad": err}}
     print(json.dumps(out), flush=True)

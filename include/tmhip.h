@@ -272,6 +272,18 @@ int tm_get_matvec_config(tm_ctx* ctx, int precision, int* variant, int* items);
  * best_ms (host, nullable) receives the best block-matvec time. */
 int tm_autotune(tm_ctx* ctx, int n_rhs, int precision, double* best_ms);
 
+/* ---- progress ------------------------------------------------------------- */
+
+/* Called on the calling thread after every restart cycle of tm_solve,
+ * tm_adjoint_solve (per right-hand side) and tm_solve_batched:
+ * cycles = restart cycles so far, iters = Arnoldi steps so far (the largest
+ * over the batch's systems), n_live = systems still iterating (1 for a single
+ * solve), max_rel_residual = largest true relative residual among them at
+ * the start of the cycle.  The callback must not call back into the same
+ * context.  fn = NULL removes it. */
+typedef void (*tm_progress_fn)(void* user, int cycles, int iters, int n_live, double max_rel_residual);
+int tm_set_progress(tm_ctx* ctx, tm_progress_fn fn, void* user);
+
 /* ---- profiling ------------------------------------------------------------ */
 
 /* When enabled, the block-matvec launches are bracketed by HIP events on the

@@ -144,6 +144,7 @@ static int gmres(tm_ctx* c, Op op, const c128* b, c128* x, const tm_solve_opts& 
     relres = beta / bnorm;
     if (!std::isfinite(beta)) return set_err(c, TM_ERR_NAN, "residual became non-finite");
     if (relres <= o.tol || it >= o.max_iter) break;
+    if (c->progress) c->progress(c->progress_user, info.cycles, it, 1, relres);
     info.cycles++;
     k_scale(st, G.V, G.r, 1.0 / beta, len);
     std::fill(gv.begin(), gv.end(), 0.0);
@@ -643,6 +644,13 @@ int tm_autotune(tm_ctx* c, int n_rhs, int precision, double* best_ms) {
   if (n_rhs < 1 || (precision != TM_PREC_FP64 && precision != TM_PREC_MIXED))
     return tmh::set_err(c, TM_ERR_INVALID_ARG, "bad arguments");
   return tmh::autotune(c, n_rhs, precision, best_ms);
+}
+
+int tm_set_progress(tm_ctx* c, tm_progress_fn fn, void* user) {
+  CHECK_CTX(c);
+  c->progress = fn;
+  c->progress_user = user;
+  return TM_OK;
 }
 
 int tm_profile_enable(tm_ctx* c, int enable) {

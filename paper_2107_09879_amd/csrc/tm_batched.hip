@@ -793,6 +793,16 @@ static int batched_impl(tm_ctx* c, int S, const tm_subregion* subs, int R, const
       nlive += live[s];
     }
     if (!nlive) break;
+    if (c->progress) {
+      double worst = 0.0;
+      int cyc = 0, itmax = 0;
+      for (int s = 0; s < ns; ++s) {
+        itmax = std::max(itmax, iters[s]);
+        cyc = std::max(cyc, cycles[s]);
+        if (live[s]) worst = std::max(worst, relres[s]);
+      }
+      c->progress(c->progress_user, cyc, itmax, nlive, worst);
+    }
     std::vector<double> tgt(ns, 0.0);
     for (int s = 0; s < ns; ++s) {
       if (!live[s]) continue;

@@ -83,6 +83,8 @@ struct tm_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   std::string err;
+  tm_progress_fn progress = nullptr;  // optional per-cycle callback
+  void* progress_user = nullptr;
   tmh::Geometry g;
   tmh::SlotMaps maps{};
   bool have_geom = false, have_t = false, have_dt = false;
@@ -109,6 +111,7 @@ struct tm_ctx {
   int mv_items[2] = {0, 0};
   tmh::DevBuf plan_items[2], plan_ibeg[2];
   int plan_R[2] = {-1, -1}, plan_target[2] = {0, 0}, plan_nitems[2] = {0, 0};
+  int plan_nreg[2] = {0, 0};  // LDS plan: items of regular tiles (wide-tile items follow)
   int last_batch_graphed = 0;
 };
 

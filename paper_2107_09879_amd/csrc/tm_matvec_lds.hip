@@ -74,6 +74,9 @@ struct LdsArgs {
   const SubParams* subs;
   const int* active;
   const int* done;
+  // wide-tile launch: rows at and beyond y_base are tiled 4 rows high; item
+  // tile indices start at tile_base; partial slots at item_base
+  int y_base, tile_base, item_base;
 };
 
 // A operand of one displacement: 4 (re, im) pairs in sigma order.
@@ -111,10 +114,16 @@ __device__ inline void read_b(const float4* __restrict__ win, int base, int wx, 
   }
 }
 
-template <typename T, int GX, int BX, int BY>
+// Tile geometry.  Regular: a (4 GX) x 16 tile, wave w owns rows 4w..4w+3 and
+// all GX column groups.  Wide (for the last rows of a lattice whose height
+// is not a multiple of 16): a (16 GX) x 4 tile, wave w owns columns
+// 4 GX w .. 4 GX w + 4 GX - 1 of the same 4 rows, so all four waves work.
+template <typename T, int GX, int BX, int BY, bool WIDE = false>
 struct LdsCfg {
-  static constexpr int TW = 4 * GX;  // tile width in sites
-  static constexpr int WX = TW - 1 + BX, WY = 16 - 1 + BY;
+  static constexpr int TW = 4 * GX;                // columns per wave
+  static constexpr int TWT = WIDE ? 4 * TW : TW;   // tile width in sites
+  static constexpr int THT = WIDE ? 4 : 16;        // tile height in sites
+  static constexpr int WX = TWT - 1 + BX, WY = THT - 1 + BY;
   static constexpr int CH = LdsT<T>::CH;
   static constexpr int CHUNKS = WX * WY * CH;
   static constexpr size_t BYTES = (size_t)CHUNKS * 16;
@@ -122,13 +131,14 @@ struct LdsCfg {
 
 // Complex products by three real MFMA products (T1 = Mr Xr, T2 = Mi Xi,
 // T3 = (Mr + Mi)(Xr + Xi); Yr = T1 - T2, Yi = T3 - T1 - T2).
-template <typename T, int GX, int BX, int BY, int PF>
+template <typename T, int GX, int BX, int BY, int PF, bool WIDE>
 __global__ __launch_bounds__(256, 2) void block_matvec_lds_kernel(LdsArgs a) {
   using L = LdsT<T>;
-  using Cfg = LdsCfg<T, GX, BX, BY>;
+  using Cfg = LdsCfg<T, GX, BX, BY, WIDE>;
   using acc_t = typename L::acc_t;
   using C = cplx<T>;
-  constexpr int TW = Cfg::TW, WX = Cfg::WX, WY = Cfg::WY, CH = Cfg::CH;
+  constexpr int TW = Cfg::TW, TWT = Cfg::TWT, THT = Cfg::THT, WX = Cfg::WX, WY = Cfg::WY,
+                CH = Cfg::CH;
   __shared__ float4 win[Cfg::CHUNKS];
   const int lane = threadIdx.x & 63;
   // wave-uniform by construction; readfirstlane lets the compiler keep the
@@ -138,7 +148,7 @@ __global__ __launch_bounds__(256, 2) void block_matvec_lds_kernel(LdsArgs a) {
   const int kq = lane >> 4;
   const int lx = jt & 3, ly = jt >> 2;
   if (a.done && *a.done) return;
-  const int item = blockIdx.x;
+  const int item = a.item_base + blockIdx.x;
   const LdsItem it = a.items[item];
   const int rc = blockIdx.y;
   const int r = rc >> 1, c = rc & 1;
@@ -153,21 +163,25 @@ __global__ __launch_bounds__(256, 2) void block_matvec_lds_kernel(LdsArgs a) {
     N = (size_t)sp.nx * sp.ny;
     voff = (size_t)sp.vec_off;
   }
-  const int X0 = (it.tile % tiles_x) * TW;
-  const int Y0 = (it.tile / tiles_x) * 16;
-  const int gy0 = Y0 + 4 * wave;
+  const int tl = it.tile - a.tile_base;
+  const int X0 = (tl % tiles_x) * TWT;
+  const int Y0 = a.y_base + (tl / tiles_x) * THT;
+  const int wxo = WIDE ? TW * wave : 0;  // this wave's column and row offsets in the tile
+  const int gy0 = Y0 + (WIDE ? 0 : 4 * wave);
+  const int gxw = X0 + wxo;
   const int ty = gy0 + ly;
   const C* __restrict__ xin =
       reinterpret_cast<const C*>(a.x) + voff + ((size_t)r * NCLASS + c) * N * SLOTS;
   const C* __restrict__ tab = reinterpret_cast<const C*>(a.table);
   const int wxt = 2 * a.tnx - 1;
   // the tile's displacement range and its block grid
-  const int dxlo = X0 - (nx - 1), dxhi = min(X0 + TW - 1, nx - 1);
-  const int dylo = Y0 - (ny - 1), dyhi = min(Y0 + 15, ny - 1);
+  const int dxlo = X0 - (nx - 1), dxhi = min(X0 + TWT - 1, nx - 1);
+  const int dylo = Y0 - (ny - 1), dyhi = min(Y0 + THT - 1, ny - 1);
   const int nbx = (dxhi - dxlo + BX) / BX;
-  // this wave's valid dy (its rows must reach a source row)
+  // this wave's valid displacements (its rows and columns must reach a source)
   const int wdylo = gy0 - (ny - 1), wdyhi = min(gy0 + 3, ny - 1);
-  const bool wave_live = gy0 < ny;
+  const int wdxlo = gxw - (nx - 1), wdxhi = min(gxw + TW - 1, nx - 1);
+  const bool wave_live = gy0 < ny && gxw < nx;
 
   acc_t t1[GX], t2[GX], t3[GX];
 #pragma unroll
@@ -196,7 +210,7 @@ __global__ __launch_bounds__(256, 2) void block_matvec_lds_kernel(LdsArgs a) {
     __syncthreads();
     if (!wave_live) continue;
     const int dyb = max(by0, max(dylo, wdylo)), dye = min(by0 + BY - 1, min(dyhi, wdyhi));
-    const int dxb = max(bx0, dxlo), dxe = min(bx0 + BX - 1, dxhi);
+    const int dxb = max(bx0, max(dxlo, wdxlo)), dxe = min(bx0 + BX - 1, min(dxhi, wdxhi));
     if (dyb > dye || dxb > dxe) continue;
     const int ndx = dxe - dxb + 1;
     const int nq = (dye - dyb + 1) * ndx;
@@ -223,7 +237,7 @@ __global__ __launch_bounds__(256, 2) void block_matvec_lds_kernel(LdsArgs a) {
       const int wy = (ty - Y0) - (y - by0) + BY - 1;
 #pragma unroll
       for (int g = 0; g < GX; ++g) {
-        const int wx = 4 * g + lx - (x - bx0) + BX - 1;
+        const int wx = wxo + 4 * g + lx - (x - bx0) + BX - 1;
         read_b(win, (wy * WX + wx) * CH, wx, wy, kq, r_[g], i_[g]);
       }
     };
@@ -253,7 +267,7 @@ __global__ __launch_bounds__(256, 2) void block_matvec_lds_kernel(LdsArgs a) {
       for (int s = 0; s < 4; ++s) ms[s] = ar[K][s] + ai[K][s];
 #pragma unroll
       for (int g = 0; g < GX; ++g) {
-        const int gx0 = X0 + 4 * g;
+        const int gx0 = gxw + 4 * g;
         if (gx0 >= nx || gx0 + 3 - cdx < 0 || gx0 - cdx >= nx) continue;  // wave-uniform
         T xs[4];
 #pragma unroll
@@ -288,13 +302,13 @@ __global__ __launch_bounds__(256, 2) void block_matvec_lds_kernel(LdsArgs a) {
     }
   }
   // this item's partial sums for every valid target of the tile
-  C* out = reinterpret_cast<C*>(a.partial) + ((size_t)item * (2 * a.R) + rc) * (TW * 16 * SLOTS);
+  C* out = reinterpret_cast<C*>(a.partial) + ((size_t)item * (2 * a.R) + rc) * (TWT * THT * SLOTS);
   if (ty < ny) {
 #pragma unroll
     for (int g = 0; g < GX; ++g) {
-      const int tx = X0 + 4 * g + lx;
+      const int tx = gxw + 4 * g + lx;
       if (tx >= nx) continue;
-      C* o = out + (size_t)((ty - Y0) * TW + (tx - X0)) * SLOTS;
+      C* o = out + (size_t)((ty - Y0) * TWT + (tx - X0)) * SLOTS;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const T yr = t1[g][v] - t2[g][v];
@@ -306,46 +320,77 @@ __global__ __launch_bounds__(256, 2) void block_matvec_lds_kernel(LdsArgs a) {
 }
 
 // ---------------------------------------------------------------- host side
-// Work of every displacement block of every tile (MFMA units plus the window
-// copy), used by the planner to cut each tile's block list into equal-work
-// items.
+// Work of every displacement block of one tile (MFMA units plus the window
+// copy), mirroring the kernel's per-wave clipping: the planner cuts each
+// tile's block list into equal-work items.  TW = columns per wave.
+static double tile_block_work(int nx, int ny, int X0, int Y0, bool wide, int TW, int BX, int BY,
+                              int win_cost, std::vector<double>& wb) {
+  const int GX = TW / 4;
+  const int TWT = wide ? 4 * TW : TW, THT = wide ? 4 : 16;
+  const int dxlo = X0 - (nx - 1), dxhi = std::min(X0 + TWT - 1, nx - 1);
+  const int dylo = Y0 - (ny - 1), dyhi = std::min(Y0 + THT - 1, ny - 1);
+  const int nbx = (dxhi - dxlo + BX) / BX, nby = (dyhi - dylo + BY) / BY;
+  wb.assign((size_t)nbx * nby, 0.0);
+  int gyw[4], gxw[4];
+  for (int wv = 0; wv < 4; ++wv) {
+    gyw[wv] = Y0 + (wide ? 0 : 4 * wv);
+    gxw[wv] = X0 + (wide ? TW * wv : 0);
+  }
+  double total = 0.0;
+  for (int b = 0; b < nbx * nby; ++b) {
+    const int bx0 = dxlo + (b % nbx) * BX, by0 = dylo + (b / nbx) * BY;
+    double w = win_cost;
+    for (int wv = 0; wv < 4; ++wv) {
+      const int gy0 = gyw[wv], gx = gxw[wv];
+      if (gy0 >= ny || gx >= nx) continue;
+      const int yb = std::max(by0, std::max(dylo, gy0 - (ny - 1)));
+      const int ye = std::min(by0 + BY - 1, std::min(dyhi, std::min(gy0 + 3, ny - 1)));
+      const int xb = std::max(bx0, std::max(dxlo, gx - (nx - 1)));
+      const int xe = std::min(bx0 + BX - 1, std::min(dxhi, std::min(gx + TW - 1, nx - 1)));
+      if (yb > ye || xb > xe) continue;
+      double row = 0.0;
+      for (int dx = xb; dx <= xe; ++dx) {
+        int groups = 0;
+        for (int q = 0; q < GX; ++q) {
+          const int gx0 = gx + 4 * q;
+          if (gx0 < nx && gx0 + 3 - dx >= 0 && gx0 - dx < nx) ++groups;
+        }
+        row += 12.0 * groups + 4.0;
+      }
+      w += row * (ye - yb + 1);
+    }
+    wb[b] = w;
+    total += w;
+  }
+  return total;
+}
+
+// Regular tiles only (the batched solver's subregions).
 double lds_block_work(int nx, int ny, int TW, int BX, int BY, int win_cost,
                       std::vector<std::vector<double>>& wb) {
   const int tiles_x = (nx + TW - 1) / TW, tiles_y = (ny + 15) / 16;
-  const int tiles = tiles_x * tiles_y;
-  const int GX = TW / 4;
-  wb.assign(tiles, {});
+  wb.assign((size_t)tiles_x * tiles_y, {});
   double total = 0.0;
-  for (int t = 0; t < tiles; ++t) {
-    const int X0 = (t % tiles_x) * TW, Y0 = (t / tiles_x) * 16;
-    const int dxlo = X0 - (nx - 1), dxhi = std::min(X0 + TW - 1, nx - 1);
-    const int dylo = Y0 - (ny - 1), dyhi = std::min(Y0 + 15, ny - 1);
-    const int nbx = (dxhi - dxlo + BX) / BX, nby = (dyhi - dylo + BY) / BY;
-    wb[t].assign((size_t)nbx * nby, 0.0);
-    for (int b = 0; b < nbx * nby; ++b) {
-      const int bx0 = dxlo + (b % nbx) * BX, by0 = dylo + (b / nbx) * BY;
-      double w = win_cost;
-      for (int dy = by0; dy < std::min(by0 + BY, dyhi + 1); ++dy) {
-        int waves = 0;
-        for (int wv = 0; wv < 4; ++wv) {
-          const int gy0 = Y0 + 4 * wv;
-          if (gy0 < ny && dy >= gy0 - (ny - 1) && dy <= std::min(gy0 + 3, ny - 1)) ++waves;
-        }
-        if (!waves) continue;
-        for (int dx = bx0; dx < std::min(bx0 + BX, dxhi + 1); ++dx) {
-          int groups = 0;
-          for (int q = 0; q < GX; ++q) {
-            const int gx0 = X0 + 4 * q;
-            if (gx0 < nx && gx0 + 3 - dx >= 0 && gx0 - dx < nx) ++groups;
-          }
-          w += waves * (12.0 * groups + 4.0);
-        }
-      }
-      wb[t][b] = w;
-      total += w;
-    }
-  }
+  for (int t = 0; t < tiles_x * tiles_y; ++t)
+    total += tile_block_work(nx, ny, (t % tiles_x) * TW, (t / tiles_x) * 16, false, TW, BX, BY,
+                             win_cost, wb[t]);
   return total;
+}
+
+// Tiling of one lattice: regular tiles over rows [0, y_wide), wide tiles (4
+// rows) over the remaining ny - y_wide < 16 rows.
+struct LdsTiling {
+  int TW, tiles_x, n_reg, y_wide, tiles_xw, n_wide;
+};
+static LdsTiling lds_tiling(const Geometry& g, int TW) {
+  LdsTiling tl;
+  tl.TW = TW;
+  tl.tiles_x = (g.nx + TW - 1) / TW;
+  tl.y_wide = 16 * (g.ny / 16);
+  tl.n_reg = tl.tiles_x * (tl.y_wide / 16);
+  tl.tiles_xw = (g.nx + 4 * TW - 1) / (4 * TW);
+  tl.n_wide = g.ny > tl.y_wide ? tl.tiles_xw * ((g.ny - tl.y_wide + 3) / 4) : 0;
+  return tl;
 }
 
 // Cut every tile's blocks into items of about `per` work; appends to items
@@ -372,10 +417,18 @@ void lds_split(const std::vector<std::vector<double>>& wb, double per, int sub,
   }
 }
 
-static void lds_plan(const Geometry& g, int TW, int BX, int BY, int win_cost, int target,
+// Items of one lattice: regular tiles first, then wide tiles (tile indices
+// continue), so the two launches take contiguous item ranges.
+static void lds_plan(const Geometry& g, const LdsTiling& tl, int BX, int BY, int win_cost, int target,
                      std::vector<LdsItem>& items, std::vector<int>& ibeg) {
-  std::vector<std::vector<double>> wb;
-  const double total = lds_block_work(g.nx, g.ny, TW, BX, BY, win_cost, wb);
+  std::vector<std::vector<double>> wb((size_t)tl.n_reg + tl.n_wide);
+  double total = 0.0;
+  for (int t = 0; t < tl.n_reg; ++t)
+    total += tile_block_work(g.nx, g.ny, (t % tl.tiles_x) * tl.TW, (t / tl.tiles_x) * 16, false, tl.TW,
+                             BX, BY, win_cost, wb[t]);
+  for (int t = 0; t < tl.n_wide; ++t)
+    total += tile_block_work(g.nx, g.ny, (t % tl.tiles_xw) * 4 * tl.TW, tl.y_wide + (t / tl.tiles_xw) * 4,
+                             true, tl.TW, BX, BY, win_cost, wb[(size_t)tl.n_reg + t]);
   items.clear();
   ibeg.clear();
   lds_split(wb, total / std::max(1, target), 0, items, ibeg);
@@ -387,7 +440,7 @@ static void lds_plan(const Geometry& g, int TW, int BX, int BY, int win_cost, in
 // the site's tile, added in item order.
 template <typename T>
 __global__ void lds_combine_kernel(const cplx<T>* __restrict__ partial, const int* __restrict__ ibeg,
-                                   int R, int nx, int tiles_x, int TW, long long N,
+                                   int R, int nx, LdsTiling tl, long long N,
                                    const c128* __restrict__ x, const c128* __restrict__ t,
                                    c128* __restrict__ y, long long vec, long long total, int mode) {
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -396,8 +449,16 @@ __global__ void lds_combine_kernel(const cplx<T>* __restrict__ partial, const in
   const long long site = (idx / SLOTS) % N;
   const int rc = (int)(idx / (SLOTS * N));
   const int sx = (int)(site % nx), sy = (int)(site / nx);
-  const int tile = (sy >> 4) * tiles_x + sx / TW;
-  const int ls = (sy & 15) * TW + (sx % TW);
+  const int TW = tl.TW;
+  int tile, ls;
+  if (sy < tl.y_wide) {
+    tile = (sy >> 4) * tl.tiles_x + sx / TW;
+    ls = (sy & 15) * TW + (sx % TW);
+  } else {
+    const int wy = sy - tl.y_wide;
+    tile = tl.n_reg + (wy >> 2) * tl.tiles_xw + sx / (4 * TW);
+    ls = (wy & 3) * (4 * TW) + (sx % (4 * TW));
+  }
   double sr = 0.0, si = 0.0;
   for (int i = ibeg[tile]; i < ibeg[tile + 1]; ++i) {
     const cplx<T> v = partial[(((size_t)i * (2 * R) + rc) * (TW * 16) + ls) * SLOTS + slot];
@@ -434,23 +495,24 @@ struct LdsChoice<double> {
   static constexpr int GX = 2, BX = 8, BY = 4;
 };
 
-template <typename T, int PF>
+template <typename T, int PF, bool WIDE>
 static void lds_launch_pf(hipStream_t st, int nitems, int R, const LdsArgs& a) {
   using Ch = LdsChoice<T>;
-  hipLaunchKernelGGL((block_matvec_lds_kernel<T, Ch::GX, Ch::BX, Ch::BY, PF>), dim3(nitems, 2 * R),
-                     dim3(256), 0, st, a);
+  hipLaunchKernelGGL((block_matvec_lds_kernel<T, Ch::GX, Ch::BX, Ch::BY, PF, WIDE>),
+                     dim3(nitems, 2 * R), dim3(256), 0, st, a);
 }
 // FP64 stages are twice as wide: depth 3 does not fit two waves' registers,
 // so FP64 runs depth 2 for variant 10
-template <typename T>
+template <typename T, bool WIDE = false>
 static void lds_launch_any(hipStream_t st, int pf, int nitems, int R, const LdsArgs& a) {
+  if (nitems <= 0) return;
   if (pf <= 1) {
-    lds_launch_pf<T, 1>(st, nitems, R, a);
+    lds_launch_pf<T, 1, WIDE>(st, nitems, R, a);
   } else if constexpr (std::is_same<T, double>::value) {
-    lds_launch_pf<T, 2>(st, nitems, R, a);
+    lds_launch_pf<T, 2, WIDE>(st, nitems, R, a);
   } else {
-    if (pf == 2) lds_launch_pf<T, 2>(st, nitems, R, a);
-    else lds_launch_pf<T, 3>(st, nitems, R, a);
+    if (pf == 2) lds_launch_pf<T, 2, WIDE>(st, nitems, R, a);
+    else lds_launch_pf<T, 3, WIDE>(st, nitems, R, a);
   }
 }
 
@@ -461,13 +523,15 @@ int lds_apply(tm_ctx* c, int which, int R, const void* table, const void* xin, c
   using Cfg = LdsCfg<T, Ch::GX, Ch::BX, Ch::BY>;
   const Geometry& g = c->g;
   const int TW = Cfg::TW;
+  const LdsTiling tl = lds_tiling(g, TW);
   const long long vec = g.vec_len(), total = vec * R;
   const int key = 1000 + items_target;  // plan cache key (distinct from the direct kernel's)
   int rc;
   if (c->plan_R[which] != R || c->plan_target[which] != key) {
     std::vector<LdsItem> items;
     std::vector<int> ibeg;
-    lds_plan(g, TW, Ch::BX, Ch::BY, 64, items_target, items, ibeg);
+    lds_plan(g, tl, Ch::BX, Ch::BY, 64, items_target, items, ibeg);
+    c->plan_nreg[which] = ibeg[tl.n_reg];
     if ((rc = ensure(c, c->plan_items[which], items.size() * sizeof(LdsItem))) != TM_OK) return rc;
     if ((rc = ensure(c, c->plan_ibeg[which], ibeg.size() * sizeof(int))) != TM_OK) return rc;
     TM_HIP(c, hipMemcpy(c->plan_items[which].p, items.data(), items.size() * sizeof(LdsItem),
@@ -490,20 +554,31 @@ int lds_apply(tm_ctx* c, int which, int R, const void* table, const void* xin, c
   a.ny = g.ny;
   a.tnx = g.tnx;
   a.tny = g.tny;
-  a.tiles_x = (g.nx + TW - 1) / TW;
+  a.tiles_x = tl.tiles_x;
   a.R = R;
   a.n_sites = g.n;
   a.subs = nullptr;
   a.active = nullptr;
   a.done = nullptr;
+  a.y_base = 0;
+  a.tile_base = 0;
+  a.item_base = 0;
+  const int nreg = c->plan_nreg[which];
   if (e0) TM_HIP(c, hipEventRecord(e0, c->stream));
-  lds_launch_any<T>(c->stream, pf, nitems, R, a);
+  lds_launch_any<T, false>(c->stream, pf, nreg, R, a);
+  // the last ny mod 16 rows: wide tiles
+  LdsArgs aw = a;
+  aw.tiles_x = tl.tiles_xw;
+  aw.y_base = tl.y_wide;
+  aw.tile_base = tl.n_reg;
+  aw.item_base = nreg;
+  lds_launch_any<T, true>(c->stream, pf, nitems - nreg, R, aw);
   if (e1) TM_HIP(c, hipEventRecord(e1, c->stream));
   if (y) {
     const int nb = (int)((total + 255) / 256);
     hipLaunchKernelGGL(lds_combine_kernel<T>, dim3(nb), dim3(256), 0, c->stream,
-                       (const cplx<T>*)c->partial.p, (const int*)c->plan_ibeg[which].p, R, g.nx,
-                       a.tiles_x, TW, (long long)g.n, x, (const c128*)c->t64.p, y, vec, total, op);
+                       (const cplx<T>*)c->partial.p, (const int*)c->plan_ibeg[which].p, R, g.nx, tl,
+                       (long long)g.n, x, (const c128*)c->t64.p, y, vec, total, op);
   }
   TM_HIP(c, hipGetLastError());
   return TM_OK;
@@ -538,6 +613,9 @@ int lds_launch(tm_ctx* c, const void* table, const void* xin, void* partial, con
   a.subs = subs;
   a.active = active;
   a.done = done;
+  a.y_base = 0;
+  a.tile_base = 0;
+  a.item_base = 0;
   const int w = std::is_same<T, double>::value ? 0 : 1;
   lds_launch_any<T>(c->stream, std::max(1, c->mv_variant[w] - 7), nitems, R, a);
   return TM_OK;

@@ -52,6 +52,10 @@ class Subregion(ctypes.Structure):
 
 _lib = None
 
+# void (*)(void* user, int cycles, int iters, int n_live, double max_rel_residual)
+PROGRESS_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                               ctypes.c_double)
+
 
 def _hip_runtimes_mapped():
     paths = set()
@@ -104,6 +108,7 @@ def load():
         "tm_set_matvec_config": (I, [P, I, I, I]),
         "tm_get_matvec_config": (I, [P, I, ctypes.POINTER(I), ctypes.POINTER(I)]),
         "tm_autotune": (I, [P, I, I, ctypes.POINTER(D)]),
+        "tm_set_progress": (I, [P, PROGRESS_FN, P]),
         "tm_profile_enable": (I, [P, I]),
         "tm_profile_query": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(L), ctypes.POINTER(D)]),
         "tm_profile_reset": (I, [P]),
@@ -346,6 +351,17 @@ class Context:
         ms = ctypes.c_double()
         self._check(self.lib.tm_autotune(self.h, int(n_rhs), PRECISIONS[precision], ctypes.byref(ms)))
         return ms.value, self.get_matvec_config(precision)
+
+    # ---- progress
+    def set_progress(self, fn):
+        """fn(cycles, iters, n_live, max_rel_residual) after every restart
+        cycle of the solvers, or None to remove it."""
+        if fn is None:
+            self._progress = None
+            self._check(self.lib.tm_set_progress(self.h, PROGRESS_FN(), None))
+            return
+        self._progress = PROGRESS_FN(lambda _u, c, i, n, r: fn(c, i, n, r))
+        self._check(self.lib.tm_set_progress(self.h, self._progress, None))
 
     # ---- profiling
     def profile_enable(self, on=True):

@@ -355,6 +355,28 @@ def test_autotune_keeps_a_correct_configuration():
     ctx.close()
 
 
+def test_progress_callback_reports_every_cycle():
+    ctx, pos, radii = make_ctx(12, 10, 3, seed=4)
+    kh, po = wl.incidences(["x"])
+    a0 = ctx.plane_wave_rhs(kh, po)
+    seen = []
+    ctx.set_progress(lambda c, i, n, r: seen.append((c, i, n, r)))
+    _, info = ctx.solve(a0, tol=1e-12, restart=10)
+    assert info[0]["status"] == 0 and len(seen) == info[0]["cycles"] > 1
+    assert [x[0] for x in seen] == list(range(len(seen)))
+    assert all(x[2] == 1 for x in seen) and abs(seen[0][3] - 1.0) < 1e-12
+    assert all(b[3] <= a[3] * (1 + 1e-12) for a, b in zip(seen, seen[1:]))
+    seen.clear()
+    _, binfo = ctx.solve_batched([(0, 0, 6, 5), (3, 2, 8, 7)], kh, po, restart=10, tol=1e-10)
+    assert len(seen) == max(i["cycles"] for row in binfo for i in row)
+    assert all(1 <= x[2] <= 2 for x in seen)
+    ctx.set_progress(None)
+    seen.clear()
+    ctx.solve(a0, tol=1e-8)
+    assert not seen
+    ctx.close()
+
+
 # ----------------------------------------------------------------- batched subregions
 SUBS = [(0, 0, 12, 9), (5, 3, 20, 16), (30, 20, 10, 10), (7, 7, 1, 1), (0, 0, 24, 20), (13, 2, 17, 5)]
 
