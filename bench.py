@@ -35,17 +35,21 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_name(variant, ctype):
-    """Name of the block-matvec kernel a variant launches (as the profiler
-    prints it, template arguments included)."""
+def kernel_names(variant, ctype):
+    """Names of the kernels one block matvec of a variant launches (as the
+    profiler prints them, template arguments included)."""
     if variant >= 8:
         gx, bx, by = (4, 16, 4) if ctype == "float" else (2, 8, 4)
         pf = variant - 7 if ctype == "float" else min(variant - 7, 2)
-        # regular tiles; rows beyond the last multiple of 16 run a second,
-        # "true" (wide-tile) instance of the same kernel
-        return f"block_matvec_lds_kernel<{ctype}, {gx}, {bx}, {by}, {pf}, false>"
+        # regular tiles, then the wide-tile instance for the rows past the
+        # last multiple of 16 (absent when the height is a multiple of 16)
+        return [f"block_matvec_lds_kernel<{ctype}, {gx}, {bx}, {by}, {pf}, {w}>" for w in ("false", "true")]
     gauss, pref, occ = variant & 1, (variant >> 1) & 1, 4 if variant & 4 else 2
-    return f"block_matvec_kernel<{ctype}, {str(bool(gauss)).lower()}, {str(bool(pref)).lower()}, {occ}>"
+    return [f"block_matvec_kernel<{ctype}, {str(bool(gauss)).lower()}, {str(bool(pref)).lower()}, {occ}>"]
+
+
+def kernel_name(variant, ctype):
+    return " + ".join(kernel_names(variant, ctype))
 
 
 MATVEC_SOURCES = ("paper_2107_09879_amd/csrc/tm_matvec_lds.hip", "paper_2107_09879_amd/csrc/tm_matvec.hip")
@@ -61,24 +65,27 @@ def kernel_source_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, workload):
-    """HBM bytes per launch of `kernel` from the committed counter summary
-    (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated against a plain copy), or
-    None when there is none for this kernel and workload or the matvec
-    sources changed since the counters were taken."""
+def measured_traffic(kernels, workload):
+    """HBM bytes of one block matvec (the sum over its kernels) from the
+    committed counter summary (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated
+    against a plain copy), or None when a kernel has no row for this workload
+    or the matvec sources changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "block_matvec_hbm_traffic.md")
     if not os.path.exists(path):
         return None
     digest = kernel_source_digest()
+    rows = {}
     with open(path) as f:
         for line in f:
             cells = [c.strip() for c in line.strip().strip("|").split("|")]
-            if len(cells) >= 4 and cells[0] == kernel and cells[1] == workload and cells[2] == digest:
+            if len(cells) >= 4 and cells[1] == workload and cells[2] == digest:
                 try:
-                    return float(cells[3])
+                    rows[cells[0]] = float(cells[3])
                 except ValueError:
-                    return None
-    return None
+                    pass
+    if not all(k in rows for k in kernels):
+        return None
+    return sum(rows[k] for k in kernels)
 
 
 def copy_calibration(torch, mib=512):
@@ -226,7 +233,10 @@ def main():
     dom = live.get("mixed", mv["mixed"])
     gbs = alg_bytes / (dom["avg_launch_ms"] / 1e3) / 1e9
     variant = ctx.get_matvec_config("mixed")[0]
-    kname = kernel_name(variant, "float")
+    knames = kernel_names(variant, "float")
+    if n % 16 == 0:
+        knames = knames[:1]
+    kname = " + ".join(knames)
 
     cpu = None
     if not args.no_cpu_baseline and args.config == "c2":
@@ -256,7 +266,7 @@ def main():
         "matvec_algorithmic_GBps": gbs,
         "roofline": {"bound": "mfma", "achieved": dom["tflops"], "peak": PEAK_FP32_MFMA,
                      "unit": "TFLOP/s", "frac": dom["tflops"] / PEAK_FP32_MFMA,
-                     "traffic": measured_traffic(kname, cfg["name"]),
+                     "traffic": measured_traffic(knames, cfg["name"]),
                      "kernel": kname, "avg_launch_ms": dom["avg_launch_ms"],
                      "flops_per_launch": dom["flops_per_launch"],
                      "kernel_source_digest": kernel_source_digest()},
