@@ -500,7 +500,9 @@ static int plan_precision(tm_ctx* c, Batch& B, int w) {
   double total = 0.0;
   for (int k = 0; k < B.S; ++k)
     total += lds_block_work(B.subs[k].nx, B.subs[k].ny, TW, BX, BY, 64, wbs[k]);
-  const int target = std::max(1, 8192 / (2 * B.R));
+  // many small equal-work items: the LDS kernel runs best near one
+  // displacement block per workgroup
+  const int target = std::max(1, 32768 / (2 * B.R));
   std::vector<LdsItem> items;
   std::vector<int> ibeg;
   for (int k = 0; k < B.S; ++k) lds_split(wbs[k], total / target, k, items, ibeg);
