@@ -110,6 +110,7 @@ def main():
     ap.add_argument("--subregions", type=int, default=0, help="c3: use only the first K subregions")
     ap.add_argument("--no-sequential", action="store_true",
                     help="c3: skip the one-subregion-at-a-time comparison")
+    ap.add_argument("--restart", type=int, default=0, help="c3: GMRES restart length (default: the workload's)")
     ap.add_argument("--tile-iters", type=int, default=300,
                     help="c5: Arnoldi steps of the bounded solve used for the extrapolation")
     ap.add_argument("--matvec-config", action="append", default=[], metavar="PREC:VARIANT:ITEMS",
@@ -409,10 +410,15 @@ def bench_batched(args):
         subs = subs[:args.subregions]
     R = len(kh)
     max_iter = 20000
+    restart = args.restart or cfg["restart"]
 
     def progress(tag):
+        last = [time.perf_counter()]
+
         def fn(cycles, iters, n_live, worst):
-            if cycles % 10 == 0:
+            now = time.perf_counter()
+            if cycles % 10 == 0 or now - last[0] > 20.0:
+                last[0] = now
                 log(f"[bench] {tag}: cycle {cycles}, iters {iters}, live {n_live}, max residual {worst:.2e}")
         return fn
 
@@ -426,7 +432,7 @@ def bench_batched(args):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         sb, info = ctx.solve_batched(subs, kh, po, use_graph=True, tol=cfg["tol"],
-                                     restart=cfg["restart"], precision=prec, max_iter=max_iter)
+                                     restart=restart, precision=prec, max_iter=max_iter)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         flat = [i for row in info for i in row]
@@ -434,8 +440,16 @@ def bench_batched(args):
                      "iters_max": max(i["iters"] for i in flat),
                      "iters_mean": float(np.mean([i["iters"] for i in flat])),
                      "converged": sum(i["status"] == 0 for i in flat), "systems": len(flat),
-                     "max_rel_residual": max(i["rel_residual"] for i in flat)}
-        log(f"[bench] batched {prec}: {dt:.2f} s {res[prec]}")
+                     "max_rel_residual": max(i["rel_residual"] for i in flat),
+                     "per_subregion": [{"box": list(q), "iters": [i["iters"] for i in row],
+                                        "converged": all(i["status"] == 0 for i in row),
+                                        "rel_residual": max(i["rel_residual"] for i in row)}
+                                       for q, row in zip(subs, info)]}
+        log(f"[bench] batched {prec}: {dt:.2f} s, {res[prec]['converged']}/{len(flat)} converged, "
+            f"iters max {res[prec]['iters_max']} mean {res[prec]['iters_mean']:.0f}")
+        for k, e in enumerate(res[prec]["per_subregion"]):
+            if not e["converged"]:
+                log(f"[bench] subregion {k} {e['box']} not converged: iters {e['iters']}, residual {e['rel_residual']:.2e}")
     ctx.set_progress(None)
     ctx.close()
     # the same systems one subregion at a time (R right-hand sides per solve)
@@ -468,7 +482,7 @@ def bench_batched(args):
            "ms_per_step": res["mixed"]["time_s"] * 1e3, "higher_is_better": False, "scaling": "weak",
            "vs_baseline": None, "dtype": "c64+f64", "data": "synthetic",
            "config": {"workload": cfg["name"], "subregions": len(subs), "sites": sites,
-                      "rhs": R, "systems": len(subs) * R},
+                      "rhs": R, "systems": len(subs) * R, "restart": restart},
            "batched": res, "sequential_mixed": None if args.no_sequential else seq,
            "batched_speedup_vs_sequential": None if args.no_sequential else seq["time_s"] / res["mixed"]["time_s"]}
     print(json.dumps(out), flush=True)
