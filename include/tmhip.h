@@ -262,8 +262,10 @@ int tm_grad_radius(tm_ctx* ctx, int n_rhs, const tm_c128* mu, const tm_c128* s,
  * next displacement loaded during the current one's products, bit 2 =
  * register budget for 4 (else 2) waves per SIMD; variants 8, 9, 10: source
  * windows staged in LDS per block of displacements, translation blocks
- * fetched 1, 2, 3 displacements ahead.  items: target work items per
- * (rhs, class) pair, 0 = default.  All variants compute the same product. */
+ * fetched 1, 2, 3 displacements ahead (FP64 runs variant 10 as 9: depth 3
+ * does not fit its register budget), with 4-row "wide" tiles for rows past
+ * the last multiple of 16.  items: target work items per (rhs, class) pair,
+ * 0 = default.  All variants compute the same product. */
 int tm_set_matvec_config(tm_ctx* ctx, int precision, int variant, int items);
 int tm_get_matvec_config(tm_ctx* ctx, int precision, int* variant, int* items);
 
