@@ -110,9 +110,12 @@ def main():
     ap.add_argument("--subregions", type=int, default=0, help="c3: use only the first K subregions")
     ap.add_argument("--no-sequential", action="store_true",
                     help="c3: skip the one-subregion-at-a-time comparison")
-    ap.add_argument("--restart", type=int, default=0, help="c3: GMRES restart length (default: the workload's)")
+    ap.add_argument("--restart", type=int, default=0,
+                    help="c3, c5: GMRES restart length (default: the workload's, 50)")
     ap.add_argument("--tile-iters", type=int, default=300,
                     help="c5: Arnoldi steps of the bounded solve used for the extrapolation")
+    ap.add_argument("--tile-rhs", type=int, default=-1,
+                    help="c5: solve only this right-hand side (0 or 1) to the tolerance and time it")
     ap.add_argument("--matvec-config", action="append", default=[], metavar="PREC:VARIANT:ITEMS",
                     help="fix the block-matvec kernel of a precision (mixed or fp64) instead of "
                          "autotuning it, e.g. mixed:9:16384")
@@ -333,11 +336,15 @@ def bench_tile(args):
         log(f"[bench] tile solve: cycle {cycles}, iters {iters}, residual {worst:.3e}")
 
     ctx.set_progress(progress)
+    full = args.tile_rhs >= 0
+    if full:  # one right-hand side to the tolerance (the solver treats them independently)
+        kh, po = kh[args.tile_rhs:args.tile_rhs + 1], po[args.tile_rhs:args.tile_rhs + 1]
     a0 = ctx.plane_wave_rhs(kh, po)
     torch.cuda.synchronize()
     t_start[0] = time.perf_counter()
-    s, info = ctx.solve(a0, tol=cfg["tol"], restart=cfg["restart"], precision="mixed",
-                        max_iter=args.tile_iters)
+    restart = args.restart or cfg["restart"]
+    s, info = ctx.solve(a0, tol=cfg["tol"], restart=restart, precision="mixed",
+                        max_iter=20000 if full else args.tile_iters)
     torch.cuda.synchronize()
     t_solve = time.perf_counter() - t_start[0]
     ctx.set_progress(None)
@@ -353,16 +360,19 @@ def bench_tile(args):
         sec_per_iter = t_solve / max(1, sum(i["iters"] for i in info))
         extrap = {"iters_per_rhs_est": it_total, "time_to_solution_s_est": it_total * sec_per_iter * R,
                   "sec_per_iteration": sec_per_iter, "basis": "extrapolated from the bounded run"}
-    log(f"[bench] tile bounded solve {t_solve:.1f} s, info {info}, extrapolation {extrap}")
-    nf = near_field_plane(ctx, s, cfg)
+    log(f"[bench] tile {'full' if full else 'bounded'} solve {t_solve:.1f} s, info {info}, "
+        f"extrapolation {extrap}")
+    nf = None if full else near_field_plane(ctx, s, cfg)
     out = {"metric": "time-to-solution at 1e-8 residual + translation-matvec GB/s, 1e4-1e5 scatterers",
            "value": mv["mixed"]["avg_launch_ms"], "unit": "ms per c64 block matvec (2 RHS)",
            "n_gpus": 1, "steps": 3, "warmup": 1, "ms_per_step": mv["mixed"]["avg_launch_ms"],
            "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "c64+f64",
-           "data": "synthetic", "config": {"workload": cfg["name"], "scatterers": N, "lmax": lmax, "rhs": R},
+           "data": "synthetic", "config": {"workload": cfg["name"], "scatterers": N, "lmax": lmax, "rhs": R,
+                                           "restart": restart},
            "table_build_s": t_table, "matvec": mv,
-           "bounded_solve": {"max_iter": args.tile_iters, "time_s": t_solve, "info": info},
-           "time_to_solution_extrapolated": extrap, "near_field": nf,
+           "bounded_solve": None if full else {"max_iter": args.tile_iters, "time_s": t_solve, "info": info},
+           "solve_one_rhs": {"rhs": args.tile_rhs, "time_to_solution_s": t_solve, "info": info} if full else None,
+           "time_to_solution_extrapolated": None if full else extrap, "near_field": nf,
            "roofline": {"bound": "mfma", "achieved": mv["mixed"]["tflops"], "peak": PEAK_FP32_MFMA,
                         "unit": "TFLOP/s", "frac": mv["mixed"]["frac"], "traffic": None,
                         "kernel": kernel_name(fixed["mixed"][0], "float")}}

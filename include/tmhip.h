@@ -137,7 +137,9 @@ enum { TM_PREC_FP64 = 0, TM_PREC_MIXED = 1 };
 
 typedef struct {
   double tol;        /* relative true residual ||T a0 - B s|| / ||T a0||   */
-  int restart;       /* Krylov dimension per cycle (1..200)                 */
+  int restart;       /* Krylov dimension per cycle: 1..1000 for tm_solve and
+                        tm_adjoint_solve ((restart+1) basis vectors of 32 N
+                        complex128 each), 1..200 for tm_solve_batched       */
   int max_iter;      /* total Arnoldi steps over all cycles                 */
   int precision;     /* TM_PREC_FP64: FP64 matvec throughout;
                         TM_PREC_MIXED: complex64 matvec with FP32

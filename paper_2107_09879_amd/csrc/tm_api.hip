@@ -482,7 +482,7 @@ int tm_plane_wave_rhs(tm_ctx* c, int R, const double* khat, const tm_c128* pol, 
 
 static int validate_opts(tm_ctx* c, const tm_solve_opts* o) {
   if (!o) return tmh::set_err(c, TM_ERR_INVALID_ARG, "null options");
-  if (!(o->tol > 0.0) || o->restart < 1 || o->restart > 200 || o->max_iter < 1 ||
+  if (!(o->tol > 0.0) || o->restart < 1 || o->restart > 1000 || o->max_iter < 1 ||
       (o->precision != TM_PREC_FP64 && o->precision != TM_PREC_MIXED) ||
       (o->precision == TM_PREC_MIXED && !(o->inner_tol > 0.0 && o->inner_tol < 1.0)))
     return tmh::set_err(c, TM_ERR_INVALID_ARG, "invalid solver options");
