@@ -283,8 +283,11 @@ int tm_autotune(tm_ctx* ctx, int n_rhs, int precision, double* best_ms);
  * cycles = restart cycles so far, iters = Arnoldi steps so far (the largest
  * over the batch's systems), n_live = systems still iterating (1 for a single
  * solve), max_rel_residual = largest true relative residual among them at
- * the start of the cycle.  The callback must not call back into the same
- * context.  fn = NULL removes it. */
+ * the start of the cycle.  Inside a cycle of tm_solve / tm_adjoint_solve it
+ * is also called every 50 Arnoldi steps (except after the cycle's last step)
+ * with cycles = completed cycles and max_rel_residual = the Givens estimate
+ * of the current relative residual.  The callback must not call back into
+ * the same context.  fn = NULL removes it. */
 typedef void (*tm_progress_fn)(void* user, int cycles, int iters, int n_live, double max_rel_residual);
 int tm_set_progress(tm_ctx* ctx, tm_progress_fn fn, void* user);
 

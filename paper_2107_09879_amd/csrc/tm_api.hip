@@ -201,6 +201,9 @@ static int gmres(tm_ctx* c, Op op, const c128* b, c128* x, const tm_solve_opts& 
       ++it;
       jend = j + 1;
       if (std::abs(gv[j + 1]) <= target || it >= o.max_iter || hn == 0.0) break;
+      // long cycles also report every 50 steps, with the Givens estimate
+      if (c->progress && (j + 1) % 50 == 0 && j + 1 < m)
+        c->progress(c->progress_user, info.cycles - 1, it, 1, std::abs(gv[j + 1]) / bnorm);
     }
     // back substitution H y = g
     for (int i = jend - 1; i >= 0; --i) {

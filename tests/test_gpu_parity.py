@@ -370,6 +370,19 @@ def test_progress_callback_reports_every_cycle():
     _, binfo = ctx.solve_batched([(0, 0, 6, 5), (3, 2, 8, 7)], kh, po, restart=10, tol=1e-10)
     assert len(seen) == max(i["cycles"] for row in binfo for i in row)
     assert all(1 <= x[2] <= 2 for x in seen)
+    # a long cycle also reports every 50 steps inside the cycle (Givens
+    # estimates, non-increasing within the cycle)
+    big, _, _ = make_ctx(20, 18, 3, seed=4)
+    big.set_progress(lambda c, i, n, r: seen.append((c, i, n, r)))
+    seen.clear()
+    _, info = big.solve(big.plane_wave_rhs(kh, po), tol=1e-13, restart=300)
+    inner = [x for x in seen if x[0] == 0 and x[1] > 0]
+    # after steps 50, 100, ... of cycle 0, except a step that ends the solve
+    # or the cycle (the next cycle reports at its start)
+    assert len(inner) == (min(info[0]["iters"], 300) - 1) // 50
+    assert all(x[1] % 50 == 0 for x in inner)
+    assert all(b[3] <= a[3] * (1 + 1e-12) for a, b in zip(inner, inner[1:]))
+    big.close()
     ctx.set_progress(None)
     seen.clear()
     ctx.solve(a0, tol=1e-8)
