@@ -22,6 +22,8 @@
 // sigma_i sigma_j M(dx,dy)[j][i].
 #include <cmath>
 
+#include <algorithm>
+
 #include "tm_internal.h"
 
 namespace tmh {
@@ -187,48 +189,79 @@ __device__ inline void hankel_up(double x, int qmax, double* hr, double* hi) {
   }
 }
 
-// One workgroup per displacement; threads = (class, target slot, source slot).
-__global__ __launch_bounds__(512) void build_table_kernel(
-    const double* __restrict__ coef, const int* __restrict__ dm, const int* __restrict__ sig,
-    c128* __restrict__ tab64, c64* __restrict__ tab32, int tnx, int tny, double pitch, double k,
-    int qmax, int transpose) {
-  const long long d = blockIdx.x;
-  const int c = threadIdx.x >> 8;
-  int i = (threadIdx.x >> 4) & 15;
-  int j = threadIdx.x & 15;
+// Per displacement d: h_q(k|d|) for q <= qmax (rad[d][q]) and e^{i mu phi}
+// for |mu| <= qmax (ang[d][mu + QMAX]), the transcendental part of every
+// entry of the block, computed once per displacement.
+__global__ void table_radial_kernel(int tnx, int tny, double pitch, double k, int qmax,
+                                    long long D, c128* __restrict__ rad, c128* __restrict__ ang) {
+  const long long d = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= D) return;
   const int wx = 2 * tnx - 1;
   const int dx = (int)(d % wx) - (tnx - 1);
   const int dy = (int)(d / wx) - (tny - 1);
-  const size_t out = ((size_t)d * NCLASS + c) * SLOTS * SLOTS + (size_t)i * SLOTS + j;
-  double re = 0.0, im = 0.0;
+  c128* rd = rad + d * (QMAX + 1);
+  c128* ad = ang + d * (2 * QMAX + 1);
+  double hr[QMAX + 1] = {0}, hi[QMAX + 1] = {0};
+  double phi = 0.0;
   if (dx != 0 || dy != 0) {
-    // transposed table: MT[i][j] = sig_i sig_j M[j][i]
-    int ii = transpose ? j : i, jj = transpose ? i : j;
     const double X = pitch * dx, Y = pitch * dy;
-    const double r = sqrt(X * X + Y * Y);
-    const double phi = atan2(Y, X);
-    double hr[QMAX + 1], hi[QMAX + 1];
-    hankel_up(k * r, qmax, hr, hi);
-    const int Q = QMAX + 1;
-    const double* cf = coef + ((((size_t)c * SLOTS + ii) * SLOTS + jj) * Q) * 2;
-    double sr = 0.0, si = 0.0;
-    for (int q = 0; q <= qmax; ++q) {
-      const double ar = cf[2 * q], ai = cf[2 * q + 1];
-      sr += ar * hr[q] - ai * hi[q];
-      si += ar * hi[q] + ai * hr[q];
-    }
-    double ps, pc;
-    sincos((double)dm[(c * SLOTS + ii) * SLOTS + jj] * phi, &ps, &pc);
-    re = sr * pc - si * ps;
-    im = sr * ps + si * pc;
-    if (transpose) {
-      const double sg = (double)(sig[c * SLOTS + i] * sig[c * SLOTS + j]);
-      re *= sg;
-      im *= sg;
+    phi = atan2(Y, X);
+    hankel_up(k * sqrt(X * X + Y * Y), qmax, hr, hi);
+  }
+  for (int q = 0; q <= QMAX; ++q) rd[q] = c128{q <= qmax ? hr[q] : 0.0, q <= qmax ? hi[q] : 0.0};
+  for (int mu = -QMAX; mu <= QMAX; ++mu) {
+    double s, c;
+    sincos((double)mu * phi, &s, &c);
+    ad[mu + QMAX] = c128{c, s};
+  }
+}
+
+// Thread = (class, target slot, source slot) entry of every block; the
+// workgroups stride over the displacements, the entry's coefficients stay
+// in registers: entry(d) = e^{i dm phi(d)} sum_q coef_q h_q(k|d|).
+constexpr int TB_UNROLL = 4;
+__global__ __launch_bounds__(512) void build_table_kernel(
+    const double* __restrict__ coef, const int* __restrict__ dm, const int* __restrict__ sig,
+    const c128* __restrict__ rad, const c128* __restrict__ ang, c128* __restrict__ tab64,
+    c64* __restrict__ tab32, int tnx, int tny, long long D, int qmax, int transpose) {
+  const int c = threadIdx.x >> 8;
+  const int i = (threadIdx.x >> 4) & 15;
+  const int j = threadIdx.x & 15;
+  // transposed table: MT[i][j] = sig_i sig_j M[j][i]
+  const int ii = transpose ? j : i, jj = transpose ? i : j;
+  const int Q = QMAX + 1;
+  const double* cf = coef + ((((size_t)c * SLOTS + ii) * SLOTS + jj) * Q) * 2;
+  double ar[QMAX + 1], ai[QMAX + 1];
+#pragma unroll
+  for (int q = 0; q <= QMAX; ++q) {
+    ar[q] = q <= qmax ? cf[2 * q] : 0.0;
+    ai[q] = q <= qmax ? cf[2 * q + 1] : 0.0;
+  }
+  const int mu = dm[(c * SLOTS + ii) * SLOTS + jj] + QMAX;
+  const double sg = transpose ? (double)(sig[c * SLOTS + i] * sig[c * SLOTS + j]) : 1.0;
+  const int wx = 2 * tnx - 1;
+  const long long center = (long long)(tny - 1) * wx + (tnx - 1);  // d of (0, 0)
+  for (long long d0 = blockIdx.x; d0 < D; d0 += (long long)gridDim.x * TB_UNROLL) {
+#pragma unroll
+    for (int u = 0; u < TB_UNROLL; ++u) {
+      const long long d = d0 + (long long)u * gridDim.x;
+      if (d >= D) break;
+      const c128* rd = rad + d * Q;
+      double sr = 0.0, si = 0.0;
+#pragma unroll
+      for (int q = 0; q <= QMAX; ++q) {
+        const c128 h = rd[q];
+        sr += ar[q] * h.re - ai[q] * h.im;
+        si += ar[q] * h.im + ai[q] * h.re;
+      }
+      const c128 e = ang[d * (2 * QMAX + 1) + mu];
+      double re = sg * (sr * e.re - si * e.im), im = sg * (sr * e.im + si * e.re);
+      if (d == center) re = im = 0.0;
+      const size_t out = ((size_t)d * NCLASS + c) * SLOTS * SLOTS + (size_t)i * SLOTS + j;
+      tab64[out] = c128{re, im};
+      tab32[out] = c64{(float)re, (float)im};
     }
   }
-  tab64[out] = c128{re, im};
-  tab32[out] = c64{(float)re, (float)im};
 }
 
 static int build_impl(tm_ctx* c, DevBuf& t64, DevBuf& t32, int transpose) {
@@ -243,24 +276,32 @@ static int build_impl(tm_ctx* c, DevBuf& t64, DevBuf& t32, int transpose) {
   if ((rc = ensure(c, t32, (size_t)D * blk * sizeof(c64))) != TM_OK) return rc;
   double* dcoef = nullptr;
   int *ddm = nullptr, *dsig = nullptr;
+  c128 *rad = nullptr, *ang = nullptr;
   TM_HIP(c, hipMalloc((void**)&dcoef, coef.size() * sizeof(double)));
   TM_HIP(c, hipMalloc((void**)&ddm, dm.size() * sizeof(int)));
   TM_HIP(c, hipMalloc((void**)&dsig, sig.size() * sizeof(int)));
+  TM_HIP(c, hipMalloc((void**)&rad, (size_t)D * (QMAX + 1) * sizeof(c128)));
+  TM_HIP(c, hipMalloc((void**)&ang, (size_t)D * (2 * QMAX + 1) * sizeof(c128)));
   TM_HIP(c, hipMemcpyAsync(dcoef, coef.data(), coef.size() * sizeof(double),
                            hipMemcpyHostToDevice, c->stream));
   TM_HIP(c, hipMemcpyAsync(ddm, dm.data(), dm.size() * sizeof(int), hipMemcpyHostToDevice,
                            c->stream));
   TM_HIP(c, hipMemcpyAsync(dsig, sig.data(), sig.size() * sizeof(int), hipMemcpyHostToDevice,
                            c->stream));
-  hipLaunchKernelGGL(build_table_kernel, dim3((unsigned)D), dim3(512), 0, c->stream, dcoef, ddm,
-                     dsig, (c128*)t64.p, (c64*)t32.p, g.tnx, g.tny, g.pitch, g.k, 2 * g.lmax,
-                     transpose);
+  hipLaunchKernelGGL(table_radial_kernel, dim3((unsigned)((D + 255) / 256)), dim3(256), 0, c->stream,
+                     g.tnx, g.tny, g.pitch, g.k, 2 * g.lmax, D, rad, ang);
+  const unsigned nwg = (unsigned)std::min<long long>(D, 4096);
+  hipLaunchKernelGGL(build_table_kernel, dim3(nwg), dim3(512), 0, c->stream, dcoef, ddm, dsig,
+                     (const c128*)rad, (const c128*)ang, (c128*)t64.p, (c64*)t32.p, g.tnx, g.tny, D,
+                     2 * g.lmax, transpose);
   TM_HIP(c, hipGetLastError());
   // the host vectors above are read by the async copies; wait before they go
   TM_HIP(c, hipStreamSynchronize(c->stream));
   TM_HIP(c, hipFree(dcoef));
   TM_HIP(c, hipFree(ddm));
   TM_HIP(c, hipFree(dsig));
+  TM_HIP(c, hipFree(rad));
+  TM_HIP(c, hipFree(ang));
   return TM_OK;
 }
 
