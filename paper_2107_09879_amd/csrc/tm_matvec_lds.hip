@@ -459,12 +459,31 @@ __global__ void lds_combine_kernel(const cplx<T>* __restrict__ partial, const in
     tile = tl.n_reg + (wy >> 2) * tl.tiles_xw + sx / (4 * TW);
     ls = (wy & 3) * (4 * TW) + (sx % (4 * TW));
   }
-  double sr = 0.0, si = 0.0;
-  for (int i = ibeg[tile]; i < ibeg[tile + 1]; ++i) {
-    const cplx<T> v = partial[(((size_t)i * (2 * R) + rc) * (TW * 16) + ls) * SLOTS + slot];
-    sr += (double)v.re;
-    si += (double)v.im;
+  // the tile's items in a fixed order, eight loads in flight and two
+  // accumulator pairs (deterministic)
+  const size_t stride = (size_t)(2 * R) * (TW * 16) * SLOTS;
+  const cplx<T>* pp = partial + ((size_t)rc * (TW * 16) + ls) * SLOTS + slot;
+  const int i1 = ibeg[tile + 1];
+  double sr0 = 0.0, si0 = 0.0, sr1 = 0.0, si1 = 0.0;
+  int i = ibeg[tile];
+  for (; i + 8 <= i1; i += 8) {
+    cplx<T> v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = pp[(size_t)(i + u) * stride];
+#pragma unroll
+    for (int u = 0; u < 8; u += 2) {
+      sr0 += (double)v[u].re;
+      si0 += (double)v[u].im;
+      sr1 += (double)v[u + 1].re;
+      si1 += (double)v[u + 1].im;
+    }
   }
+  for (; i < i1; ++i) {
+    const cplx<T> v = pp[(size_t)i * stride];
+    sr0 += (double)v.re;
+    si0 += (double)v.im;
+  }
+  const double sr = sr0 + sr1, si = si0 + si1;
   c128 o;
   if (mode == (int)Op::Forward) {
     const c128 tv = t[idx % vec];
