@@ -158,12 +158,30 @@ __global__ void b_combine(const cplx<T>* __restrict__ partial, const int* __rest
   const int tile = p.pad0 + (sy >> 4) * p.tiles_x + sx / TW;
   const int ls = (sy & 15) * TW + (sx % TW);
   const int rc = r * NCLASS + cls;
-  double sr = 0.0, si = 0.0;
-  for (int i = ibeg[tile]; i < ibeg[tile + 1]; ++i) {
-    const cplx<T> v = partial[(((size_t)i * (2 * R) + rc) * (TW * 16) + ls) * SLOTS + slot];
-    sr += (double)v.re;
-    si += (double)v.im;
+  // the tile's items in a fixed order, eight loads in flight (deterministic)
+  const size_t stride = (size_t)(2 * R) * (TW * 16) * SLOTS;
+  const cplx<T>* pp = partial + ((size_t)rc * (TW * 16) + ls) * SLOTS + slot;
+  const int i1 = ibeg[tile + 1];
+  double sr0 = 0.0, si0 = 0.0, sr1 = 0.0, si1 = 0.0;
+  int i = ibeg[tile];
+  for (; i + 8 <= i1; i += 8) {
+    cplx<T> v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = pp[(size_t)(i + u) * stride];
+#pragma unroll
+    for (int u = 0; u < 8; u += 2) {
+      sr0 += (double)v[u].re;
+      si0 += (double)v[u].im;
+      sr1 += (double)v[u + 1].re;
+      si1 += (double)v[u + 1].im;
+    }
   }
+  for (; i < i1; ++i) {
+    const cplx<T> v = pp[(size_t)i * stride];
+    sr0 += (double)v.re;
+    si0 += (double)v.im;
+  }
+  const double sr = sr0 + sr1, si = si0 + si1;
   const long long fs = (long long)(p.oy + sy) * nxf + (p.ox + sx);
   const c128 tv = t[((long long)cls * Nf + fs) * SLOTS + slot];
   const c128 xv = x[e];

@@ -468,3 +468,44 @@ def test_full_size_c2_sampled_rows_and_solve():
     r_rows = s[rows] - t * oracle.rows_A(pos, K, lmax, s, rows) - b
     assert np.linalg.norm(r_rows) / np.linalg.norm(b) < 1e-6
     ctx.close()
+
+
+def test_full_size_c5_sampled_rows():
+    """300 x 300 lens tile, lmax 3, 2 RHS, in the launch configuration the
+    tile benchmark times (both block-matvec precisions): sampled rows of the
+    coupling operator against the oracle's row-by-row product."""
+    print("[case] full-size c5", flush=True)
+    pos, radii, kh, po, cfg = wl.config_inputs("c5")
+    n, lmax, R = cfg["nx"], cfg["lmax"], 2
+    ctx = tmhip.Context(0)
+    ctx.set_geometry(pos, K, lmax)
+    ctx.set_spheres(to_dev(radii, torch.float64), wl.N_REL)
+    ctx.set_matvec_config("mixed", 9, 32768 // (2 * R))
+    ctx.set_matvec_config("fp64", 8, 16384 // (2 * R))
+    x = rand_vec(np.random.default_rng(300), R, n * n, 30)
+    y64 = host(ctx.apply_operator(to_dev(x), "coupling", "fp64"))
+    y32 = host(ctx.apply_operator(to_dev(x), "coupling", "mixed"))
+    # a corner, the last site, and sites in the last (4-row) band and the centre
+    for r, rows in ((0, [0, n * n - 1]), (1, [n * (n - 3) + 150, n * 150 + 149])):
+        ref = oracle.rows_A(pos, K, lmax, x[r], rows)
+        assert rel(y64[r][rows], ref) < 1e-12, (r, rows)
+        assert rel(y32[r][rows], ref) < 2e-5, (r, rows)
+    ctx.close()
+
+
+def test_full_size_c4_transposed_rows():
+    """150 x 150 lattice, lmax 3 (the adjoint workload): sampled rows of the
+    transposed coupling operator the adjoint solve applies."""
+    print("[case] full-size c4", flush=True)
+    pos, radii, kh, po, cfg = wl.config_inputs("c4")
+    n, lmax = cfg["nx"], cfg["lmax"]
+    ctx = tmhip.Context(0)
+    ctx.set_geometry(pos, K, lmax)
+    ctx.set_spheres(to_dev(radii, torch.float64), wl.N_REL)
+    x = rand_vec(np.random.default_rng(150), 1, n * n, 30)
+    rows = [0, n * 75 + 74, n * n - 1]
+    ref = oracle.rows_A(pos, K, lmax, x[0], rows, transpose=True)
+    for prec, tol in (("fp64", 1e-12), ("mixed", 2e-5)):
+        y = host(ctx.apply_operator(to_dev(x), "coupling_t", prec))[0]
+        assert rel(y[rows], ref) < tol, prec
+    ctx.close()
