@@ -189,6 +189,13 @@ class Context:
         except Exception:
             pass
 
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
+
     # ---- set-up
     def set_geometry(self, positions, k, lmax):
         pos = np.ascontiguousarray(positions, dtype=np.float64)
