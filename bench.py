@@ -116,6 +116,13 @@ def main():
                     help="c5: Arnoldi steps of the bounded solve used for the extrapolation")
     ap.add_argument("--tile-rhs", type=int, default=-1,
                     help="c5: solve only this right-hand side (0 or 1) to the tolerance and time it")
+    ap.add_argument("--tile-precision", default="mixed", choices=["mixed", "fp64"],
+                    help="c5: precision of the --tile-rhs solve")
+    ap.add_argument("--tile-max-iter", type=int, default=20000,
+                    help="c5: Arnoldi steps allowed to the --tile-rhs solve (a multiple of the restart "
+                         "ends it on a cycle boundary, where a later run can resume exactly)")
+    ap.add_argument("--tile-x0", default="", help="c5: .npy start vector of the --tile-rhs solve")
+    ap.add_argument("--tile-save", default="", help="c5: .npy file for the --tile-rhs solution")
     ap.add_argument("--matvec-config", action="append", default=[], metavar="PREC:VARIANT:ITEMS",
                     help="fix the block-matvec kernel of a precision (mixed or fp64) instead of "
                          "autotuning it, e.g. mixed:9:16384")
@@ -340,11 +347,17 @@ def bench_tile(args):
     if full:  # one right-hand side to the tolerance (the solver treats them independently)
         kh, po = kh[args.tile_rhs:args.tile_rhs + 1], po[args.tile_rhs:args.tile_rhs + 1]
     a0 = ctx.plane_wave_rhs(kh, po)
+    restart = args.restart or cfg["restart"]
+    prec = args.tile_precision if full else "mixed"
+    x0 = None
+    if full and args.tile_x0:  # resume from a saved iterate (exact on a restart-cycle boundary)
+        x0 = torch.tensor(np.load(args.tile_x0), dtype=torch.complex128, device="cuda")
     torch.cuda.synchronize()
     t_start[0] = time.perf_counter()
-    restart = args.restart or cfg["restart"]
-    s, info = ctx.solve(a0, tol=cfg["tol"], restart=restart, precision="mixed",
-                        max_iter=20000 if full else args.tile_iters)
+    s, info = ctx.solve(a0, x0=x0, tol=cfg["tol"], restart=restart, precision=prec,
+                        max_iter=args.tile_max_iter if full else args.tile_iters)
+    if full and args.tile_save:
+        np.save(args.tile_save, s.cpu().numpy())
     torch.cuda.synchronize()
     t_solve = time.perf_counter() - t_start[0]
     ctx.set_progress(None)
@@ -371,7 +384,9 @@ def bench_tile(args):
                                            "restart": restart},
            "table_build_s": t_table, "matvec": mv,
            "bounded_solve": None if full else {"max_iter": args.tile_iters, "time_s": t_solve, "info": info},
-           "solve_one_rhs": {"rhs": args.tile_rhs, "time_to_solution_s": t_solve, "info": info} if full else None,
+           "solve_one_rhs": {"rhs": args.tile_rhs, "precision": prec, "resumed": bool(args.tile_x0),
+                             "max_iter": args.tile_max_iter, "time_s": t_solve, "info": info}
+           if full else None,
            "time_to_solution_extrapolated": None if full else extrap, "near_field": nf,
            "roofline": {"bound": "mfma", "achieved": mv["mixed"]["tflops"], "peak": PEAK_FP32_MFMA,
                         "unit": "TFLOP/s", "frac": mv["mixed"]["frac"], "traffic": None,
