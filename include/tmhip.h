@@ -65,7 +65,11 @@ typedef enum {
 /* ---- context ------------------------------------------------------------ */
 
 /* Create a context on HIP device `device`, enqueuing on `hip_stream`
- * (a hipStream_t; NULL = the device's null stream). */
+ * (a hipStream_t; NULL = the device's null stream).  The block matvec also
+ * runs one of its launches on a second stream of default priority that the
+ * context creates on first use and releases in tm_destroy; that launch is
+ * ordered after earlier work on `hip_stream`, and later work on `hip_stream`
+ * waits for it, so ordering on `hip_stream` is as if everything ran there. */
 int tm_create(tm_ctx** ctx, int device, void* hip_stream);
 void tm_destroy(tm_ctx* ctx);
 const char* tm_status_string(int status);

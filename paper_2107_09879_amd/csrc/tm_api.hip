@@ -293,6 +293,12 @@ void tm_destroy(tm_ctx* c) {
                         &c->plan_ibeg[0], &c->plan_ibeg[1]})
     tmh::release(*b);
   if (c->host_pinned) hipHostFree(c->host_pinned);
+  if (c->side) {
+    hipStreamSynchronize(c->side);
+    hipStreamDestroy(c->side);
+  }
+  if (c->ev_fork) hipEventDestroy(c->ev_fork);
+  if (c->ev_join) hipEventDestroy(c->ev_join);
   for (int w = 0; w < 2; ++w)
     for (auto& pr : c->prof_pending[w]) {
       hipEventDestroy(pr.first);

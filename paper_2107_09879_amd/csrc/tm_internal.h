@@ -82,6 +82,10 @@ struct ProfAcc {
 struct tm_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
+  // second stream (default priority) for the wide-tile launch of the block
+  // matvec, forked from and joined back into `stream` by the two events
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   std::string err;
   tm_progress_fn progress = nullptr;  // optional per-cycle callback
   void* progress_user = nullptr;

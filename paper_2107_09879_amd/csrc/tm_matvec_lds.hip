@@ -583,15 +583,29 @@ int lds_apply(tm_ctx* c, int which, int R, const void* table, const void* xin, c
   a.tile_base = 0;
   a.item_base = 0;
   const int nreg = c->plan_nreg[which];
-  if (e0) TM_HIP(c, hipEventRecord(e0, c->stream));
-  lds_launch_any<T, false>(c->stream, pf, nreg, R, a);
-  // the last ny mod 16 rows: wide tiles
+  // the last ny mod 16 rows: wide tiles, launched on the side stream so that
+  // their work groups fill the CUs the regular launch leaves idle at its tail
+  // (the two write disjoint partial-sum slots; the combine waits for both)
   LdsArgs aw = a;
   aw.tiles_x = tl.tiles_xw;
   aw.y_base = tl.y_wide;
   aw.tile_base = tl.n_reg;
   aw.item_base = nreg;
-  lds_launch_any<T, true>(c->stream, pf, nitems - nreg, R, aw);
+  const bool wide = nitems > nreg;
+  if (wide && !c->side) {
+    TM_HIP(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+    TM_HIP(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+    TM_HIP(c, hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+  }
+  if (e0) TM_HIP(c, hipEventRecord(e0, c->stream));
+  if (wide) {
+    TM_HIP(c, hipEventRecord(c->ev_fork, c->stream));
+    TM_HIP(c, hipStreamWaitEvent(c->side, c->ev_fork, 0));
+    lds_launch_any<T, true>(c->side, pf, nitems - nreg, R, aw);
+    TM_HIP(c, hipEventRecord(c->ev_join, c->side));
+  }
+  lds_launch_any<T, false>(c->stream, pf, nreg, R, a);
+  if (wide) TM_HIP(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
   if (e1) TM_HIP(c, hipEventRecord(e1, c->stream));
   if (y) {
     const int nb = (int)((total + 255) / 256);
