@@ -592,10 +592,20 @@ int lds_apply(tm_ctx* c, int which, int R, const void* table, const void* xin, c
   aw.tile_base = tl.n_reg;
   aw.item_base = nreg;
   const bool wide = nitems > nreg;
-  if (wide && !c->side) {
-    TM_HIP(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
-    TM_HIP(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
-    TM_HIP(c, hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+  if (wide && !c->ev_join) {  // created once; each handle is kept only once created
+    if (!c->side) {
+      hipStream_t s = nullptr;
+      TM_HIP(c, hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+      c->side = s;
+    }
+    if (!c->ev_fork) {
+      hipEvent_t e = nullptr;
+      TM_HIP(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      c->ev_fork = e;
+    }
+    hipEvent_t e = nullptr;
+    TM_HIP(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    c->ev_join = e;
   }
   if (e0) TM_HIP(c, hipEventRecord(e0, c->stream));
   if (wide) {
