@@ -99,6 +99,39 @@ def test_operator_is_deterministic():
 
 
 # ----------------------------------------------------------------- set-up kernels
+def test_lds_matvec_chains_on_a_user_stream_without_host_syncs():
+    """The remainder-row (wide-tile) launch runs on the context's second
+    stream.  It must follow earlier work on the caller's stream and precede
+    later work there: two chained products on a private stream, with every
+    LDS variant and a lattice whose height leaves two remainder rows, are
+    synchronised only at the end."""
+    print("[case] lds chain on a user stream", flush=True)
+    nx, ny, lmax = 20, 18, 3
+    rng = np.random.default_rng(2018)
+    L = oracle.n_coeffs(lmax)
+    x = rand_vec(rng, 1, nx * ny, L)
+    lc = oracle.LatticeCoupling(nx, ny, wl.PITCH, K, lmax)
+    ref1 = lc.apply(x[0])
+    ref2 = lc.apply(ref1)
+    st = torch.cuda.Stream(device=DEV)
+    out = {}
+    with torch.cuda.stream(st):
+        ctx, pos, radii = make_ctx(nx, ny, lmax)
+        xd = to_dev(x)
+        for prec in ("fp64", "mixed"):
+            for v in (8, 9, 10):
+                ctx.set_matvec_config(prec, v, 0)
+                y1 = ctx.apply_operator(xd, "coupling", prec)
+                y2 = ctx.apply_operator(y1, "coupling", prec)
+                out[prec, v] = (y1, y2)
+    st.synchronize()
+    for (prec, v), (y1, y2) in out.items():
+        tol = 1e-12 if prec == "fp64" else 2e-5
+        assert rel(y1.cpu().numpy()[0], ref1) < tol, (prec, v)
+        assert rel(y2.cpu().numpy()[0], ref2) < 2 * tol, (prec, v)
+    ctx.close()
+
+
 def test_mie_and_plane_wave_match_oracle():
     ctx, pos, radii = make_ctx(7, 6, 3, lo=0.12, hi=0.28, seed=5)
     t, dt = ctx.get_tmatrix_diag()
