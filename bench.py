@@ -110,6 +110,9 @@ def main():
     ap.add_argument("--subregions", type=int, default=0, help="c3: use only the first K subregions")
     ap.add_argument("--no-sequential", action="store_true",
                     help="c3: skip the one-subregion-at-a-time comparison")
+    ap.add_argument("--no-batch-autotune", action="store_true",
+                    help="c3: keep the batched path's default launch configuration instead of "
+                         "timing the candidates on the batch first")
     ap.add_argument("--restart", type=int, default=0,
                     help="c3, c5: GMRES restart length (default: the workload's, 50)")
     ap.add_argument("--tile-iters", type=int, default=300,
@@ -450,6 +453,7 @@ def bench_batched(args):
     ctx = tmhip.Context(0)
     ctx.set_geometry(pos, wl.K, cfg["lmax"])
     ctx.set_spheres(torch.tensor(radii, dtype=torch.float64, device="cuda"), wl.N_REL)
+    ctx.set_batch_autotune(not args.no_batch_autotune)
     res = {}
     precs = ["mixed"] if args.no_fp64 else ["mixed", "fp64"]
     for prec in precs:
@@ -461,7 +465,10 @@ def bench_batched(args):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         flat = [i for row in info for i in row]
+        pf, items = ctx.batch_config(prec)
         res[prec] = {"time_s": dt, "graph": ctx.batch_graph_used(),
+                     "launch": {"autotuned": not args.no_batch_autotune, "prefetch": pf,
+                                "items_per_rhs_class": items},
                      "iters_max": max(i["iters"] for i in flat),
                      "iters_mean": float(np.mean([i["iters"] for i in flat])),
                      "converged": sum(i["status"] == 0 for i in flat), "systems": len(flat),

@@ -219,6 +219,22 @@ int tm_solve_batched(tm_ctx* ctx, int n_sub, const tm_subregion* subs, int n_rhs
  * captured hipGraph, 0 if it ran them eagerly. */
 int tm_batch_graph_used(const tm_ctx* ctx);
 
+/* Batched autotuner (the work items of the batched path, App. I.D's
+ * subregion jobs sharing one launch).  on = 1: every later tm_solve_batched
+ * first times one batched matvec, all systems active, for each table
+ * prefetch depth (1..3 complex64, 1..2 FP64) and work split (16k, 32k, 64k
+ * workgroups), in the precision of its Arnoldi steps, and keeps the fastest
+ * (18 or 12 extra matvecs, synchronous).  on = 0 (default): about 32k
+ * workgroups and the prefetch depth of the context's matvec variant
+ * (tm_set_matvec_config; depth 1 for variants 0..7).  Every configuration
+ * computes the same product up to rounding. */
+int tm_set_batch_autotune(tm_ctx* ctx, int on);
+
+/* Launch configuration the last tm_solve_batched used for `precision`
+ * (TM_PREC_FP64 or TM_PREC_MIXED): table prefetch depth and work items per
+ * (rhs, class) pair; both 0 before the first batched solve. */
+int tm_get_batch_config(const tm_ctx* ctx, int precision, int* prefetch, int* items);
+
 /* ---- readout ------------------------------------------------------------- */
 
 /* Scattered field E_sca(x) = sum_i s_i^T Phi(k(x - x_i)) (App. I.C, eq.

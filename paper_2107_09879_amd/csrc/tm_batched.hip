@@ -33,7 +33,7 @@ void lds_split(const std::vector<std::vector<double>>& wb, double per, int sub,
                std::vector<LdsItem>& items, std::vector<int>& ibeg);
 template <typename T>
 int lds_launch(tm_ctx* c, const void* table, const void* xin, void* partial, const LdsItem* items,
-               int nitems, int R, const SubParams* subs, const int* active, const int* done);
+               int nitems, int R, const SubParams* subs, const int* active, const int* done, int pf);
 template <typename T>
 void lds_geometry(int& TW, int& BX, int& BY);
 
@@ -478,7 +478,10 @@ struct Batch {
   // device
   DevBuf d_sp[2], d_out_off, d_items[2], d_ibeg[2], d_blocks, d_sysblk;
   const SubParams* sp_cur = nullptr;  // subregion table of the precision in use
+  std::vector<SubParams> sp_host[2];  // host copies per precision slot (0 FP64, 1 c64)
   int nitems[2] = {0, 0};
+  int pf[2] = {1, 1};        // table prefetch depth of the LDS kernel per slot
+  int items_tgt[2] = {0, 0};  // work items per (rhs, class) the plan was cut for
   int nblocks = 0;
   DevBuf b, x, r, w, V, xlow, partial, dots1, dots2, dpart, npart, hn, beta, bnorm, target, y;
   DevBuf H, cs, sn, g, jend, active, live, done;
@@ -510,17 +513,16 @@ struct Batch {
 
 static int ensure_b(tm_ctx* c, DevBuf& b, size_t bytes) { return ensure(c, b, bytes); }
 
+// Equal-work items over all subregions for precision slot w, about `target`
+// items per (rhs, class) pair; the partial-sum buffer is grown to fit.
 template <typename T>
-static int plan_precision(tm_ctx* c, Batch& B, int w) {
+static int plan_precision(tm_ctx* c, Batch& B, int w, int target) {
   int TW, BX, BY;
   lds_geometry<T>(TW, BX, BY);
+  const std::vector<SubParams>& sp = B.sp_host[w];
   std::vector<std::vector<std::vector<double>>> wbs(B.S);
   double total = 0.0;
-  for (int k = 0; k < B.S; ++k)
-    total += lds_block_work(B.subs[k].nx, B.subs[k].ny, TW, BX, BY, 64, wbs[k]);
-  // many small equal-work items: the LDS kernel runs best near one
-  // displacement block per workgroup
-  const int target = std::max(1, 32768 / (2 * B.R));
+  for (int k = 0; k < B.S; ++k) total += lds_block_work(sp[k].nx, sp[k].ny, TW, BX, BY, 64, wbs[k]);
   std::vector<LdsItem> items;
   std::vector<int> ibeg;
   for (int k = 0; k < B.S; ++k) lds_split(wbs[k], total / target, k, items, ibeg);
@@ -531,7 +533,9 @@ static int plan_precision(tm_ctx* c, Batch& B, int w) {
   TM_HIP(c, hipMemcpy(B.d_items[w].p, items.data(), items.size() * sizeof(LdsItem), hipMemcpyHostToDevice));
   TM_HIP(c, hipMemcpy(B.d_ibeg[w].p, ibeg.data(), ibeg.size() * sizeof(int), hipMemcpyHostToDevice));
   B.nitems[w] = (int)items.size();
-  return TM_OK;
+  B.items_tgt[w] = target;
+  const size_t pbytes = (size_t)B.nitems[w] * 2 * B.R * TW * 16 * SLOTS * sizeof(cplx<T>);
+  return ensure_b(c, B.partial, pbytes);
 }
 
 static inline unsigned nbk(long long n) { return (unsigned)((n + BT - 1) / BT); }
@@ -549,7 +553,7 @@ static int b_apply(tm_ctx* c, Batch& B, const c128* xin, c128* yout, const int* 
   }
   int rc = lds_launch<T>(c, w ? c->tab32.p : c->tab64.p, src, B.partial.p,
                          (const LdsItem*)B.d_items[w].p, B.nitems[w], B.R,
-                         B.sp_cur, act, done);
+                         B.sp_cur, act, done, B.pf[w]);
   if (rc != TM_OK) return rc;
   hipLaunchKernelGGL(b_combine<T>, dim3(nbk(B.total)), dim3(BT), 0, c->stream,
                      (const cplx<T>*)B.partial.p, (const int*)B.d_ibeg[w].p,
@@ -621,6 +625,58 @@ static int b_norms(tm_ctx* c, Batch& B, const c128* v, const int* act, std::vect
                            c->stream));
   TM_HIP(c, hipStreamSynchronize(c->stream));
   return TM_OK;
+}
+
+// Batched autotuner: one batched matvec with every system active per
+// candidate (table prefetch depth x work split), the first launch of each
+// untimed, the fastest kept.  Input and output are scratch vectors (the
+// zeroed basis and w): timing does not depend on the values.
+template <typename T>
+static int b_autotune(tm_ctx* c, Batch& B) {
+  const int w = std::is_same<T, double>::value ? 0 : 1;
+  std::vector<int> ones(B.nsys, 1);
+  TM_HIP(c, hipMemcpy(B.live.p, ones.data(), B.nsys * sizeof(int), hipMemcpyHostToDevice));
+  hipEvent_t e0, e1;
+  TM_HIP(c, hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return set_err(c, TM_ERR_HIP, "event creation for the batched autotuner failed");
+  }
+  const int pfmax = w ? 3 : 2;
+  const int wg_targets[] = {16384, 32768, 65536};
+  float best = 1e30f;
+  int best_pf = B.pf[w], best_tgt = B.items_tgt[w];
+  int rc = TM_OK;
+  bool timing_failed = false;
+  for (int wg : wg_targets) {
+    const int tgt = std::max(1, wg / (2 * B.R));
+    if ((rc = plan_precision<T>(c, B, w, tgt)) != TM_OK) break;
+    for (int pf = 1; pf <= pfmax && rc == TM_OK && !timing_failed; ++pf) {
+      B.pf[w] = pf;
+      float ms = 0.f;
+      for (int rep = 0; rep < 2 && rc == TM_OK && !timing_failed; ++rep) {
+        timing_failed = hipEventRecord(e0, c->stream) != hipSuccess;
+        if (!timing_failed)
+          rc = b_apply<T>(c, B, (const c128*)B.V.p, (c128*)B.w.p, (const int*)B.live.p, nullptr);
+        if (rc == TM_OK && !timing_failed)
+          timing_failed = hipEventRecord(e1, c->stream) != hipSuccess ||
+                          hipEventSynchronize(e1) != hipSuccess ||
+                          hipEventElapsedTime(&ms, e0, e1) != hipSuccess;
+      }
+      if (rc == TM_OK && !timing_failed && ms < best) {
+        best = ms;
+        best_pf = pf;
+        best_tgt = tgt;
+      }
+    }
+    if (timing_failed) break;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc != TM_OK) return rc;
+  if (timing_failed) return set_err(c, TM_ERR_HIP, "timing in the batched autotuner failed");
+  B.pf[w] = best_pf;
+  return plan_precision<T>(c, B, w, best_tgt);
 }
 
 template <typename T>
@@ -759,12 +815,15 @@ static int batched_impl(tm_ctx* c, int S, const tm_subregion* subs, int R, const
   TM_HIP(c, hipMemcpy(B.d_sp[1].p, sp32.data(), S * sizeof(SubParams), hipMemcpyHostToDevice));
   TM_HIP(c, hipMemcpy(B.d_sp[0].p, sp64.data(), S * sizeof(SubParams), hipMemcpyHostToDevice));
   B.subs = sp32;
-  if ((rc = plan_precision<float>(c, B, 1)) != TM_OK) return rc;
-  B.subs = sp64;
-  if ((rc = plan_precision<double>(c, B, 0)) != TM_OK) return rc;
-  size_t pbytes = std::max((size_t)B.nitems[1] * 2 * R * TW * 16 * SLOTS * sizeof(c64),
-                           (size_t)B.nitems[0] * 2 * R * TW64 * 16 * SLOTS * sizeof(c128));
-  if ((rc = ensure_b(c, B.partial, pbytes)) != TM_OK) return rc;
+  B.sp_host[1] = sp32;
+  B.sp_host[0] = sp64;
+  // default launch configuration: many small equal-work items (the LDS kernel
+  // runs best near one displacement block per workgroup, about 32k
+  // workgroups per launch) and the context's prefetch depth
+  for (int w = 0; w < 2; ++w) B.pf[w] = std::max(1, c->mv_variant[w] - 7);
+  const int tgt0 = std::max(1, 32768 / (2 * R));
+  if ((rc = plan_precision<float>(c, B, 1, tgt0)) != TM_OK) return rc;
+  if ((rc = plan_precision<double>(c, B, 0, tgt0)) != TM_OK) return rc;
   if ((rc = ensure_pinned(c, 4096)) != TM_OK) return rc;
   auto use_sp = [&](int w) {
     B.sp_cur = (const SubParams*)B.d_sp[w].p;
@@ -788,6 +847,21 @@ static int batched_impl(tm_ctx* c, int S, const tm_subregion* subs, int R, const
   hipLaunchKernelGGL(b_fill, dim3(nbk((long long)(m + 1) * Lt)), dim3(BT), 0, c->stream, (c128*)B.V.p,
                      (long long)(m + 1) * Lt);
   TM_HIP(c, hipMemcpyAsync(B.r.p, B.b.p, Lt * cb, hipMemcpyDeviceToDevice, c->stream));
+  // the Arnoldi precision's launch configuration, timed on this batch
+  if (c->batch_autotune) {
+    if (o.precision == TM_PREC_MIXED) {
+      use_sp(1);
+      rc = b_autotune<float>(c, B);
+    } else {
+      use_sp(0);
+      rc = b_autotune<double>(c, B);
+    }
+    if (rc != TM_OK) return rc;
+  }
+  for (int w = 0; w < 2; ++w) {
+    c->batch_pf[w] = (w == 0) ? std::min(B.pf[w], 2) : std::min(B.pf[w], 3);
+    c->batch_items[w] = B.items_tgt[w];
+  }
   std::vector<int> live(ns, 1), iters(ns, 0), cycles(ns, 0), mv64(ns, 0), mvlo(ns, 0);
   std::vector<double> relres(ns, 0.0);
   for (int s = 0; s < ns; ++s) {
@@ -894,6 +968,21 @@ static int batched_impl(tm_ctx* c, int S, const tm_subregion* subs, int R, const
 }
 
 }  // namespace tmh
+
+extern "C" int tm_set_batch_autotune(tm_ctx* c, int on) {
+  if (!c) return TM_ERR_INVALID_ARG;
+  c->batch_autotune = on ? 1 : 0;
+  return TM_OK;
+}
+
+extern "C" int tm_get_batch_config(const tm_ctx* c, int precision, int* prefetch, int* items) {
+  if (!c || !prefetch || !items || (precision != TM_PREC_FP64 && precision != TM_PREC_MIXED))
+    return TM_ERR_INVALID_ARG;
+  const int w = precision == TM_PREC_MIXED ? 1 : 0;
+  *prefetch = c->batch_pf[w];
+  *items = c->batch_items[w];
+  return TM_OK;
+}
 
 extern "C" int tm_solve_batched(tm_ctx* c, int n_sub, const tm_subregion* subs, int n_rhs,
                                 const double* khat, const tm_c128* pol, tm_c128* s_out,

@@ -117,6 +117,11 @@ struct tm_ctx {
   int plan_R[2] = {-1, -1}, plan_target[2] = {0, 0}, plan_nitems[2] = {0, 0};
   int plan_nreg[2] = {0, 0};  // LDS plan: items of regular tiles (wide-tile items follow)
   int last_batch_graphed = 0;
+  // batched solves: time the candidate launch configurations before solving
+  // (1) or use the fixed default (0); the configuration of the last batched
+  // solve per precision slot (table prefetch depth, items per (rhs, class))
+  int batch_autotune = 0;
+  int batch_pf[2] = {0, 0}, batch_items[2] = {0, 0};
 };
 
 namespace tmh {

@@ -636,11 +636,11 @@ void lds_geometry(int& TW, int& BX, int& BY) {
 template void lds_geometry<float>(int&, int&, int&);
 template void lds_geometry<double>(int&, int&, int&);
 
-// Launch the LDS kernel over a batched item list (no allocation, no host
-// synchronisation: safe under stream capture).
+// Launch the LDS kernel over a batched item list with table prefetch depth
+// pf (no allocation, no host synchronisation: safe under stream capture).
 template <typename T>
 int lds_launch(tm_ctx* c, const void* table, const void* xin, void* partial, const LdsItem* items,
-               int nitems, int R, const SubParams* subs, const int* active, const int* done) {
+               int nitems, int R, const SubParams* subs, const int* active, const int* done, int pf) {
   LdsArgs a;
   a.table = table;
   a.x = xin;
@@ -659,14 +659,13 @@ int lds_launch(tm_ctx* c, const void* table, const void* xin, void* partial, con
   a.y_base = 0;
   a.tile_base = 0;
   a.item_base = 0;
-  const int w = std::is_same<T, double>::value ? 0 : 1;
-  lds_launch_any<T>(c->stream, std::max(1, c->mv_variant[w] - 7), nitems, R, a);
+  lds_launch_any<T>(c->stream, pf, nitems, R, a);
   return TM_OK;
 }
 template int lds_launch<float>(tm_ctx*, const void*, const void*, void*, const LdsItem*, int, int,
-                               const SubParams*, const int*, const int*);
+                               const SubParams*, const int*, const int*, int);
 template int lds_launch<double>(tm_ctx*, const void*, const void*, void*, const LdsItem*, int, int,
-                                const SubParams*, const int*, const int*);
+                                const SubParams*, const int*, const int*, int);
 
 template int lds_apply<float>(tm_ctx*, int, int, const void*, const void*, const c128*, c128*, int,
                               int, hipEvent_t, hipEvent_t, int);

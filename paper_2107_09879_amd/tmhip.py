@@ -105,6 +105,8 @@ def load():
         "tm_solve_batched": (I, [P, I, P, I, P, P, P, ctypes.POINTER(SolveOpts),
                                  ctypes.POINTER(SolveInfo), I]),
         "tm_batch_graph_used": (I, [P]),
+        "tm_set_batch_autotune": (I, [P, I]),
+        "tm_get_batch_config": (I, [P, I, ctypes.POINTER(I), ctypes.POINTER(I)]),
         "tm_set_matvec_config": (I, [P, I, I, I]),
         "tm_get_matvec_config": (I, [P, I, ctypes.POINTER(I), ctypes.POINTER(I)]),
         "tm_autotune": (I, [P, I, I, ctypes.POINTER(D)]),
@@ -290,6 +292,16 @@ class Context:
 
     def batch_graph_used(self):
         return bool(self.lib.tm_batch_graph_used(self.h))
+
+    def set_batch_autotune(self, on=True):
+        self._check(self.lib.tm_set_batch_autotune(self.h, int(bool(on))))
+
+    def batch_config(self, precision):
+        """(table prefetch depth, items per (rhs, class)) of the last batched solve."""
+        pf, it = ctypes.c_int(), ctypes.c_int()
+        self._check(self.lib.tm_get_batch_config(self.h, PRECISIONS[precision], ctypes.byref(pf),
+                                                 ctypes.byref(it)))
+        return pf.value, it.value
 
     def apply_operator(self, x, op="forward", precision="fp64"):
         x = _dev(x, torch.complex128, "x")

@@ -427,11 +427,14 @@ def test_progress_callback_reports_every_cycle():
 SUBS = [(0, 0, 12, 9), (5, 3, 20, 16), (30, 20, 10, 10), (7, 7, 1, 1), (0, 0, 24, 20), (13, 2, 17, 5)]
 
 
-@pytest.mark.parametrize("precision,use_graph", [("fp64", False), ("fp64", True), ("mixed", True)])
-def test_batched_subregions_match_single_solves(precision, use_graph):
+@pytest.mark.parametrize("precision,use_graph,autotune",
+                         [("fp64", False, False), ("fp64", True, False), ("mixed", True, False),
+                          ("fp64", True, True), ("mixed", True, True)])
+def test_batched_subregions_match_single_solves(precision, use_graph, autotune):
     """Every (subregion, rhs) of a batch equals the same subregion solved on
-    its own (scatterers outside it ignored), for graph replay and eager runs."""
-    print(f"[case] batched {precision} graph={use_graph}", flush=True)
+    its own (scatterers outside it ignored), for graph replay and eager runs,
+    with the default launch configuration and with the batched autotuner's."""
+    print(f"[case] batched {precision} graph={use_graph} autotune={autotune}", flush=True)
     nx, ny, lmax = 40, 30, 3
     pos = wl.lattice_positions(nx, ny)
     radii = wl.lens_radii(nx, ny)
@@ -439,12 +442,22 @@ def test_batched_subregions_match_single_solves(precision, use_graph):
     ctx = tmhip.Context(0)
     ctx.set_geometry(pos, K, lmax)
     ctx.set_spheres(to_dev(radii, torch.float64), wl.N_REL)
+    assert ctx.batch_config(precision) == (0, 0)
+    ctx.set_batch_autotune(autotune)
     sb, info = ctx.solve_batched(SUBS, kh, po, use_graph=use_graph, tol=1e-11, precision=precision,
                                  max_iter=20000)
     for k in range(len(SUBS)):
         print(f"[info] sub {k} {SUBS[k]}: {info[k]}", flush=True)
     if use_graph:
         assert ctx.batch_graph_used()
+    pf, items = ctx.batch_config(precision)
+    print(f"[info] batch config {precision}: prefetch {pf}, items {items}", flush=True)
+    R = len(kh)
+    if autotune:
+        assert 1 <= pf <= (3 if precision == "mixed" else 2)
+        assert items in [wg // (2 * R) for wg in (16384, 32768, 65536)]
+    else:
+        assert (pf, items) == (1, 32768 // (2 * R))
     for k, (ox, oy, sx, sy) in enumerate(SUBS):
         ix, iy = np.meshgrid(np.arange(ox, ox + sx), np.arange(oy, oy + sy))
         idx = (iy * nx + ix).ravel()
