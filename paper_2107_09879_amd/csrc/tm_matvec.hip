@@ -400,6 +400,9 @@ static int ensure_plan(tm_ctx* c, int R, int which) {
   int rc;
   if ((rc = ensure(c, c->plan_items[which], items.size() * sizeof(MvItem))) != TM_OK) return rc;
   if ((rc = ensure(c, c->plan_ibeg[which], ibeg.size() * sizeof(int))) != TM_OK) return rc;
+  // launches of the previous plan may still read it (the upload is not
+  // ordered with a non-blocking context stream)
+  TM_HIP(c, hipStreamSynchronize(c->stream));
   TM_HIP(c, hipMemcpy(c->plan_items[which].p, items.data(), items.size() * sizeof(MvItem),
                       hipMemcpyHostToDevice));
   TM_HIP(c, hipMemcpy(c->plan_ibeg[which].p, ibeg.data(), ibeg.size() * sizeof(int),

@@ -553,6 +553,10 @@ int lds_apply(tm_ctx* c, int which, int R, const void* table, const void* xin, c
     c->plan_nreg[which] = ibeg[tl.n_reg];
     if ((rc = ensure(c, c->plan_items[which], items.size() * sizeof(LdsItem))) != TM_OK) return rc;
     if ((rc = ensure(c, c->plan_ibeg[which], ibeg.size() * sizeof(int))) != TM_OK) return rc;
+    // launches of the previous plan may still read it, on the context stream
+    // or the side stream joined into it (the upload is not ordered with a
+    // non-blocking stream)
+    TM_HIP(c, hipStreamSynchronize(c->stream));
     TM_HIP(c, hipMemcpy(c->plan_items[which].p, items.data(), items.size() * sizeof(LdsItem),
                         hipMemcpyHostToDevice));
     TM_HIP(c, hipMemcpy(c->plan_ibeg[which].p, ibeg.data(), ibeg.size() * sizeof(int),

@@ -113,22 +113,35 @@ def test_lds_matvec_chains_on_a_user_stream_without_host_syncs():
     lc = oracle.LatticeCoupling(nx, ny, wl.PITCH, K, lmax)
     ref1 = lc.apply(x[0])
     ref2 = lc.apply(ref1)
+    # a second right-hand side: a call with R = 2 followed at once by one
+    # with R = 1 re-cuts the work split while the first may still run
+    xb = np.concatenate([x, rand_vec(rng, 1, nx * ny, L)])
+    refb = lc.apply(xb[1])
     st = torch.cuda.Stream(device=DEV)
-    out = {}
+    out, outb = {}, {}
     with torch.cuda.stream(st):
         ctx, pos, radii = make_ctx(nx, ny, lmax)
         xd = to_dev(x)
+        xbd = to_dev(xb)
         for prec in ("fp64", "mixed"):
             for v in (8, 9, 10):
                 ctx.set_matvec_config(prec, v, 0)
                 y1 = ctx.apply_operator(xd, "coupling", prec)
                 y2 = ctx.apply_operator(y1, "coupling", prec)
                 out[prec, v] = (y1, y2)
+            yb2 = ctx.apply_operator(xbd, "coupling", prec)
+            yb1 = ctx.apply_operator(xd, "coupling", prec)
+            outb[prec] = (yb2, yb1)
     st.synchronize()
     for (prec, v), (y1, y2) in out.items():
         tol = 1e-12 if prec == "fp64" else 2e-5
         assert rel(y1.cpu().numpy()[0], ref1) < tol, (prec, v)
         assert rel(y2.cpu().numpy()[0], ref2) < 2 * tol, (prec, v)
+    for prec, (yb2, yb1) in outb.items():
+        tol = 1e-12 if prec == "fp64" else 2e-5
+        assert rel(yb2.cpu().numpy()[0], ref1) < tol, prec
+        assert rel(yb2.cpu().numpy()[1], refb) < tol, prec
+        assert rel(yb1.cpu().numpy()[0], ref1) < tol, prec
     ctx.close()
 
 
