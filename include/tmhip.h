@@ -28,7 +28,9 @@
  *     in tm_destroy.
  *   - Calls enqueue work on the context's stream and return without waiting,
  *     except those that fill host outputs (solve info, host result arrays),
- *     which synchronise the stream before returning.
+ *     which synchronise the stream before returning, and those that allocate
+ *     or re-cut the block matvec's work split (a new number of right-hand
+ *     sides or matvec configuration), which first drain the stream.
  *   - One context per host thread.  Calls never throw and never abort; they
  *     return a tm_status.  tm_last_error gives a message for the last failing
  *     call on a context.
