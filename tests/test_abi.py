@@ -56,6 +56,9 @@ def test_host_only_entry_points(lib):
     # a null context is rejected, not dereferenced
     lib.tm_destroy(None)
     assert lib.tm_set_geometry(None, 1, None, ctypes.c_double(1.0), 1) == -1
+    assert lib.tm_set_batch_autotune(None, 1) == -1
+    pf, it = ctypes.c_int(), ctypes.c_int()
+    assert lib.tm_get_batch_config(None, 1, ctypes.byref(pf), ctypes.byref(it)) == -1
 
 
 def test_library_is_gfx950_code():
