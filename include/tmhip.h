@@ -114,8 +114,9 @@ int tm_mie(int lmax, double k, double radius, double n_re, double n_im, tm_c128*
            tm_c128* dtdr_out);
 
 /* Homogeneous spheres (Mie T-matrices, the sphere case of App. I.B):
- * radii: device, [N] (> 0, finite; neighbouring spheres must not overlap,
- * i.e. r_i + r_j < pitch for lattice neighbours, else TM_ERR_OVERLAP);
+ * radii: device, [N] (> 0, finite; no two spheres may intersect, i.e.
+ * r_i + r_j < |x_i - x_j| for every pair, diagonal and farther neighbours
+ * included, else TM_ERR_OVERLAP);
  * relative refractive index n_re + i n_im (n_im >= 0).  Computes the
  * diagonal T and dT/dr on the device. */
 int tm_set_spheres(tm_ctx* ctx, const double* radii, double n_re, double n_im);
@@ -293,9 +294,11 @@ int tm_grad_radius(tm_ctx* ctx, int n_rhs, const tm_c128* mu, const tm_c128* s,
 int tm_set_matvec_config(tm_ctx* ctx, int precision, int variant, int items);
 int tm_get_matvec_config(tm_ctx* ctx, int precision, int* variant, int* items);
 
-/* Time every variant with a few work-item counts on the current geometry for
- * n_rhs right-hand sides and keep the fastest for `precision`.  Synchronises;
- * best_ms (host, nullable) receives the best block-matvec time. */
+/* Time the LDS-staged variants (8..10; FP64: 8, 9) with a few work-item
+ * counts (2k..32k workgroups) on the current geometry for n_rhs right-hand
+ * sides and keep the fastest for `precision`.  Synchronises; best_ms (host,
+ * nullable) receives the best block-matvec time.  Without a call, FP64 uses
+ * variant 9 and complex64 variant 10 with the default work split. */
 int tm_autotune(tm_ctx* ctx, int n_rhs, int precision, double* best_ms);
 
 /* ---- progress ------------------------------------------------------------- */

@@ -68,6 +68,26 @@ int ensure_pinned(tm_ctx* c, size_t bytes) {
   return TM_OK;
 }
 
+// Plane-wave incidences: khat unit vectors, pol finite and transverse.
+int validate_incidence(tm_ctx* c, int R, const double* khat, const tm_c128* pol) {
+  for (int r = 0; r < R; ++r) {
+    const double* kh = khat + 3 * r;
+    const double nk = std::sqrt(kh[0] * kh[0] + kh[1] * kh[1] + kh[2] * kh[2]);
+    if (!std::isfinite(nk) || std::fabs(nk - 1.0) > 1e-9)
+      return set_err(c, TM_ERR_INVALID_ARG, "khat must be a unit vector");
+    double dr = 0, di = 0;
+    for (int q = 0; q < 3; ++q) {
+      if (!std::isfinite(pol[3 * r + q].re) || !std::isfinite(pol[3 * r + q].im))
+        return set_err(c, TM_ERR_NAN, "non-finite polarisation");
+      dr += kh[q] * pol[3 * r + q].re;
+      di += kh[q] * pol[3 * r + q].im;
+    }
+    if (std::hypot(dr, di) > 1e-9)
+      return set_err(c, TM_ERR_INVALID_ARG, "polarisation must be transverse to khat");
+  }
+  return TM_OK;
+}
+
 // ---------------------------------------------------------------- GMRES
 struct Gm {
   tm_ctx* c;
@@ -415,15 +435,23 @@ int tm_set_spheres(tm_ctx* c, const double* radii, double n_re, double n_im) {
     if (g.k * r[i] * std::max(1.0, nabs) > 12.0)
       return tmh::set_err(c, TM_ERR_INVALID_ARG, "k r |n| > 12 is outside the supported range");
   }
-  for (int i = 0; i < g.n; ++i) {
-    const int ix = i % g.nx, iy = i / g.nx;
-    if (ix + 1 < g.nx && r[i] + r[i + 1] >= g.pitch)
-      return tmh::set_err(c, TM_ERR_OVERLAP, "spheres " + std::to_string(i) + " and " +
-                                                std::to_string(i + 1) + " overlap");
-    if (iy + 1 < g.ny && r[i] + r[i + g.nx] >= g.pitch)
-      return tmh::set_err(c, TM_ERR_OVERLAP, "spheres " + std::to_string(i) + " and " +
-                                                std::to_string(i + g.nx) + " overlap");
-  }
+  // non-intersecting spheres (App. I.C): every pair closer than twice the
+  // largest radius is checked, diagonal and farther neighbours included
+  double rmax = 0.0;
+  for (int i = 0; i < g.n; ++i) rmax = std::max(rmax, r[i]);
+  const int reach = (int)std::floor(2.0 * rmax / g.pitch);
+  for (int dy = 0; dy <= reach; ++dy)
+    for (int dx = (dy == 0 ? 1 : -reach); dx <= reach; ++dx) {
+      const double dist = g.pitch * std::hypot((double)dx, (double)dy);
+      if (dist > 2.0 * rmax) continue;
+      for (int iy = 0; iy + dy < g.ny; ++iy)
+        for (int ix = std::max(0, -dx); ix < g.nx && ix + dx < g.nx; ++ix) {
+          const int i = iy * g.nx + ix, j = (iy + dy) * g.nx + ix + dx;
+          if (r[i] + r[j] >= dist)
+            return tmh::set_err(c, TM_ERR_OVERLAP, "spheres " + std::to_string(i) + " and " +
+                                                      std::to_string(j) + " overlap");
+        }
+    }
   int rc = tmh::launch_mie(c, radii, n_re, n_im);
   if (rc != TM_OK) return rc;
   c->have_t = c->have_dt = true;
@@ -471,21 +499,8 @@ int tm_plane_wave_rhs(tm_ctx* c, int R, const double* khat, const tm_c128* pol, 
   CHECK_CTX(c);
   if (!c->have_geom) return tmh::set_err(c, TM_ERR_STATE, "set geometry first");
   if (R < 1 || !khat || !pol || !a0) return tmh::set_err(c, TM_ERR_INVALID_ARG, "bad arguments");
-  for (int r = 0; r < R; ++r) {
-    const double* kh = khat + 3 * r;
-    const double nk = std::sqrt(kh[0] * kh[0] + kh[1] * kh[1] + kh[2] * kh[2]);
-    if (!std::isfinite(nk) || std::fabs(nk - 1.0) > 1e-9)
-      return tmh::set_err(c, TM_ERR_INVALID_ARG, "khat must be a unit vector");
-    double dr = 0, di = 0;
-    for (int q = 0; q < 3; ++q) {
-      if (!std::isfinite(pol[3 * r + q].re) || !std::isfinite(pol[3 * r + q].im))
-        return tmh::set_err(c, TM_ERR_NAN, "non-finite polarisation");
-      dr += kh[q] * pol[3 * r + q].re;
-      di += kh[q] * pol[3 * r + q].im;
-    }
-    if (std::hypot(dr, di) > 1e-9)
-      return tmh::set_err(c, TM_ERR_INVALID_ARG, "polarisation must be transverse to khat");
-  }
+  int rc;
+  if ((rc = tmh::validate_incidence(c, R, khat, pol)) != TM_OK) return rc;
   return tmh::launch_plane_wave(c, R, khat, pol, a0);
 }
 

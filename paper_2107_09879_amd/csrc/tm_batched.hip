@@ -998,6 +998,8 @@ extern "C" int tm_solve_batched(tm_ctx* c, int n_sub, const tm_subregion* subs, 
       (o->precision != TM_PREC_FP64 && o->precision != TM_PREC_MIXED) ||
       (o->precision == TM_PREC_MIXED && !(o->inner_tol > 0.0 && o->inner_tol < 1.0)) || o->use_x0)
     return tmh::set_err(c, TM_ERR_INVALID_ARG, "invalid solver options (x0 not supported in batch)");
+  int rc;
+  if ((rc = tmh::validate_incidence(c, n_rhs, khat, pol)) != TM_OK) return rc;
   for (int k = 0; k < n_sub; ++k) {
     const tm_subregion& q = subs[k];
     if (q.side_x < 1 || q.side_y < 1 || q.origin_x < 0 || q.origin_y < 0 ||

@@ -111,9 +111,13 @@ struct tm_ctx {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pending[2];
   // matvec launch configuration per precision slot (0 = FP64, 1 = complex64):
   // kernel variant, target work items per (rhs, class), and the cached plan
-  int mv_variant[2] = {0, 0};
+  // default: the LDS-staged kernels (FP64 prefetch depth 2, complex64 depth 3)
+  int mv_variant[2] = {9, 10};
   int mv_items[2] = {0, 0};
   tmh::DevBuf plan_items[2], plan_ibeg[2];
+  // the cached plan of a precision slot is reused only for the same kernel
+  // family (1 = direct, 2 = LDS-staged), R and work-item target
+  int plan_kind[2] = {0, 0};
   int plan_R[2] = {-1, -1}, plan_target[2] = {0, 0}, plan_nitems[2] = {0, 0};
   int plan_nreg[2] = {0, 0};  // LDS plan: items of regular tiles (wide-tile items follow)
   int last_batch_graphed = 0;
@@ -137,6 +141,7 @@ int set_err(tm_ctx* c, int code, const std::string& msg);
   } while (0)
 
 int ensure(tm_ctx* c, DevBuf& b, size_t bytes);
+int validate_incidence(tm_ctx* c, int R, const double* khat, const tm_c128* pol);
 int ensure_pinned(tm_ctx* c, size_t bytes);
 void release(DevBuf& b);
 

@@ -393,7 +393,8 @@ static int default_items(int R) { return std::max(1, (16384 + 2 * R - 1) / (2 * 
 
 static int ensure_plan(tm_ctx* c, int R, int which) {
   const int target = c->mv_items[which] > 0 ? c->mv_items[which] : default_items(R);
-  if (c->plan_R[which] == R && c->plan_target[which] == target) return TM_OK;
+  if (c->plan_kind[which] == 1 && c->plan_R[which] == R && c->plan_target[which] == target)
+    return TM_OK;
   std::vector<MvItem> items;
   std::vector<int> ibeg;
   make_plan(c->g, target, items, ibeg);
@@ -407,6 +408,7 @@ static int ensure_plan(tm_ctx* c, int R, int which) {
                       hipMemcpyHostToDevice));
   TM_HIP(c, hipMemcpy(c->plan_ibeg[which].p, ibeg.data(), ibeg.size() * sizeof(int),
                       hipMemcpyHostToDevice));
+  c->plan_kind[which] = 1;
   c->plan_R[which] = R;
   c->plan_target[which] = target;
   c->plan_nitems[which] = (int)items.size();
@@ -511,51 +513,20 @@ static int autotune_impl(tm_ctx* c, int R, double* best_ms) {
   TM_HIP(c, hipEventCreate(&e1));
   double best = 1e300;
   int bv = c->mv_variant[which], bi = c->mv_items[which];
-  for (int v = 0; v < N_VARIANTS; ++v) {
+  // only the LDS-staged variants: the direct kernels (0..7) never won at any
+  // measured size and cost up to tens of milliseconds per timed launch; FP64
+  // runs variant 10 as 9
+  const int vlast = std::is_same<T, double>::value ? LDS_VARIANT + 1 : N_VARIANTS - 1;
+  for (int v = LDS_VARIANT; v <= vlast; ++v) {
     for (int wt : wg_targets) {
       c->mv_variant[which] = v;
       c->mv_items[which] = std::max(1, wt / (2 * R));
-      if (v >= LDS_VARIANT) {
-        double tmin = 1e300;
-        for (int rep = 0; rep < 4; ++rep) {
-          rc = lds_apply<T>(c, which, R, std::is_same<T, double>::value ? c->tab64.p : c->tab32.p,
-                            c->xlow.p, nullptr, nullptr, 0, c->mv_items[which], e0, e1,
-                            v - LDS_VARIANT + 1);
-          if (rc != TM_OK) return rc;
-          TM_HIP(c, hipEventSynchronize(e1));
-          float ms = 0.f;
-          TM_HIP(c, hipEventElapsedTime(&ms, e0, e1));
-          if (rep > 0) tmin = std::min(tmin, (double)ms);
-        }
-        if (tmin < best) {
-          best = tmin;
-          bv = v;
-          bi = c->mv_items[which];
-        }
-        continue;
-      }
-      if ((rc = ensure_plan(c, R, which)) != TM_OK) return rc;
-      const int nitems = c->plan_nitems[which];
-      if ((rc = ensure(c, c->partial, (size_t)nitems * 2 * R * 256 * SLOTS * sizeof(cplx<T>))) !=
-          TM_OK)
-        return rc;
-      MvArgs a;
-      a.table = std::is_same<T, double>::value ? c->tab64.p : c->tab32.p;
-      a.x = c->xlow.p;
-      a.partial = c->partial.p;
-      a.items = (const MvItem*)c->plan_items[which].p;
-      a.nx = g.nx;
-      a.ny = g.ny;
-      a.tnx = g.tnx;
-      a.tny = g.tny;
-      a.tiles_x = (g.nx + 15) / 16;
-      a.R = R;
-      a.n_sites = g.n;
       double tmin = 1e300;
       for (int rep = 0; rep < 4; ++rep) {
-        TM_HIP(c, hipEventRecord(e0, c->stream));
-        hipLaunchKernelGGL(mv_kernel<T>(v), dim3(nitems, 2 * R), dim3(256), 0, c->stream, a);
-        TM_HIP(c, hipEventRecord(e1, c->stream));
+        rc = lds_apply<T>(c, which, R, std::is_same<T, double>::value ? c->tab64.p : c->tab32.p,
+                          c->xlow.p, nullptr, nullptr, 0, c->mv_items[which], e0, e1,
+                          v - LDS_VARIANT + 1);
+        if (rc != TM_OK) return rc;
         TM_HIP(c, hipEventSynchronize(e1));
         float ms = 0.f;
         TM_HIP(c, hipEventElapsedTime(&ms, e0, e1));

@@ -544,9 +544,8 @@ int lds_apply(tm_ctx* c, int which, int R, const void* table, const void* xin, c
   const int TW = Cfg::TW;
   const LdsTiling tl = lds_tiling(g, TW);
   const long long vec = g.vec_len(), total = vec * R;
-  const int key = 1000 + items_target;  // plan cache key (distinct from the direct kernel's)
   int rc;
-  if (c->plan_R[which] != R || c->plan_target[which] != key) {
+  if (c->plan_kind[which] != 2 || c->plan_R[which] != R || c->plan_target[which] != items_target) {
     std::vector<LdsItem> items;
     std::vector<int> ibeg;
     lds_plan(g, tl, Ch::BX, Ch::BY, 64, items_target, items, ibeg);
@@ -561,8 +560,9 @@ int lds_apply(tm_ctx* c, int which, int R, const void* table, const void* xin, c
                         hipMemcpyHostToDevice));
     TM_HIP(c, hipMemcpy(c->plan_ibeg[which].p, ibeg.data(), ibeg.size() * sizeof(int),
                         hipMemcpyHostToDevice));
+    c->plan_kind[which] = 2;
     c->plan_R[which] = R;
-    c->plan_target[which] = key;
+    c->plan_target[which] = items_target;
     c->plan_nitems[which] = (int)items.size();
   }
   const int nitems = c->plan_nitems[which];

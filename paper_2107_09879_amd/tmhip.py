@@ -141,11 +141,34 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def _dev(t, dtype, name):
-    if not isinstance(t, torch.Tensor) or not t.is_cuda:
-        raise TypeError(f"{name} must be a CUDA/HIP torch tensor")
+def _shape(t, dtype, name, tail=None, lead_max=None):
+    """Type, dtype and shape of an array bound for the device.
+
+    tail: the trailing dimensions the library assumes (None entries match any
+    size); lead_max: the largest number of leading dimensions allowed (a
+    missing leading rhs dimension means one right-hand side)."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
     if t.dtype != dtype:
         raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if tail is not None:
+        tail = tuple(tail)
+        shp = tuple(t.shape)
+        nlead = len(shp) - len(tail)
+        ok = 0 <= nlead <= (lead_max if lead_max is not None else 0)
+        ok = ok and all(w is None or w == v for w, v in zip(tail, shp[nlead:]))
+        if not ok:
+            want = ("[R, " if lead_max else "[") + ", ".join("*" if w is None else str(w) for w in tail) + "]"
+            raise ValueError(f"{name} must have shape {want}, got {list(shp)}")
+    return t
+
+
+def _place(t, name, device=None):
+    """The array on the context's device, contiguous, conjugation resolved."""
+    if not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA/HIP torch tensor")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, the context on {device}")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
     # the library reads raw memory: materialise lazy conjugate / negative views
@@ -154,6 +177,37 @@ def _dev(t, dtype, name):
     if t.is_neg():
         t = t.resolve_neg()
     return t
+
+
+def _dev(t, dtype, name, device=None, tail=None, lead_max=None):
+    return _place(_shape(t, dtype, name, tail, lead_max), name, device)
+
+
+def _devs(device, *specs):
+    """Several arrays: every shape is checked before any device check, so a
+    mis-shaped argument raises ValueError whatever the others hold.
+    specs: (tensor, dtype, name, tail, lead_max)."""
+    ts = [_shape(t, dt, nm, tl, lm) for t, dt, nm, tl, lm in specs]
+    return [_place(t, sp[2], device) for t, sp in zip(ts, specs)]
+
+
+def _host(a, dtype, name, shape):
+    """A contiguous host copy of `a` with the given shape (None = any size)."""
+    a = np.ascontiguousarray(a, dtype=dtype)
+    if a.ndim != len(shape) or any(w is not None and w != v for w, v in zip(shape, a.shape)):
+        want = "[" + ", ".join("*" if w is None else str(w) for w in shape) + "]"
+        raise ValueError(f"{name} must have shape {want}, got {list(a.shape)}")
+    return a
+
+
+def _incidence(khat, pol):
+    kh = _host(np.atleast_2d(khat), np.float64, "khat", (None, 3))
+    po = _host(np.atleast_2d(pol), np.complex128, "pol", (kh.shape[0], 3))
+    return kh, po
+
+
+def _nrhs(t, tail_dims):
+    return t.shape[0] if t.dim() > tail_dims else 1
 
 
 class Context:
@@ -200,7 +254,7 @@ class Context:
 
     # ---- set-up
     def set_geometry(self, positions, k, lmax):
-        pos = np.ascontiguousarray(positions, dtype=np.float64)
+        pos = _host(positions, np.float64, "positions", (None, 3))
         self._check(self.lib.tm_set_geometry(self.h, len(pos), pos.ctypes.data_as(ctypes.c_void_p),
                                              float(k), int(lmax)))
         self.n, self.lmax, self.L = len(pos), int(lmax), self.lib.tm_coeff_count(int(lmax))
@@ -212,19 +266,17 @@ class Context:
         return nx.value, ny.value, p.value
 
     def set_spheres(self, radii, n_rel):
-        r = _dev(radii, torch.float64, "radii")
+        r = _dev(radii, torch.float64, "radii", self.device, (self.n,))
         n_rel = complex(n_rel)
         self._check(self.lib.tm_set_spheres(self.h, _ptr(r), n_rel.real, n_rel.imag))
 
     def set_tmatrix_diag(self, t):
-        t = _dev(t, torch.complex128, "t")
+        t = _dev(t, torch.complex128, "t", self.device, (self.n, self.L))
         self._check(self.lib.tm_set_tmatrix_diag(self.h, _ptr(t)))
 
     def set_tmatrix_dense(self, T):
         """T [N, L, L] complex128 on the device (row-major per scatterer)."""
-        T = _dev(T, torch.complex128, "T")
-        if tuple(T.shape) != (self.n, self.L, self.L):
-            raise ValueError(f"T must have shape {(self.n, self.L, self.L)}")
+        T = _dev(T, torch.complex128, "T", self.device, (self.n, self.L, self.L))
         self._check(self.lib.tm_set_tmatrix_dense(self.h, _ptr(T)))
 
     def get_tmatrix_diag(self):
@@ -234,8 +286,7 @@ class Context:
         return t, dt
 
     def plane_wave_rhs(self, khat, pol):
-        kh = np.ascontiguousarray(np.atleast_2d(khat), dtype=np.float64)
-        po = np.ascontiguousarray(np.atleast_2d(pol), dtype=np.complex128)
+        kh, po = _incidence(khat, pol)
         R = kh.shape[0]
         a0 = torch.empty(R, self.n, self.L, dtype=torch.complex128, device=self.device)
         self._check(self.lib.tm_plane_wave_rhs(self.h, R, kh.ctypes.data_as(ctypes.c_void_p),
@@ -252,9 +303,16 @@ class Context:
         o.inner_tol, o.use_x0 = inner_tol, int(bool(use_x0))
         return o
 
-    def _solve(self, fn, rhs, x0, **kw):
-        rhs = _dev(rhs, torch.complex128, "rhs")
-        R = rhs.shape[0] if rhs.dim() == 3 else 1
+    def _solve(self, fname, rhs, x0, **kw):
+        _shape(rhs, torch.complex128, "rhs", (self.n, self.L), 1)
+        if x0 is not None:
+            _shape(x0, torch.complex128, "x0", (self.n, self.L), 1)
+            if x0.shape != rhs.shape:
+                raise ValueError(f"x0 must have the shape of the right-hand side {list(rhs.shape)}")
+            x0 = _place(x0, "x0", self.device)
+        rhs = _place(rhs, "rhs", self.device)
+        R = _nrhs(rhs, 2)
+        fn = getattr(self.lib, fname)
         out = x0.clone() if x0 is not None else torch.zeros_like(rhs)
         o = self.make_opts(use_x0=x0 is not None, **kw)
         infos = (SolveInfo * R)()
@@ -263,17 +321,16 @@ class Context:
         return out, [i.as_dict() for i in infos]
 
     def solve(self, a0, x0=None, **kw):
-        return self._solve(self.lib.tm_solve, a0, x0, **kw)
+        return self._solve("tm_solve", a0, x0, **kw)
 
     def adjoint_solve(self, v, x0=None, **kw):
-        return self._solve(self.lib.tm_adjoint_solve, v, x0, **kw)
+        return self._solve("tm_adjoint_solve", v, x0, **kw)
 
     def solve_batched(self, subs, khat, pol, use_graph=True, **kw):
         """subs: [(origin_x, origin_y, side_x, side_y)]; returns ([s_k [R, N_k, L]], infos [S][R])."""
         S = len(subs)
         arr = (Subregion * S)(*[Subregion(*map(int, q)) for q in subs])
-        kh = np.ascontiguousarray(np.atleast_2d(khat), dtype=np.float64)
-        po = np.ascontiguousarray(np.atleast_2d(pol), dtype=np.complex128)
+        kh, po = _incidence(khat, pol)
         R = kh.shape[0]
         sizes = [R * q[2] * q[3] * self.L for q in subs]
         out = torch.empty(sum(sizes), dtype=torch.complex128, device=self.device)
@@ -304,8 +361,8 @@ class Context:
         return pf.value, it.value
 
     def apply_operator(self, x, op="forward", precision="fp64"):
-        x = _dev(x, torch.complex128, "x")
-        R = x.shape[0] if x.dim() == 3 else 1
+        x = _dev(x, torch.complex128, "x", self.device, (self.n, self.L), 1)
+        R = _nrhs(x, 2)
         y = torch.empty_like(x)
         self._check(self.lib.tm_apply_operator(self.h, R, _ptr(x), _ptr(y), PRECISIONS[precision],
                                                OPS[op]))
@@ -313,9 +370,9 @@ class Context:
 
     # ---- readout
     def near_field(self, s, pts, precision="fp64"):
-        s = _dev(s, torch.complex128, "s")
-        pts = _dev(pts, torch.float64, "pts")
-        R = s.shape[0] if s.dim() == 3 else 1
+        s, pts = _devs(self.device, (s, torch.complex128, "s", (self.n, self.L), 1),
+                       (pts, torch.float64, "pts", (None, 3), None))
+        R = _nrhs(s, 2)
         E = torch.empty(R, pts.shape[0], 3, dtype=torch.complex128, device=self.device)
         self._check(self.lib.tm_near_field(self.h, R, _ptr(s), pts.shape[0], _ptr(pts), _ptr(E),
                                            PRECISIONS[precision]))
@@ -323,35 +380,39 @@ class Context:
 
     def near_field_adjoint(self, pts, w):
         """v = transpose of the near-field map applied to w [R, P, 3]."""
-        pts = _dev(pts, torch.float64, "pts")
-        w = _dev(w, torch.complex128, "w")
-        R = w.shape[0] if w.dim() == 3 else 1
+        _shape(pts, torch.float64, "pts", (None, 3))
+        pts, w = _devs(self.device, (pts, torch.float64, "pts", (None, 3), None),
+                       (w, torch.complex128, "w", (pts.shape[0], 3), 1))
+        R = _nrhs(w, 2)
         v = torch.empty(R, self.n, self.L, dtype=torch.complex128, device=self.device)
         self._check(self.lib.tm_near_field_adjoint(self.h, R, pts.shape[0], _ptr(pts), _ptr(w), _ptr(v)))
         return v
 
     def far_field(self, s, dirs):
-        s = _dev(s, torch.complex128, "s")
-        dirs = _dev(dirs, torch.float64, "dirs")
-        R = s.shape[0] if s.dim() == 3 else 1
+        s, dirs = _devs(self.device, (s, torch.complex128, "s", (self.n, self.L), 1),
+                        (dirs, torch.float64, "dirs", (None, 3), None))
+        R = _nrhs(s, 2)
         F = torch.empty(R, dirs.shape[0], 3, dtype=torch.complex128, device=self.device)
         self._check(self.lib.tm_far_field(self.h, R, _ptr(s), dirs.shape[0], _ptr(dirs), _ptr(F)))
         return F
 
     # ---- sensitivities
     def detector_vector(self, xd, w):
-        xd = np.ascontiguousarray(xd, dtype=np.float64)
-        w = np.ascontiguousarray(w, dtype=np.complex128)
+        xd = _host(xd, np.float64, "xd", (3,))
+        w = _host(w, np.complex128, "w", (3,))
         v = torch.empty(self.n, self.L, dtype=torch.complex128, device=self.device)
         self._check(self.lib.tm_detector_vector(self.h, xd.ctypes.data_as(ctypes.c_void_p),
                                                 w.ctypes.data_as(ctypes.c_void_p), _ptr(v)))
         return v
 
     def grad_radius(self, mu, s, a0):
-        mu = _dev(mu, torch.complex128, "mu")
-        s = _dev(s, torch.complex128, "s")
-        a0 = _dev(a0, torch.complex128, "a0")
-        R = mu.shape[0] if mu.dim() == 3 else 1
+        spec = [(t, torch.complex128, nm, (self.n, self.L), 1) for t, nm in ((mu, "mu"), (s, "s"), (a0, "a0"))]
+        for t, *rest in spec:
+            _shape(t, *rest)
+        R = _nrhs(mu, 2)
+        if _nrhs(s, 2) != R or _nrhs(a0, 2) != R:
+            raise ValueError("mu, s and a0 must hold the same number of right-hand sides")
+        mu, s, a0 = _devs(self.device, *spec)
         g = torch.empty(R, self.n, dtype=torch.float64, device=self.device)
         self._check(self.lib.tm_grad_radius(self.h, R, _ptr(mu), _ptr(s), _ptr(a0), _ptr(g)))
         return g

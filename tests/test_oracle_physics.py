@@ -11,7 +11,8 @@ import pytest
 
 import workloads as wl
 from oracle.mie import mie_ab, mie_tmatrix_diag_many
-from oracle.solver import (LatticeCoupling, coupling_dense, extinction, far_field, gmres,
+from oracle.solver import (LatticeCoupling, coupling_dense, detector_vectors, extinction,
+                           far_field, gmres,
                            near_field, objective_and_gradient_dense, rows_A, scattering,
                            solve_dense, system_dense)
 from oracle.vswf import n_coeffs, plane_wave_coeffs
@@ -182,3 +183,43 @@ def test_adjoint_gradient_fd():
         Om = objective_and_gradient_dense(pos, K, lmax, rm, wl.N_REL, kh, po, xd)[0]
         fd = (Op - Om) / (2 * h)
         assert abs(fd - g[i]) < 1e-6 * np.abs(g).max()
+
+
+def test_detector_vectors_are_the_near_field(rng):
+    """The point-detector functional of App. IV (eq. "performance_metric" with
+    sigma a point mass at xd) is the scattered field at xd, eq.
+    "sca_fld_concise": v[c] . s = E_sca,c(xd) for random s, on a 3-D cluster
+    and on a lattice, with detectors above and below the lattice plane (a
+    mirrored or reversed displacement in the detector vectors fails here)."""
+    lmax = 3
+    L = n_coeffs(lmax)
+    cluster = _random_cluster(rng, 6)
+    for pos, pts in ((cluster, ([0.7, -0.4, 3.5], [0.3, 1.1, -3.6], [4.0, 4.5, 0.2])),
+                     (wl.lattice_positions(4, 3), ([0.7, 0.4, 2.5], [0.3, 1.1, -1.7], [5.0, 4.0, 0.9]))):
+        s = rng.normal(size=(len(pos), L)) + 1j * rng.normal(size=(len(pos), L))
+        for xd in pts:
+            v = detector_vectors(pos, K, lmax, xd)
+            z = np.einsum('cil,il->c', v, s)
+            E = near_field(s, pos, K, lmax, np.array([xd]))[0]
+            assert np.abs(z - E).max() <= 1e-12 * np.abs(E).max()
+            # the mirror image of the detector sees a different field
+            xm = np.array(xd) * np.array([1.0, 1.0, -1.0])
+            zm = np.einsum('cil,il->c', detector_vectors(pos, K, lmax, xm), s)
+            assert np.abs(zm - E).max() > 1e-3 * np.abs(E).max()
+
+
+@pytest.mark.parametrize("xd", [[0.6, 0.6, 3.0], [0.9, 0.3, -2.2]])
+def test_objective_is_total_intensity_at_the_detector(xd):
+    """O returned with the gradient is |E_inc + E_sca|^2 at xd (reading of the
+    adjoint workload's objective), with E_inc the plane wave's closed form and
+    E_sca the direct-sum readout of the LU solution."""
+    pos = wl.lattice_positions(3, 3)
+    radii = wl.uniform_radii(9, 0.12, 0.28, 11)
+    kh, po = wl.incidence("p10")
+    lmax = 2
+    xd = np.array(xd)
+    O, g, s, mu = objective_and_gradient_dense(pos, K, lmax, radii, wl.N_REL, kh, po, xd)
+    s_ref = _solve(pos, radii, lmax, kh, po)
+    assert np.linalg.norm(s - s_ref) <= 1e-13 * np.linalg.norm(s_ref)
+    E = po * np.exp(1j * K * np.dot(kh, xd)) + near_field(s_ref, pos, K, lmax, xd[None])[0]
+    assert abs(O - np.sum(np.abs(E) ** 2)) <= 1e-12 * O
