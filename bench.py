@@ -282,6 +282,9 @@ def main():
         "matvec_algorithmic_GBps": gbs,
         "roofline": {"bound": "mfma", "achieved": dom["tflops"], "peak": PEAK_FP32_MFMA,
                      "unit": "TFLOP/s", "frac": dom["tflops"] / PEAK_FP32_MFMA,
+                     # issued matrix-core flops (Gauss 3-product form, padded slots)
+                     "mfma_issue_frac": dom["tflops"] * mfma_issue_ratio(lmax) / PEAK_FP32_MFMA,
+                     "effective_ceiling_tflops": PEAK_FP32_MFMA / mfma_issue_ratio(lmax),
                      "traffic": measured_traffic(knames, cfg["name"]),
                      "kernel": kname, "avg_launch_ms": dom["avg_launch_ms"],
                      "flops_per_launch": dom["flops_per_launch"],
@@ -500,7 +503,7 @@ def bench_batched(args):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         a0 = one.plane_wave_rhs(kh, po)
-        _, info = one.solve(a0, tol=cfg["tol"], restart=cfg["restart"], precision="mixed",
+        _, info = one.solve(a0, tol=cfg["tol"], restart=restart, precision="mixed",
                             max_iter=max_iter)
         torch.cuda.synchronize()
         seq["time_s"] += time.perf_counter() - t0
@@ -588,6 +591,48 @@ def bench_adjoint(args):
     ctx.close()
 
 
+def host_cpu():
+    """nproc (CPUs this process may run on) and the lscpu model name."""
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except Exception:
+        nproc = os.cpu_count()
+    model = None
+    try:
+        import subprocess
+
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except Exception:
+        pass
+    if model is None:
+        try:
+            with open("/proc/cpuinfo") as f:
+                for line in f:
+                    if line.startswith("model name"):
+                        model = line.split(":", 1)[1].strip()
+                        break
+        except OSError:
+            pass
+    return {"nproc": nproc, "cpu_model": model}
+
+
+def mfma_issue_ratio(lmax):
+    """Issued matrix-core flops per algorithmic flop of the complex64 block
+    matvec: per 16 target sites, displacement and class the kernel issues
+    (S/16)^2 x 4 x 3 MFMA 16x16x4 instructions (complex products from three
+    real products, S = padded class size) of 2048 flops each, against
+    16 x (L/2)^2 x 8 algorithmic flops."""
+    L = 2 * lmax * (lmax + 2)
+    S = 16 * ((L // 2 + 15) // 16)
+    hw = (S // 16) ** 2 * 4 * 3 * 2048
+    alg = 16 * (L // 2) ** 2 * 8
+    return hw / alg
+
+
 def cpu_baseline(pos, radii, kh, po, cfg, gpu_info):
     """The oracle on the host cores: one FP64 matrix-free matvec at the full
     workload, timed, times the number of FP64-equivalent matvecs the GPU solve
@@ -599,6 +644,7 @@ def cpu_baseline(pos, radii, kh, po, cfg, gpu_info):
         cores = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
     except Exception:
         cores = os.cpu_count()
+    host = host_cpu()
     n = cfg["nx"]
     lmax = cfg["lmax"]
     t0 = time.perf_counter()
@@ -619,7 +665,7 @@ def cpu_baseline(pos, radii, kh, po, cfg, gpu_info):
     est = t_setup + t_mv * matvecs
     log(f"[bench] oracle: block setup {t_setup:.1f} s, one FP64 matvec {t_mv:.1f} s "
         f"(from a {frac:.1%} sample), x {matvecs} matvecs")
-    return {"value": est, "unit": "s", "cores": cores, "kind": "oracle",
+    return {"value": est, "unit": "s", "cores": cores, "kind": "oracle", **host,
             "sample": f"oracle FP64 matvec at this workload timed on every third lattice "
                       f"displacement ({frac:.1%} of the pairs) and scaled to one full matvec "
                       f"({t_mv:.2f} s), plus the per-displacement block setup ({t_setup:.2f} s), "
