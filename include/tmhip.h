@@ -196,6 +196,26 @@ enum {
 int tm_apply_operator(tm_ctx* ctx, int n_rhs, const tm_c128* x, tm_c128* y, int precision,
                       int op);
 
+/* Allocation-free variant of tm_apply_operator, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, result and rounding
+ * class as tm_apply_operator (the block-matvec work split differs, so
+ * complex64 results differ from it by FP32 summation order).  It calls no
+ * hipMalloc/hipFree and never synchronises: it enqueues kernels only.  Its
+ * packed vectors, low-precision input copy, work split and partial sums live
+ * in one static device array of TM_NOALLOC_SCRATCH_BYTES per GPU, held until
+ * the process ends; a problem whose buffers do not fit returns
+ * TM_ERR_INVALID_ARG (about 2 N n_rhs <= 1.5e6 sites x right-hand sides; the
+ * work split is thinned to fit).  Calls on one GPU share that array: calls
+ * that overlap in time on the same GPU (other streams, other threads, other
+ * contexts) race and must be serialised by the caller.  Requires a diagonal
+ * T for TM_OP_FORWARD / TM_OP_ADJOINT (TM_ERR_STATE for a dense T) and, for
+ * the transposed ops, tables already built by an earlier tm_apply_operator
+ * with a transposed op or tm_adjoint_solve (TM_ERR_STATE otherwise). */
+#define TM_NOALLOC_SCRATCH_BYTES (128ull * 1024ull * 1024ull)
+int tm_apply_operator_noalloc(tm_ctx* ctx, int n_rhs, const tm_c128* x, tm_c128* y,
+                              int precision, int op);
+
 /* ---- batched subregions --------------------------------------------------- */
 
 /* A rectangular subregion of the current lattice: sites (ix, iy) with

@@ -299,6 +299,11 @@ int tm_create(tm_ctx** out, int device, void* stream) {
   if (!c) return TM_ERR_OOM;
   c->device = device;
   c->stream = (hipStream_t)stream;
+  const int rc = tmh::noalloc_init(c);
+  if (rc != TM_OK) {
+    delete c;
+    return rc;
+  }
   *out = c;
   return TM_OK;
 }

@@ -180,6 +180,24 @@ int apply_op(tm_ctx* c, Op op, int prec, int R, const c128* x, c128* y);
 double matvec_flops(const Geometry& g);
 int autotune(tm_ctx* c, int R, int prec, double* best_ms);
 
+// block-kernel input: out = (T)(t * x) (t non-null) or (T)x
+template <typename T>
+void launch_prep(hipStream_t st, const c128* x, const c128* t, void* out, long long vec,
+                 long long total);
+// LDS-staged matvec with a device-made uniform work split (ipt items per
+// tile) and every buffer inside `buf` (tm_matvec_lds.hip); no allocation,
+// no host synchronisation
+template <typename T>
+size_t lds_fixed_bytes(const Geometry& g, int R, int ipt);
+template <typename T>
+int lds_fixed_default_ipt(const Geometry& g, int R);
+template <typename T>
+int lds_apply_fixed(tm_ctx* c, int R, const void* table, const void* xin, const c128* x, c128* y,
+                    int op, int pf, int ipt, void* buf);
+// per-device address of the allocation-free entry point's scratch array,
+// looked up once per device by tm_create (tm_noalloc.hip)
+int noalloc_init(tm_ctx* c);
+
 // Krylov kernels (tm_krylov.hip)
 void k_multidot(hipStream_t st, const c128* V, long long stride, int nvec, const c128* w,
                 long long len, c128* partial, int nblk);

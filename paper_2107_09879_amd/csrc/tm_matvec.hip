@@ -320,6 +320,15 @@ __global__ void prep_kernel(const c128* __restrict__ x, const c128* __restrict__
   out[idx] = cplx<T>{(T)v.re, (T)v.im};
 }
 
+template <typename T>
+void launch_prep(hipStream_t st, const c128* x, const c128* t, void* out, long long vec,
+                 long long total) {
+  hipLaunchKernelGGL(prep_kernel<T>, dim3((int)((total + 255) / 256)), dim3(256), 0, st, x, t,
+                     (cplx<T>*)out, vec, total);
+}
+template void launch_prep<float>(hipStream_t, const c128*, const c128*, void*, long long, long long);
+template void launch_prep<double>(hipStream_t, const c128*, const c128*, void*, long long, long long);
+
 double matvec_flops(const Geometry& g) {
   // 2 classes x (L/2)^2 complex multiply-adds x 8 real flops per ordered pair
   const double N = (double)g.n;

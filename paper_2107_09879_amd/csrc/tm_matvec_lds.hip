@@ -631,6 +631,128 @@ int lds_apply(tm_ctx* c, int which, int R, const void* table, const void* xin, c
   return TM_OK;
 }
 
+// Uniform work split computed on the device (no host planner, no upload):
+// every tile of the lattice gets `ipt` items that cut its displacement-block
+// list into equal-count ranges (empty ranges allowed); ibeg[t] = t * ipt.
+template <typename T>
+__global__ void lds_uniform_plan_kernel(LdsItem* __restrict__ items, int* __restrict__ ibeg, int nx,
+                                        int ny, LdsTiling tl, int ipt) {
+  using Ch = LdsChoice<T>;
+  const int ntile = tl.n_reg + tl.n_wide;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx <= ntile) {
+    ibeg[idx] = idx * ipt;
+  }
+  if (idx >= ntile * ipt) return;
+  const int t = idx / ipt, k = idx % ipt;
+  int X0, Y0, TWT, THT;
+  if (t < tl.n_reg) {
+    X0 = (t % tl.tiles_x) * tl.TW;
+    Y0 = (t / tl.tiles_x) * 16;
+    TWT = tl.TW;
+    THT = 16;
+  } else {
+    const int w = t - tl.n_reg;
+    X0 = (w % tl.tiles_xw) * 4 * tl.TW;
+    Y0 = tl.y_wide + (w / tl.tiles_xw) * 4;
+    TWT = 4 * tl.TW;
+    THT = 4;
+  }
+  const int dxlo = X0 - (nx - 1), dxhi = min(X0 + TWT - 1, nx - 1);
+  const int dylo = Y0 - (ny - 1), dyhi = min(Y0 + THT - 1, ny - 1);
+  const int nb = ((dxhi - dxlo + Ch::BX) / Ch::BX) * ((dyhi - dylo + Ch::BY) / Ch::BY);
+  const int chunk = (nb + ipt - 1) / ipt;
+  const int b0 = min(nb, k * chunk), b1 = min(nb, b0 + chunk);
+  items[idx] = LdsItem{t, b0, b1, 0};
+}
+
+// Bytes of the uniform-split matvec's buffers inside a caller-provided
+// region: items, ibeg, partial sums (each 256-byte aligned).
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+template <typename T>
+size_t lds_fixed_bytes(const Geometry& g, int R, int ipt) {
+  using Ch = LdsChoice<T>;
+  const LdsTiling tl = lds_tiling(g, 4 * Ch::GX);
+  const size_t ntile = (size_t)tl.n_reg + tl.n_wide;
+  const size_t nitems = ntile * ipt;
+  return align256(nitems * sizeof(LdsItem)) + align256((ntile + 1) * sizeof(int)) +
+         align256(nitems * 2 * R * (size_t)tl.TW * 16 * SLOTS * sizeof(cplx<T>));
+}
+// Items per tile of the default work split (about 16k workgroups).
+template <typename T>
+int lds_fixed_default_ipt(const Geometry& g, int R) {
+  using Ch = LdsChoice<T>;
+  const LdsTiling tl = lds_tiling(g, 4 * Ch::GX);
+  const int ntile = tl.n_reg + tl.n_wide;
+  const int target = std::max(1, (16384 + 2 * R - 1) / (2 * R));
+  return std::max(1, (target + ntile - 1) / ntile);
+}
+
+// The block matvec and its combine with every buffer inside `buf` (laid out
+// as lds_fixed_bytes says), the work split made on the device: enqueues only
+// kernels on the context stream (regular and wide tiles one after the other),
+// allocates nothing and never synchronises.
+template <typename T>
+int lds_apply_fixed(tm_ctx* c, int R, const void* table, const void* xin, const c128* x, c128* y,
+                    int op, int pf, int ipt, void* buf) {
+  using Ch = LdsChoice<T>;
+  const Geometry& g = c->g;
+  const LdsTiling tl = lds_tiling(g, 4 * Ch::GX);
+  const int ntile = tl.n_reg + tl.n_wide;
+  const int nitems = ntile * ipt;
+  char* p = static_cast<char*>(buf);
+  LdsItem* items = reinterpret_cast<LdsItem*>(p);
+  p += align256((size_t)nitems * sizeof(LdsItem));
+  int* ibeg = reinterpret_cast<int*>(p);
+  p += align256((size_t)(ntile + 1) * sizeof(int));
+  void* partial = p;
+  const int nth = std::max(nitems, ntile + 1);
+  hipLaunchKernelGGL(lds_uniform_plan_kernel<T>, dim3((nth + 255) / 256), dim3(256), 0, c->stream,
+                     items, ibeg, g.nx, g.ny, tl, ipt);
+  LdsArgs a;
+  a.table = table;
+  a.x = xin;
+  a.partial = partial;
+  a.items = items;
+  a.nx = g.nx;
+  a.ny = g.ny;
+  a.tnx = g.tnx;
+  a.tny = g.tny;
+  a.tiles_x = tl.tiles_x;
+  a.R = R;
+  a.n_sites = g.n;
+  a.subs = nullptr;
+  a.active = nullptr;
+  a.done = nullptr;
+  a.y_base = 0;
+  a.tile_base = 0;
+  a.item_base = 0;
+  const int nreg = tl.n_reg * ipt;
+  lds_launch_any<T, false>(c->stream, pf, nreg, R, a);
+  if (nitems > nreg) {
+    LdsArgs aw = a;
+    aw.tiles_x = tl.tiles_xw;
+    aw.y_base = tl.y_wide;
+    aw.tile_base = tl.n_reg;
+    aw.item_base = nreg;
+    lds_launch_any<T, true>(c->stream, pf, nitems - nreg, R, aw);
+  }
+  const long long vec = g.vec_len(), total = vec * R;
+  hipLaunchKernelGGL(lds_combine_kernel<T>, dim3((int)((total + 255) / 256)), dim3(256), 0, c->stream,
+                     (const cplx<T>*)partial, (const int*)ibeg, R, g.nx, tl, (long long)g.n, x,
+                     (const c128*)c->t64.p, y, vec, total, op);
+  TM_HIP(c, hipGetLastError());
+  return TM_OK;
+}
+template size_t lds_fixed_bytes<float>(const Geometry&, int, int);
+template size_t lds_fixed_bytes<double>(const Geometry&, int, int);
+template int lds_fixed_default_ipt<float>(const Geometry&, int);
+template int lds_fixed_default_ipt<double>(const Geometry&, int);
+template int lds_apply_fixed<float>(tm_ctx*, int, const void*, const void*, const c128*, c128*, int,
+                                    int, int, void*);
+template int lds_apply_fixed<double>(tm_ctx*, int, const void*, const void*, const c128*, c128*, int,
+                                     int, int, void*);
+
 template <typename T>
 void lds_geometry(int& TW, int& BX, int& BY) {
   TW = 4 * LdsChoice<T>::GX;

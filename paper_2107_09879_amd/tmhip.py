@@ -96,6 +96,7 @@ def load():
         "tm_solve": (I, [P, I, P, P, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo)]),
         "tm_adjoint_solve": (I, [P, I, P, P, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo)]),
         "tm_apply_operator": (I, [P, I, P, P, I, I]),
+        "tm_apply_operator_noalloc": (I, [P, I, P, P, I, I]),
         "tm_near_field": (I, [P, I, P, I, P, P, I]),
         "tm_near_field_adjoint": (I, [P, I, I, P, P, P]),
         "tm_mie": (I, [I, D, D, D, D, P, P]),
@@ -367,6 +368,18 @@ class Context:
         self._check(self.lib.tm_apply_operator(self.h, R, _ptr(x), _ptr(y), PRECISIONS[precision],
                                                OPS[op]))
         return y
+
+    def apply_operator_noalloc(self, x, out, op="forward", precision="fp64"):
+        """tm_apply_operator_noalloc: writes into the caller's `out` (same
+        shape as x); the library allocates nothing for the call."""
+        x = _dev(x, torch.complex128, "x", self.device, (self.n, self.L), 1)
+        out = _dev(out, torch.complex128, "out", self.device, (self.n, self.L), 1)
+        if out.shape != x.shape:
+            raise ValueError(f"out has shape {tuple(out.shape)}, x {tuple(x.shape)}")
+        R = _nrhs(x, 2)
+        self._check(self.lib.tm_apply_operator_noalloc(self.h, R, _ptr(x), _ptr(out),
+                                                       PRECISIONS[precision], OPS[op]))
+        return out
 
     # ---- readout
     def near_field(self, s, pts, precision="fp64"):
