@@ -37,7 +37,8 @@
  *
  * Scope: scatterers on a rectangular lattice in the z = 0 plane (the
  * metasurface setting of the paper), which lets the library tabulate one
- * translation block per lattice displacement.  lmax 1..3.
+ * translation block per lattice displacement.  lmax 1..6 (App. I.B's
+ * truncation; the paper's cylinders use lmax 6).
  */
 #ifndef TMHIP_H
 #define TMHIP_H
@@ -108,7 +109,7 @@ int tm_set_tmatrix_dense(tm_ctx* ctx, const tm_c128* T);
  * computed on the current HIP device, no context needed: t_out host
  * [2][lmax] with t_out[p*lmax + l-1] = -b_l (p = 0, M-type) or -a_l (p = 1,
  * N-type); dtdr_out host [2][lmax] or NULL: d t / d radius.  Requires
- * 1 <= lmax <= 3, k > 0, radius > 0, n_im >= 0 and k radius |n| <= 12.
+ * 1 <= lmax <= 6, k > 0, radius > 0, n_im >= 0 and k radius |n| <= 12.
  * Synchronous; allocates and frees a small device buffer. */
 int tm_mie(int lmax, double k, double radius, double n_re, double n_im, tm_c128* t_out,
            tm_c128* dtdr_out);
@@ -310,7 +311,10 @@ int tm_grad_radius(tm_ctx* ctx, int n_rhs, const tm_c128* mu, const tm_c128* s,
  * fetched 1, 2, 3 displacements ahead (FP64 runs variant 10 as 9: depth 3
  * does not fit its register budget), with 4-row "wide" tiles for rows past
  * the last multiple of 16.  items: target work items per (rhs, class) pair,
- * 0 = default.  All variants compute the same product. */
+ * 0 = default.  All variants compute the same product.  Variants 0..7 are
+ * written for lmax <= 3 (one 16-slot group per z-mirror class); at lmax 4..6
+ * a request for them runs the LDS-staged kernel (variant 9 FP64, 10
+ * complex64) instead. */
 int tm_set_matvec_config(tm_ctx* ctx, int precision, int variant, int items);
 int tm_get_matvec_config(tm_ctx* ctx, int precision, int* variant, int* items);
 

@@ -342,7 +342,7 @@ int tm_set_geometry(tm_ctx* c, int n, const double* pos, double k, int lmax) {
   CHECK_CTX(c);
   if (n < 1 || !pos) return tmh::set_err(c, TM_ERR_INVALID_ARG, "need n >= 1 positions");
   if (lmax < 1 || lmax > tmh::LMAX_SUPPORTED)
-    return tmh::set_err(c, TM_ERR_INVALID_ARG, "lmax must be in [1, 3]");
+    return tmh::set_err(c, TM_ERR_INVALID_ARG, "lmax must be in [1, 6]");
   if (!(k > 0.0) || !std::isfinite(k)) return tmh::set_err(c, TM_ERR_INVALID_ARG, "k must be > 0");
   for (int i = 0; i < 3 * n; ++i)
     if (!std::isfinite(pos[i])) return tmh::set_err(c, TM_ERR_NAN, "non-finite position");

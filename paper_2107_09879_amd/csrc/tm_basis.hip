@@ -194,7 +194,7 @@ __global__ void mie_kernel(const double* __restrict__ radii, int N, double k, do
     for (int mm = -l; mm <= l; ++mm)
       for (int p = 0; p < 2; ++p) {
         const int n = n_of_plm(p, l, mm, lmax);
-        const size_t o = ((size_t)mp.cls_of[n] * N + i) * SLOTS + mp.slot_of[n];
+        const size_t o = ((size_t)mp.cls_of[n] * N + i) * mp.S + mp.slot_of[n];
         t64[o] = c128{t[p][l].re, t[p][l].im};
         t32[o] = c64{(float)t[p][l].re, (float)t[p][l].im};
         dt64[o] = c128{dt[p][l].re, dt[p][l].im};
@@ -222,23 +222,23 @@ __global__ void set_t_kernel(const tm_c128* __restrict__ t, int N, SlotMaps mp,
   if (e >= (long long)N * mp.L) return;
   const int n = (int)(e % mp.L);
   const long long i = e / mp.L;
-  const size_t o = ((size_t)mp.cls_of[n] * N + i) * SLOTS + mp.slot_of[n];
+  const size_t o = ((size_t)mp.cls_of[n] * N + i) * mp.S + mp.slot_of[n];
   const tm_c128 v = t[e];
   t64[o] = c128{v.re, v.im};
   t32[o] = c64{(float)v.re, (float)v.im};
 }
 
 // Dense per-scatterer T (boundary order, T[i][n][n']) applied to slot-layout
-// vectors [R][class][site][16].  One thread per output element; pads give 0
+// vectors [R][class][site][S].  One thread per output element; pads give 0
 // (modes 0, 2) or x (mode 1, where x's pads are 0).
 __global__ void tdense_kernel(const tm_c128* __restrict__ T, SlotMaps mp, long long N, int mode,
                               const c128* __restrict__ x, const c128* __restrict__ z,
                               c128* __restrict__ y, long long total) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= total) return;
-  const int slot = (int)(e % SLOTS);
-  const long long site = (e / SLOTS) % N;
-  const long long rc = e / (SLOTS * N);
+  const int slot = (int)(e % mp.S);
+  const long long site = (e / mp.S) % N;
+  const long long rc = e / (mp.S * N);
   const long long r = rc / NCLASS;
   const int c = (int)(rc % NCLASS);
   const int n = mp.n_of[c][slot];
@@ -247,7 +247,7 @@ __global__ void tdense_kernel(const tm_c128* __restrict__ T, SlotMaps mp, long l
   if (n >= 0) {
     const tm_c128* Ti = T + (size_t)site * L * L;
     for (int n2 = 0; n2 < L; ++n2) {
-      const c128 zv = z[((size_t)(r * NCLASS + mp.cls_of[n2]) * N + site) * SLOTS + mp.slot_of[n2]];
+      const c128 zv = z[((size_t)(r * NCLASS + mp.cls_of[n2]) * N + site) * mp.S + mp.slot_of[n2]];
       const tm_c128 tv = mode == 2 ? Ti[(size_t)n2 * L + n] : Ti[(size_t)n * L + n2];
       ar += tv.re * zv.re - tv.im * zv.im;
       ai += tv.re * zv.im + tv.im * zv.re;
@@ -340,7 +340,8 @@ __global__ __launch_bounds__(256) void near_field_v2(
     const tm_c128* __restrict__ s, int N, int nx, double x0, double y0, double pitch, double k,
     const double* __restrict__ pts, int P, tm_c128* __restrict__ E) {
   constexpr int L = 2 * LMAX * (LMAX + 2), H = LMAX * (LMAX + 2);
-  constexpr int CHN = 32;
+  // spheres staged per LDS chunk: at most 48 KB of coefficients
+  constexpr int CHN = (LMAX <= 3) ? 32 : 8;
   __shared__ cplx<T> sh[CHN][R][L];
   const int ip = blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = ip < P;
@@ -503,7 +504,10 @@ static void nf_dispatch(int lmax, int R, dim3 g, hipStream_t st, const tm_c128* 
   switch (lmax) {
     case 1: nf_dispatch_r<T, 1>(R, g, st, s, N, nx, x0, y0, pitch, k, pts, P, E); break;
     case 2: nf_dispatch_r<T, 2>(R, g, st, s, N, nx, x0, y0, pitch, k, pts, P, E); break;
-    default: nf_dispatch_r<T, 3>(R, g, st, s, N, nx, x0, y0, pitch, k, pts, P, E); break;
+    case 3: nf_dispatch_r<T, 3>(R, g, st, s, N, nx, x0, y0, pitch, k, pts, P, E); break;
+    case 4: nf_dispatch_r<T, 4>(R, g, st, s, N, nx, x0, y0, pitch, k, pts, P, E); break;
+    case 5: nf_dispatch_r<T, 5>(R, g, st, s, N, nx, x0, y0, pitch, k, pts, P, E); break;
+    default: nf_dispatch_r<T, 6>(R, g, st, s, N, nx, x0, y0, pitch, k, pts, P, E); break;
   }
 }
 
@@ -513,10 +517,11 @@ static void nf_dispatch(int lmax, int R, dim3 g, hipStream_t st, const tm_c128* 
 // One workgroup per (rhs, direction): threads stride over scatterers to form
 // c_n = sum_i e^{-ik d.x_i} s_{i,n}, then a fixed-order wave + LDS reduction.
 constexpr int FF_THREADS = 256;
+template <int LMAXT>
 __global__ __launch_bounds__(FF_THREADS) void far_field_kernel(
     const tm_c128* __restrict__ s, int R, int N, int L, int lmax, int nx, double x0, double y0,
     double pitch, double k, const double* __restrict__ dirs, int D, tm_c128* __restrict__ F) {
-  constexpr int LM = 2 * LMAX_SUPPORTED * (LMAX_SUPPORTED + 2);
+  constexpr int LM = 2 * LMAXT * (LMAXT + 2);
   __shared__ double red[FF_THREADS / 64][2 * LM];
   const int e = blockIdx.x;
   const int r = e / D, id = e % D;
@@ -700,16 +705,16 @@ __global__ __launch_bounds__(256) void near_field_t_kernel(
 
 // grad[r][i] = 2 Re sum_slots mu * dt * aexc   (slot layout inputs)
 __global__ void grad_kernel(const c128* __restrict__ mu, const c128* __restrict__ dt,
-                            const c128* __restrict__ aexc, int R, int N, double* __restrict__ g) {
+                            const c128* __restrict__ aexc, int R, int N, int S, double* __restrict__ g) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (long long)R * N) return;
   const int r = (int)(e / N);
   const long long i = e % N;
   double acc = 0.0;
   for (int c = 0; c < NCLASS; ++c) {
-    for (int sl = 0; sl < SLOTS; ++sl) {
-      const size_t o = ((size_t)c * N + i) * SLOTS + sl;
-      const size_t ov = (size_t)r * NCLASS * N * SLOTS + o;
+    for (int sl = 0; sl < S; ++sl) {
+      const size_t o = ((size_t)c * N + i) * S + sl;
+      const size_t ov = (size_t)r * NCLASS * N * S + o;
       const c128 a = mu[ov], d = dt[o], b = aexc[ov];
       const double pr = a.re * d.re - a.im * d.im, pi = a.re * d.im + a.im * d.re;
       acc += pr * b.re - pi * b.im;
@@ -800,8 +805,19 @@ int launch_near_field(tm_ctx* c, int R, const tm_c128* s, int P, const double* p
 
 int launch_far_field(tm_ctx* c, int R, const tm_c128* s, int D, const double* dirs, tm_c128* F) {
   const Geometry& g = c->g;
-  hipLaunchKernelGGL(far_field_kernel, dim3((unsigned)((long long)R * D)), dim3(FF_THREADS), 0,
-                     c->stream, s, R, g.n, g.L, g.lmax, g.nx, g.x0, g.y0, g.pitch, g.k, dirs, D, F);
+#define FF_LAUNCH(LM)                                                                              \
+  hipLaunchKernelGGL(far_field_kernel<LM>, dim3((unsigned)((long long)R * D)), dim3(FF_THREADS), 0, \
+                     c->stream, s, R, g.n, g.L, g.lmax, g.nx, g.x0, g.y0, g.pitch, g.k, dirs, D, F)
+  // per-thread coefficient sums sized for the geometry's lmax
+  switch (g.lmax) {
+    case 1: FF_LAUNCH(1); break;
+    case 2: FF_LAUNCH(2); break;
+    case 3: FF_LAUNCH(3); break;
+    case 4: FF_LAUNCH(4); break;
+    case 5: FF_LAUNCH(5); break;
+    default: FF_LAUNCH(6); break;
+  }
+#undef FF_LAUNCH
   TM_HIP(c, hipGetLastError());
   return TM_OK;
 }
@@ -826,7 +842,7 @@ int launch_near_field_t(tm_ctx* c, int R, int P, const double* pts, const tm_c12
 int launch_grad(tm_ctx* c, int R, const c128* mu_slot, const c128* aexc_slot, double* grad) {
   const Geometry& g = c->g;
   hipLaunchKernelGGL(grad_kernel, dim3(nblk((long long)R * g.n)), dim3(256), 0, c->stream, mu_slot,
-                     (const c128*)c->dt64.p, aexc_slot, R, g.n, grad);
+                     (const c128*)c->dt64.p, aexc_slot, R, g.n, g.S, grad);
   TM_HIP(c, hipGetLastError());
   return TM_OK;
 }

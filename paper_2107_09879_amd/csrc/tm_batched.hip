@@ -83,8 +83,8 @@ __global__ void b_gather_rhs(const tm_c128* __restrict__ a0, const c128* __restr
   const SubParams p = sp[k];
   const long long Nk = (long long)p.nx * p.ny;
   long long q = e - p.vec_off;
-  const int slot = (int)(q % SLOTS);
-  q /= SLOTS;
+  const int slot = (int)(q % m.S);
+  q /= m.S;
   const long long site = q % Nk;
   q /= Nk;
   const int cls = (int)(q % NCLASS);
@@ -94,7 +94,7 @@ __global__ void b_gather_rhs(const tm_c128* __restrict__ a0, const c128* __restr
   c128 v{0.0, 0.0};
   if (n >= 0) {
     const tm_c128 a = a0[((long long)r * Nf + fs) * m.L + n];
-    const c128 tv = t[((long long)cls * Nf + fs) * SLOTS + slot];
+    const c128 tv = t[((long long)cls * Nf + fs) * m.S + slot];
     v = c128{tv.re * a.re - tv.im * a.im, tv.re * a.im + tv.im * a.re};
   }
   out[e] = v;
@@ -119,7 +119,7 @@ __global__ void b_unpack(const c128* __restrict__ in, const SubParams* __restric
   q /= m.L;
   const long long site = q % Nk;
   const int r = (int)(q / Nk);
-  const c128 v = in[p.vec_off + (((long long)r * NCLASS + m.cls_of[n]) * Nk + site) * SLOTS + m.slot_of[n]];
+  const c128 v = in[p.vec_off + (((long long)r * NCLASS + m.cls_of[n]) * Nk + site) * m.S + m.slot_of[n]];
   out[e] = tm_c128{v.re, v.im};
 }
 
@@ -139,7 +139,7 @@ __global__ void b_combine(const cplx<T>* __restrict__ partial, const int* __rest
                           const SubParams* __restrict__ sp, int S, int R, int TW, int nxf, long long Nf,
                           const c128* __restrict__ x, const c128* __restrict__ t,
                           c128* __restrict__ y, long long total, const int* __restrict__ active,
-                          const int* __restrict__ done) {
+                          const int* __restrict__ done, int SL, int NG) {
   if (done && *done) return;
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= total) return;
@@ -147,19 +147,21 @@ __global__ void b_combine(const cplx<T>* __restrict__ partial, const int* __rest
   const SubParams p = sp[k];
   const long long Nk = (long long)p.nx * p.ny;
   long long q = e - p.vec_off;
-  const int slot = (int)(q % SLOTS);
-  q /= SLOTS;
+  const int sl = (int)(q % SL);
+  q /= SL;
   const long long site = q % Nk;
   q /= Nk;
   const int cls = (int)(q % NCLASS);
   const int r = (int)(q / NCLASS);
   if (active && !active[k * R + r]) return;
+  const int slot = sl % SLOTS;
   const int sx = (int)(site % p.nx), sy = (int)(site / p.nx);
   const int tile = p.pad0 + (sy >> 4) * p.tiles_x + sx / TW;
   const int ls = (sy & 15) * TW + (sx % TW);
-  const int rc = r * NCLASS + cls;
+  // partial-sum row ((r * 2 + c) * NG + slot group)
+  const int rc = (r * NCLASS + cls) * NG + sl / SLOTS;
   // the tile's items in a fixed order, eight loads in flight (deterministic)
-  const size_t stride = (size_t)(2 * R) * (TW * 16) * SLOTS;
+  const size_t stride = (size_t)(2 * R * NG) * (TW * 16) * SLOTS;
   const cplx<T>* pp = partial + ((size_t)rc * (TW * 16) + ls) * SLOTS + slot;
   const int i1 = ibeg[tile + 1];
   double sr0 = 0.0, si0 = 0.0, sr1 = 0.0, si1 = 0.0;
@@ -183,7 +185,7 @@ __global__ void b_combine(const cplx<T>* __restrict__ partial, const int* __rest
   }
   const double sr = sr0 + sr1, si = si0 + si1;
   const long long fs = (long long)(p.oy + sy) * nxf + (p.ox + sx);
-  const c128 tv = t[((long long)cls * Nf + fs) * SLOTS + slot];
+  const c128 tv = t[((long long)cls * Nf + fs) * SL + sl];
   const c128 xv = x[e];
   y[e] = c128{xv.re - (tv.re * sr - tv.im * si), xv.im - (tv.re * si + tv.im * sr)};
 }
@@ -534,7 +536,7 @@ static int plan_precision(tm_ctx* c, Batch& B, int w, int target) {
   TM_HIP(c, hipMemcpy(B.d_ibeg[w].p, ibeg.data(), ibeg.size() * sizeof(int), hipMemcpyHostToDevice));
   B.nitems[w] = (int)items.size();
   B.items_tgt[w] = target;
-  const size_t pbytes = (size_t)B.nitems[w] * 2 * B.R * TW * 16 * SLOTS * sizeof(cplx<T>);
+  const size_t pbytes = (size_t)B.nitems[w] * 2 * B.R * c->g.NG * TW * 16 * SLOTS * sizeof(cplx<T>);
   return ensure_b(c, B.partial, pbytes);
 }
 
@@ -558,7 +560,7 @@ static int b_apply(tm_ctx* c, Batch& B, const c128* xin, c128* yout, const int* 
   hipLaunchKernelGGL(b_combine<T>, dim3(nbk(B.total)), dim3(BT), 0, c->stream,
                      (const cplx<T>*)B.partial.p, (const int*)B.d_ibeg[w].p,
                      B.sp_cur, B.S, B.R, B.TW, c->g.nx, (long long)c->g.n, xin,
-                     (const c128*)c->t64.p, yout, B.total, act, done);
+                     (const c128*)c->t64.p, yout, B.total, act, done, c->g.S, c->g.NG);
   return TM_OK;
 }
 
@@ -756,7 +758,7 @@ static int batched_impl(tm_ctx* c, int S, const tm_subregion* subs, int R, const
     p.vec_off = off;
     B.subs.push_back(p);
     B.out_off.push_back(ooff);
-    off += (long long)R * NCLASS * p.nx * p.ny * SLOTS;
+    off += (long long)R * NCLASS * p.nx * p.ny * g.S;
     ooff += (long long)R * p.nx * p.ny * g.L;
   }
   B.total = off;
@@ -766,7 +768,7 @@ static int batched_impl(tm_ctx* c, int S, const tm_subregion* subs, int R, const
   std::vector<SegBlock> blocks;
   std::vector<int> sysblk;
   for (int k = 0; k < S; ++k) {
-    const long long len = (long long)NCLASS * B.subs[k].nx * B.subs[k].ny * SLOTS;
+    const long long len = (long long)NCLASS * B.subs[k].nx * B.subs[k].ny * g.S;
     for (int r = 0; r < R; ++r) {
       sysblk.push_back((int)blocks.size());
       const long long lo = B.subs[k].vec_off + (long long)r * len;

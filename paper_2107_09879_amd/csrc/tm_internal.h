@@ -3,10 +3,12 @@
 // Internal vector layout ("slot layout"): the in-plane lattice makes every
 // translation block split into two classes c = (l + m + p) mod 2 (z-mirror
 // symmetry of App. I.C's alpha/beta: P_q^|mu|(0) vanishes unless q + |mu| is
-// even, alpha needs l+l'+q even and beta odd).  Each class holds L/2 <= 15
-// coefficients, padded to 16 slots, so a per-scatterer vector is stored as
-//   [rhs][class 0..1][site 0..N-1][slot 0..15]   complex
-// and a translation block per displacement as [class][16][16].  Pad slots are
+// even, alpha needs l+l'+q even and beta odd).  Each class holds L/2
+// coefficients (8, 15, 24, 35, 48 for lmax 2..6), padded to S = 16, 32 or 48
+// slots (whole groups of 16, the MFMA tile edge), so a per-scatterer vector
+// is stored as
+//   [rhs][class 0..1][site 0..N-1][slot 0..S-1]   complex
+// and a translation block per displacement as [class][S][S].  Pad slots are
 // zero in every table, T and vector, and stay zero under every operation.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -19,10 +21,14 @@
 
 namespace tmh {
 
-constexpr int SLOTS = 16;         // slots per class
+constexpr int SLOTS = 16;          // slots per group (the MFMA tile edge)
 constexpr int NCLASS = 2;
-constexpr int LMAX_SUPPORTED = 3; // 2*lmax(lmax+2)/2 <= 16
+constexpr int LMAX_SUPPORTED = 6;
+constexpr int SMAX = 48;           // slots per class at lmax 6 (48 members)
+constexpr int LM_MAX = 2 * LMAX_SUPPORTED * (LMAX_SUPPORTED + 2);  // 96 coefficients
 constexpr int QMAX = 2 * LMAX_SUPPORTED;
+// slots per class for lmax: L/2 = lmax(lmax+2) rounded up to a multiple of 16
+inline int slots_for_lmax(int lmax) { return SLOTS * ((lmax * (lmax + 2) + SLOTS - 1) / SLOTS); }
 
 template <typename T>
 struct cplx {
@@ -33,25 +39,26 @@ using c128 = cplx<double>;
 
 struct Geometry {
   int n = 0, nx = 0, ny = 0, lmax = 0, L = 0;
+  int S = SLOTS, NG = 1;                      // slots per class, groups of 16 per class
   double pitch = 0.0, k = 0.0, x0 = 0.0, y0 = 0.0;
   // slot map: for boundary index n -> class, slot; and per class the list
   std::vector<int> cls_of, slot_of;           // [L]
   std::vector<int> n_of[NCLASS];              // [class][slot] -> n or -1
   int tnx = 0, tny = 0;                       // table half extents (= nx, ny)
   long long n_disp() const { return (long long)(2 * tnx - 1) * (2 * tny - 1); }
-  long long vec_len() const { return (long long)NCLASS * n * SLOTS; }  // complex per RHS
+  long long vec_len() const { return (long long)NCLASS * n * S; }  // complex per RHS
 };
 
 // Device-side argument bundle for coefficient maps.
 struct SlotMaps {
-  int cls_of[2 * LMAX_SUPPORTED * (LMAX_SUPPORTED + 2)];
-  int slot_of[2 * LMAX_SUPPORTED * (LMAX_SUPPORTED + 2)];
-  int n_of[NCLASS][SLOTS];
-  int L, lmax;
+  int cls_of[LM_MAX];
+  int slot_of[LM_MAX];
+  int n_of[NCLASS][SMAX];
+  int L, lmax, S;
 };
 
 // One subregion of a batched solve: its lattice, the offset of its
-// [R][2][N_k][16] block in the packed vector, and its origin in the full
+// [R][2][N_k][S] block in the packed vector, and its origin in the full
 // lattice (for T and positions).
 struct SubParams {
   int nx, ny, tiles_x, ox;
@@ -93,10 +100,10 @@ struct tm_ctx {
   tmh::SlotMaps maps{};
   bool have_geom = false, have_t = false, have_dt = false;
   bool t_dense = false;  // T given as dense per-scatterer blocks (tden), not diagonal
-  // translation tables [D][2][16][16]
+  // translation tables [D][2][S][S]
   tmh::DevBuf tab64, tab32, tabT64, tabT32;
   bool have_tabT = false;
-  // T and dT/dr in slot layout [2][N][16]
+  // T and dT/dr in slot layout [2][N][S]
   tmh::DevBuf t64, t32, dt64;
   tmh::DevBuf tden, ttmp;  // dense T [N][L][L] (boundary order); its scratch vector
   // workspaces
@@ -166,7 +173,6 @@ int launch_mie_one(hipStream_t st, double radius, double k, double nre, double n
                    tm_c128* out);
 int launch_near_field_t(tm_ctx* c, int R, int P, const double* pts, const tm_c128* w, tm_c128* v);
 int launch_grad(tm_ctx* c, int R, const c128* mu_slot, const c128* aexc_slot, double* grad);
-
 // layout conversions (tm_krylov.hip)
 void pack_slots(hipStream_t st, const Geometry& g, const SlotMaps& m, int R, const tm_c128* in,
                 c128* out);
@@ -187,6 +193,9 @@ void launch_prep(hipStream_t st, const c128* x, const c128* t, void* out, long l
 // LDS-staged matvec with a device-made uniform work split (ipt items per
 // tile) and every buffer inside `buf` (tm_matvec_lds.hip); no allocation,
 // no host synchronisation
+template <typename T>
+int lds_apply(tm_ctx* c, int which, int R, const void* table, const void* xin, const c128* x,
+              c128* y, int op, int items_target, hipEvent_t e0, hipEvent_t e1, int pf);
 template <typename T>
 size_t lds_fixed_bytes(const Geometry& g, int R, int ipt);
 template <typename T>

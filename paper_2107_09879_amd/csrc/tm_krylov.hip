@@ -185,15 +185,15 @@ __global__ void mul_t_kernel(c128* __restrict__ out, const c128* __restrict__ t,
   out[e] = c128{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
 }
 
-// boundary [R][N][L] -> slot [R][2][N][16]
+// boundary [R][N][L] -> slot [R][2][N][S]
 __global__ void pack_kernel(const tm_c128* __restrict__ in, c128* __restrict__ out, SlotMaps m,
                             long long N, long long total) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= total) return;
-  const int slot = (int)(e % SLOTS);
-  const long long site = (e / SLOTS) % N;
-  const int cls = (int)((e / (SLOTS * N)) % NCLASS);
-  const long long r = e / (SLOTS * N * NCLASS);
+  const int slot = (int)(e % m.S);
+  const long long site = (e / m.S) % N;
+  const int cls = (int)((e / (m.S * N)) % NCLASS);
+  const long long r = e / (m.S * N * NCLASS);
   const int n = m.n_of[cls][slot];
   c128 v{0.0, 0.0};
   if (n >= 0) {
@@ -203,7 +203,7 @@ __global__ void pack_kernel(const tm_c128* __restrict__ in, c128* __restrict__ o
   out[e] = v;
 }
 
-// slot [R][2][N][16] -> boundary [R][N][L]
+// slot [R][2][N][S] -> boundary [R][N][L]
 __global__ void unpack_kernel(const c128* __restrict__ in, tm_c128* __restrict__ out, SlotMaps m,
                               long long N, long long total) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -211,7 +211,7 @@ __global__ void unpack_kernel(const c128* __restrict__ in, tm_c128* __restrict__
   const int n = (int)(e % m.L);
   const long long site = (e / m.L) % N;
   const long long r = e / (m.L * N);
-  const c128 v = in[((r * NCLASS + m.cls_of[n]) * N + site) * SLOTS + m.slot_of[n]];
+  const c128 v = in[((r * NCLASS + m.cls_of[n]) * N + site) * m.S + m.slot_of[n]];
   out[e] = tm_c128{v.re, v.im};
 }
 

@@ -451,7 +451,13 @@ static int apply_impl(tm_ctx* c, Op op, int R, const c128* x, c128* y) {
                        total);
     xin = (const cplx<T>*)c->xlow.p;
   }
-  if (c->mv_variant[which] >= LDS_VARIANT) {
+  // the direct kernels (variants 0..7) are written for one 16-slot group
+  // per class (lmax <= 3); larger lmax runs the LDS-staged kernel at the
+  // default prefetch depth
+  const int variant = (g.NG == 1 || c->mv_variant[which] >= LDS_VARIANT)
+                          ? c->mv_variant[which]
+                          : (std::is_same<T, double>::value ? LDS_VARIANT + 1 : LDS_VARIANT + 2);
+  if (variant >= LDS_VARIANT) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->prof) {
       TM_HIP(c, hipEventCreate(&e0));
@@ -459,7 +465,7 @@ static int apply_impl(tm_ctx* c, Op op, int R, const c128* x, c128* y) {
     }
     const int tgt = c->mv_items[which] > 0 ? c->mv_items[which] : default_items(R);
     rc = lds_apply<T>(c, which, R, table, xin, x, y, (int)op, tgt, e0, e1,
-                      c->mv_variant[which] - LDS_VARIANT + 1);
+                      variant - LDS_VARIANT + 1);
     if (c->prof && rc == TM_OK) {
       c->prof_pending[which].push_back({e0, e1});
       c->prof_acc[which].flops = matvec_flops(g) * R;

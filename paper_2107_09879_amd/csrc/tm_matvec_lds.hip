@@ -1,7 +1,7 @@
 // Block matvec with the source vectors staged in LDS.
 //
 // Same product as tm_matvec.hip (z_t = sum_{s != t} M(t - s) x_s over the
-// lattice, one 16x16 complex block per displacement and z-mirror class,
+// lattice, one S x S complex block per displacement and z-mirror class,
 // App. I.C / App. I.D), reorganised like a 2-D convolution: a workgroup owns
 // a target tile of (4*GX) x 16 sites and walks its displacement range in
 // blocks of BX x BY displacements.  For each block the (4*GX + BX - 1) x
@@ -12,7 +12,13 @@
 // table in global memory; both operands of the next displacement are fetched
 // while the current one's MFMAs run.
 //
-// K ordering: the 16 input slots are consumed as four MFMA K-steps; lane group
+// Slot groups: S = 16 NG slots per class.  A workgroup computes one group gg of
+// 16 target slots and loops over the NG source groups hh inside each
+// displacement block (a window per (block, hh)); its accumulators add every
+// hh, so its partial sums are final for (item, rhs, class, gg).  NG = 1 for
+// lmax <= 3.
+//
+// K ordering: the 16 input slots of a group are consumed as four MFMA K-steps; lane group
 // kq = lane/16 at step s supplies slot sigma(kq, s).  FP32: sigma = 2kq+s for
 // s < 2 and 8+2kq+s-2 otherwise, so each lane reads two 16-byte chunks (two
 // complex64 slots each); FP64: sigma = 4s+kq, four 16-byte chunks (one
@@ -61,9 +67,9 @@ struct LdsT<double> {
 };
 
 struct LdsArgs {
-  const void* table;  // [D][2][16][16]
-  const void* x;      // [R][2][N][16] (or packed per subregion)
-  void* partial;      // [item][R*2][tile sites][16]
+  const void* table;  // [D][2][S][S]
+  const void* x;      // [R][2][N][S] (or packed per subregion)
+  void* partial;      // [item][R*2*NG][tile sites][16]
   const LdsItem* items;
   int nx, ny, tnx, tny;
   int tiles_x, R;
@@ -77,19 +83,21 @@ struct LdsArgs {
   // wide-tile launch: rows at and beyond y_base are tiled 4 rows high; item
   // tile indices start at tile_base; partial slots at item_base
   int y_base, tile_base, item_base;
+  int S, NG;  // slots per class and its groups of 16
 };
 
-// A operand of one displacement: 4 (re, im) pairs in sigma order.
-__device__ inline void load_a(const c64* __restrict__ blk, int jt, int kq, float* ar, float* ai) {
-  const float4 p = *reinterpret_cast<const float4*>(blk + jt * SLOTS + 2 * kq);
-  const float4 q = *reinterpret_cast<const float4*>(blk + jt * SLOTS + 8 + 2 * kq);
+// A operand of one displacement (a 16 x 16 sub-block, rows S apart): 4 (re,
+// im) pairs in sigma order.
+__device__ inline void load_a(const c64* __restrict__ blk, int S, int jt, int kq, float* ar, float* ai) {
+  const float4 p = *reinterpret_cast<const float4*>(blk + jt * S + 2 * kq);
+  const float4 q = *reinterpret_cast<const float4*>(blk + jt * S + 8 + 2 * kq);
   ar[0] = p.x; ai[0] = p.y; ar[1] = p.z; ai[1] = p.w;
   ar[2] = q.x; ai[2] = q.y; ar[3] = q.z; ai[3] = q.w;
 }
-__device__ inline void load_a(const c128* __restrict__ blk, int jt, int kq, double* ar, double* ai) {
+__device__ inline void load_a(const c128* __restrict__ blk, int S, int jt, int kq, double* ar, double* ai) {
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
-    const double2 p = *reinterpret_cast<const double2*>(blk + jt * SLOTS + 4 * s + kq);
+    const double2 p = *reinterpret_cast<const double2*>(blk + jt * S + 4 * s + kq);
     ar[s] = p.x;
     ai[s] = p.y;
   }
@@ -150,8 +158,10 @@ __global__ __launch_bounds__(256, 2) void block_matvec_lds_kernel(LdsArgs a) {
   if (a.done && *a.done) return;
   const int item = a.item_base + blockIdx.x;
   const LdsItem it = a.items[item];
-  const int rc = blockIdx.y;
-  const int r = rc >> 1, c = rc & 1;
+  const int rc = blockIdx.y;  // ((r * 2 + c) * NG + gg)
+  const int NG = a.NG, S = a.S;
+  const int gg = rc % NG;
+  const int r = (rc / NG) >> 1, c = (rc / NG) & 1;
   int nx = a.nx, ny = a.ny, tiles_x = a.tiles_x;
   size_t N = (size_t)a.n_sites, voff = 0;
   if (a.subs) {
@@ -170,8 +180,8 @@ __global__ __launch_bounds__(256, 2) void block_matvec_lds_kernel(LdsArgs a) {
   const int gy0 = Y0 + (WIDE ? 0 : 4 * wave);
   const int gxw = X0 + wxo;
   const int ty = gy0 + ly;
-  const C* __restrict__ xin =
-      reinterpret_cast<const C*>(a.x) + voff + ((size_t)r * NCLASS + c) * N * SLOTS;
+  const C* __restrict__ xin0 =
+      reinterpret_cast<const C*>(a.x) + voff + ((size_t)r * NCLASS + c) * N * S;
   const C* __restrict__ tab = reinterpret_cast<const C*>(a.table);
   const int wxt = 2 * a.tnx - 1;
   // the tile's displacement range and its block grid
@@ -191,7 +201,10 @@ __global__ __launch_bounds__(256, 2) void block_matvec_lds_kernel(LdsArgs a) {
     t3[g] = acc_t{0, 0, 0, 0};
   }
 
-  for (int b = it.b0; b < it.b1; ++b) {
+  for (int bh = it.b0 * NG; bh < it.b1 * NG; ++bh) {
+    const int b = bh / NG, hh = bh % NG;
+    const C* __restrict__ xin = xin0 + SLOTS * hh;
+    const int boff = (SLOTS * gg) * S + SLOTS * hh;  // sub-block (gg, hh) of a table block
     const int bx0 = dxlo + (b % nbx) * BX;
     const int by0 = dylo + (b / nbx) * BY;
     // window origin: source site of target (X0, Y0) at displacement (bx0+BX-1, by0+BY-1)
@@ -204,7 +217,7 @@ __global__ __launch_bounds__(256, 2) void block_matvec_lds_kernel(LdsArgs a) {
       const int gx = wx0 + wx, gy = wy0 + wy;
       float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
       if (gx >= 0 && gx < nx && gy >= 0 && gy < ny)
-        v = *reinterpret_cast<const float4*>(xin + ((size_t)gy * nx + gx) * SLOTS + h * (SLOTS / CH));
+        v = *reinterpret_cast<const float4*>(xin + ((size_t)gy * nx + gx) * S + h * (SLOTS / CH));
       win[site * CH + L::swz(h, wx, wy)] = v;
     }
     __syncthreads();
@@ -231,7 +244,8 @@ __global__ __launch_bounds__(256, 2) void block_matvec_lds_kernel(LdsArgs a) {
       }
     };
     auto table_block = [&](int x, int y) {
-      return tab + (((size_t)(y + a.tny - 1) * wxt + (x + a.tnx - 1)) * NCLASS + c) * (SLOTS * SLOTS);
+      return tab + (((size_t)(y + a.tny - 1) * wxt + (x + a.tnx - 1)) * NCLASS + c) * (size_t)(S * S) +
+             boff;
     };
     auto read_all_b = [&](int x, int y, T (*r_)[4], T (*i_)[4]) {
       const int wy = (ty - Y0) - (y - by0) + BY - 1;
@@ -250,7 +264,7 @@ __global__ __launch_bounds__(256, 2) void block_matvec_lds_kernel(LdsArgs a) {
     int adx = dxb, ady = dyb, bdx = dxb, bdy = dyb, cdx = dxb, cdy = dyb;
 #pragma unroll
     for (int p = 0; p < PF; ++p) {
-      load_a(table_block(adx, ady), jt, kq, ar[p], ai[p]);
+      load_a(table_block(adx, ady), S, jt, kq, ar[p], ai[p]);
       advance_fetch(adx, ady);
     }
     read_all_b(bdx, bdy, br[0], bi[0]);
@@ -258,7 +272,7 @@ __global__ __launch_bounds__(256, 2) void block_matvec_lds_kernel(LdsArgs a) {
     // step q of the block, with q % U == K known at compile time
     auto step = [&](auto kc, int q) {
       constexpr int K = decltype(kc)::value;
-      load_a(table_block(adx, ady), jt, kq, ar[(K + PF) % U], ai[(K + PF) % U]);
+      load_a(table_block(adx, ady), S, jt, kq, ar[(K + PF) % U], ai[(K + PF) % U]);
       advance_fetch(adx, ady);
       read_all_b(bdx, bdy, br[(K + 1) % U], bi[(K + 1) % U]);
       advance_fetch(bdx, bdy);
@@ -302,7 +316,7 @@ __global__ __launch_bounds__(256, 2) void block_matvec_lds_kernel(LdsArgs a) {
     }
   }
   // this item's partial sums for every valid target of the tile
-  C* out = reinterpret_cast<C*>(a.partial) + ((size_t)item * (2 * a.R) + rc) * (TWT * THT * SLOTS);
+  C* out = reinterpret_cast<C*>(a.partial) + ((size_t)item * (2 * a.R * NG) + rc) * (TWT * THT * SLOTS);
   if (ty < ny) {
 #pragma unroll
     for (int g = 0; g < GX; ++g) {
@@ -442,12 +456,15 @@ template <typename T>
 __global__ void lds_combine_kernel(const cplx<T>* __restrict__ partial, const int* __restrict__ ibeg,
                                    int R, int nx, LdsTiling tl, long long N,
                                    const c128* __restrict__ x, const c128* __restrict__ t,
-                                   c128* __restrict__ y, long long vec, long long total, int mode) {
+                                   c128* __restrict__ y, long long vec, long long total, int mode,
+                                   int S, int NG) {
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= total) return;
-  const int slot = (int)(idx % SLOTS);
-  const long long site = (idx / SLOTS) % N;
-  const int rc = (int)(idx / (SLOTS * N));
+  const int sl = (int)(idx % S);
+  const long long site = (idx / S) % N;
+  // partial-sum row: ((r * 2 + c) * NG + slot group), slot within the group
+  const int rc = (int)(idx / (S * N)) * NG + sl / SLOTS;
+  const int slot = sl % SLOTS;
   const int sx = (int)(site % nx), sy = (int)(site / nx);
   const int TW = tl.TW;
   int tile, ls;
@@ -461,7 +478,7 @@ __global__ void lds_combine_kernel(const cplx<T>* __restrict__ partial, const in
   }
   // the tile's items in a fixed order, eight loads in flight and two
   // accumulator pairs (deterministic)
-  const size_t stride = (size_t)(2 * R) * (TW * 16) * SLOTS;
+  const size_t stride = (size_t)(2 * R * NG) * (TW * 16) * SLOTS;
   const cplx<T>* pp = partial + ((size_t)rc * (TW * 16) + ls) * SLOTS + slot;
   const int i1 = ibeg[tile + 1];
   double sr0 = 0.0, si0 = 0.0, sr1 = 0.0, si1 = 0.0;
@@ -518,7 +535,7 @@ template <typename T, int PF, bool WIDE>
 static void lds_launch_pf(hipStream_t st, int nitems, int R, const LdsArgs& a) {
   using Ch = LdsChoice<T>;
   hipLaunchKernelGGL((block_matvec_lds_kernel<T, Ch::GX, Ch::BX, Ch::BY, PF, WIDE>),
-                     dim3(nitems, 2 * R), dim3(256), 0, st, a);
+                     dim3(nitems, 2 * R * a.NG), dim3(256), 0, st, a);
 }
 // FP64 stages are twice as wide: depth 3 does not fit two waves' registers,
 // so FP64 runs depth 2 for variant 10
@@ -566,7 +583,8 @@ int lds_apply(tm_ctx* c, int which, int R, const void* table, const void* xin, c
     c->plan_nitems[which] = (int)items.size();
   }
   const int nitems = c->plan_nitems[which];
-  if ((rc = ensure(c, c->partial, (size_t)nitems * 2 * R * TW * 16 * SLOTS * sizeof(cplx<T>))) != TM_OK)
+  if ((rc = ensure(c, c->partial,
+                   (size_t)nitems * 2 * R * g.NG * TW * 16 * SLOTS * sizeof(cplx<T>))) != TM_OK)
     return rc;
   LdsArgs a;
   a.table = table;
@@ -586,6 +604,8 @@ int lds_apply(tm_ctx* c, int which, int R, const void* table, const void* xin, c
   a.y_base = 0;
   a.tile_base = 0;
   a.item_base = 0;
+  a.S = g.S;
+  a.NG = g.NG;
   const int nreg = c->plan_nreg[which];
   // the last ny mod 16 rows: wide tiles, launched on the side stream so that
   // their work groups fill the CUs the regular launch leaves idle at its tail
@@ -625,7 +645,7 @@ int lds_apply(tm_ctx* c, int which, int R, const void* table, const void* xin, c
     const int nb = (int)((total + 255) / 256);
     hipLaunchKernelGGL(lds_combine_kernel<T>, dim3(nb), dim3(256), 0, c->stream,
                        (const cplx<T>*)c->partial.p, (const int*)c->plan_ibeg[which].p, R, g.nx, tl,
-                       (long long)g.n, x, (const c128*)c->t64.p, y, vec, total, op);
+                       (long long)g.n, x, (const c128*)c->t64.p, y, vec, total, op, g.S, g.NG);
   }
   TM_HIP(c, hipGetLastError());
   return TM_OK;
@@ -676,7 +696,7 @@ size_t lds_fixed_bytes(const Geometry& g, int R, int ipt) {
   const size_t ntile = (size_t)tl.n_reg + tl.n_wide;
   const size_t nitems = ntile * ipt;
   return align256(nitems * sizeof(LdsItem)) + align256((ntile + 1) * sizeof(int)) +
-         align256(nitems * 2 * R * (size_t)tl.TW * 16 * SLOTS * sizeof(cplx<T>));
+         align256(nitems * 2 * R * (size_t)g.NG * tl.TW * 16 * SLOTS * sizeof(cplx<T>));
 }
 // Items per tile of the default work split (about 16k workgroups).
 template <typename T>
@@ -727,6 +747,8 @@ int lds_apply_fixed(tm_ctx* c, int R, const void* table, const void* xin, const 
   a.y_base = 0;
   a.tile_base = 0;
   a.item_base = 0;
+  a.S = g.S;
+  a.NG = g.NG;
   const int nreg = tl.n_reg * ipt;
   lds_launch_any<T, false>(c->stream, pf, nreg, R, a);
   if (nitems > nreg) {
@@ -740,7 +762,7 @@ int lds_apply_fixed(tm_ctx* c, int R, const void* table, const void* xin, const 
   const long long vec = g.vec_len(), total = vec * R;
   hipLaunchKernelGGL(lds_combine_kernel<T>, dim3((int)((total + 255) / 256)), dim3(256), 0, c->stream,
                      (const cplx<T>*)partial, (const int*)ibeg, R, g.nx, tl, (long long)g.n, x,
-                     (const c128*)c->t64.p, y, vec, total, op);
+                     (const c128*)c->t64.p, y, vec, total, op, g.S, g.NG);
   TM_HIP(c, hipGetLastError());
   return TM_OK;
 }
@@ -785,6 +807,8 @@ int lds_launch(tm_ctx* c, const void* table, const void* xin, void* partial, con
   a.y_base = 0;
   a.tile_base = 0;
   a.item_base = 0;
+  a.S = c->g.S;
+  a.NG = c->g.NG;
   lds_launch_any<T>(c->stream, pf, nitems, R, a);
   return TM_OK;
 }

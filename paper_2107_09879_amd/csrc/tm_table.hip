@@ -14,7 +14,7 @@
 // the host once per geometry (exact factorials); the per-displacement work --
 // Hankel functions, phases, sums, rounding to complex64 -- runs on the GPU.
 //
-// Table layout: [disp][class][16 target slots][16 source slots], with
+// Table layout: [disp][class][S target slots][S source slots], with
 // disp = (dy + tny - 1) * (2 tnx - 1) + (dx + tnx - 1); the dx = dy = 0 block
 // is zero so the matvec needs no special case for the excluded self term.
 // The transposed table holds the blocks of A^T: (A^T)_ts = xi(x_s - x_t) =
@@ -94,9 +94,11 @@ static void plm_of(int n, int lmax, int& p, int& l, int& m) {
 
 void host_slot_maps(int lmax, Geometry& g, SlotMaps& mp) {
   g.L = 2 * lmax * (lmax + 2);
+  g.S = slots_for_lmax(lmax);
+  g.NG = g.S / SLOTS;
   g.cls_of.assign(g.L, 0);
   g.slot_of.assign(g.L, 0);
-  for (int c = 0; c < NCLASS; ++c) g.n_of[c].assign(SLOTS, -1);
+  for (int c = 0; c < NCLASS; ++c) g.n_of[c].assign(g.S, -1);
   int cnt[NCLASS] = {0, 0};
   for (int n = 0; n < g.L; ++n) {
     int p, l, m;
@@ -110,37 +112,38 @@ void host_slot_maps(int lmax, Geometry& g, SlotMaps& mp) {
   mp = SlotMaps{};
   mp.L = g.L;
   mp.lmax = lmax;
+  mp.S = g.S;
   for (int n = 0; n < g.L; ++n) {
     mp.cls_of[n] = g.cls_of[n];
     mp.slot_of[n] = g.slot_of[n];
   }
   for (int c = 0; c < NCLASS; ++c)
-    for (int s = 0; s < SLOTS; ++s) mp.n_of[c][s] = g.n_of[c][s];
+    for (int s = 0; s < SMAX; ++s) mp.n_of[c][s] = s < g.S ? g.n_of[c][s] : -1;
 }
 
 // Host constants: coef[c][i][j][q] (i target slot, j source slot) and
 // dm[c][i][j] = m_src - m_tgt, sig[c][i] = (-1)^(l+p).
-static void host_table_constants(const Geometry& g, std::vector<double>& coef,
+static void host_table_constants(const Geometry& g, int Q, std::vector<double>& coef,
                                  std::vector<int>& dm, std::vector<int>& sig) {
-  const int Q = QMAX + 1;
-  coef.assign((size_t)NCLASS * SLOTS * SLOTS * Q * 2, 0.0);
-  dm.assign((size_t)NCLASS * SLOTS * SLOTS, 0);
-  sig.assign((size_t)NCLASS * SLOTS, 0);
+  const int S = g.S;
+  coef.assign((size_t)NCLASS * S * S * Q * 2, 0.0);
+  dm.assign((size_t)NCLASS * S * S, 0);
+  sig.assign((size_t)NCLASS * S, 0);
   for (int c = 0; c < NCLASS; ++c) {
-    for (int i = 0; i < SLOTS; ++i) {
+    for (int i = 0; i < S; ++i) {
       int nv = g.n_of[c][i];
       if (nv >= 0) {
         int pp, lp, mp;
         plm_of(nv, g.lmax, pp, lp, mp);
-        sig[c * SLOTS + i] = ((lp + pp) & 1) ? -1 : 1;
+        sig[c * S + i] = ((lp + pp) & 1) ? -1 : 1;
       }
-      for (int j = 0; j < SLOTS; ++j) {
+      for (int j = 0; j < S; ++j) {
         int nu = g.n_of[c][j];
         if (nu < 0 || nv < 0) continue;
         int p, l, m, pp, lp, mp;
         plm_of(nu, g.lmax, p, l, m);
         plm_of(nv, g.lmax, pp, lp, mp);
-        dm[(c * SLOTS + i) * SLOTS + j] = m - mp;
+        dm[(c * S + i) * S + j] = m - mp;
         double root = std::sqrt((2.0 * l + 1) * (2.0 * lp + 1) /
                                 (2.0 * l * (l + 1) * lp * (lp + 1)));
         double sgn = ((std::abs(m - mp)) & 1) ? -1.0 : 1.0;  // (-1)^(m-m')
@@ -161,7 +164,7 @@ static void host_table_constants(const Geometry& g, std::vector<double>& coef,
           val *= root * sgn * pbar_at_zero(q, std::abs(m - mp));
           double re, im;
           ipow(std::abs(m - mp) - std::abs(m) - std::abs(mp) + lp - l + q, re, im);
-          size_t o = ((((size_t)c * SLOTS + i) * SLOTS + j) * Q + q) * 2;
+          size_t o = ((((size_t)c * S + i) * S + j) * Q + q) * 2;
           coef[o] = re * val;
           coef[o + 1] = im * val;
         }
@@ -190,7 +193,7 @@ __device__ inline void hankel_up(double x, int qmax, double* hr, double* hi) {
 }
 
 // Per displacement d: h_q(k|d|) for q <= qmax (rad[d][q]) and e^{i mu phi}
-// for |mu| <= qmax (ang[d][mu + QMAX]), the transcendental part of every
+// for |mu| <= qmax (ang[d][mu + qmax]), the transcendental part of every
 // entry of the block, computed once per displacement.
 __global__ void table_radial_kernel(int tnx, int tny, double pitch, double k, int qmax,
                                     long long D, c128* __restrict__ rad, c128* __restrict__ ang) {
@@ -199,8 +202,8 @@ __global__ void table_radial_kernel(int tnx, int tny, double pitch, double k, in
   const int wx = 2 * tnx - 1;
   const int dx = (int)(d % wx) - (tnx - 1);
   const int dy = (int)(d / wx) - (tny - 1);
-  c128* rd = rad + d * (QMAX + 1);
-  c128* ad = ang + d * (2 * QMAX + 1);
+  c128* rd = rad + d * (qmax + 1);
+  c128* ad = ang + d * (2 * qmax + 1);
   double hr[QMAX + 1] = {0}, hi[QMAX + 1] = {0};
   double phi = 0.0;
   if (dx != 0 || dy != 0) {
@@ -208,39 +211,44 @@ __global__ void table_radial_kernel(int tnx, int tny, double pitch, double k, in
     phi = atan2(Y, X);
     hankel_up(k * sqrt(X * X + Y * Y), qmax, hr, hi);
   }
-  for (int q = 0; q <= QMAX; ++q) rd[q] = c128{q <= qmax ? hr[q] : 0.0, q <= qmax ? hi[q] : 0.0};
-  for (int mu = -QMAX; mu <= QMAX; ++mu) {
+  for (int q = 0; q <= qmax; ++q) rd[q] = c128{hr[q], hi[q]};
+  for (int mu = -qmax; mu <= qmax; ++mu) {
     double s, c;
     sincos((double)mu * phi, &s, &c);
-    ad[mu + QMAX] = c128{c, s};
+    ad[mu + qmax] = c128{c, s};
   }
 }
 
-// Thread = (class, target slot, source slot) entry of every block; the
-// workgroups stride over the displacements, the entry's coefficients stay
-// in registers: entry(d) = e^{i dm phi(d)} sum_q coef_q h_q(k|d|).
+// Thread = one (class, target slot, source slot) entry of every block
+// (blockIdx.y picks a range of 512 entries); the workgroups stride over the
+// displacements and the entry's coefficients stay in registers:
+// entry(d) = e^{i dm phi(d)} sum_q coef_q h_q(k|d|), q <= QM = 2 lmax.
 constexpr int TB_UNROLL = 4;
+template <int QM>
 __global__ __launch_bounds__(512) void build_table_kernel(
     const double* __restrict__ coef, const int* __restrict__ dm, const int* __restrict__ sig,
     const c128* __restrict__ rad, const c128* __restrict__ ang, c128* __restrict__ tab64,
-    c64* __restrict__ tab32, int tnx, int tny, long long D, int qmax, int transpose) {
-  const int c = threadIdx.x >> 8;
-  const int i = (threadIdx.x >> 4) & 15;
-  const int j = threadIdx.x & 15;
+    c64* __restrict__ tab32, int tnx, int tny, long long D, int S, int transpose) {
+  const int ent = blockIdx.y * 512 + threadIdx.x;
+  if (ent >= NCLASS * S * S) return;
+  const int c = ent / (S * S);
+  const int i = (ent / S) % S;
+  const int j = ent % S;
   // transposed table: MT[i][j] = sig_i sig_j M[j][i]
   const int ii = transpose ? j : i, jj = transpose ? i : j;
-  const int Q = QMAX + 1;
-  const double* cf = coef + ((((size_t)c * SLOTS + ii) * SLOTS + jj) * Q) * 2;
-  double ar[QMAX + 1], ai[QMAX + 1];
+  constexpr int Q = QM + 1;
+  const double* cf = coef + ((((size_t)c * S + ii) * S + jj) * Q) * 2;
+  double ar[Q], ai[Q];
 #pragma unroll
-  for (int q = 0; q <= QMAX; ++q) {
-    ar[q] = q <= qmax ? cf[2 * q] : 0.0;
-    ai[q] = q <= qmax ? cf[2 * q + 1] : 0.0;
+  for (int q = 0; q < Q; ++q) {
+    ar[q] = cf[2 * q];
+    ai[q] = cf[2 * q + 1];
   }
-  const int mu = dm[(c * SLOTS + ii) * SLOTS + jj] + QMAX;
-  const double sg = transpose ? (double)(sig[c * SLOTS + i] * sig[c * SLOTS + j]) : 1.0;
+  const int mu = dm[(c * S + ii) * S + jj] + QM;
+  const double sg = transpose ? (double)(sig[c * S + i] * sig[c * S + j]) : 1.0;
   const int wx = 2 * tnx - 1;
   const long long center = (long long)(tny - 1) * wx + (tnx - 1);  // d of (0, 0)
+  const size_t blk = (size_t)NCLASS * S * S;
   for (long long d0 = blockIdx.x; d0 < D; d0 += (long long)gridDim.x * TB_UNROLL) {
 #pragma unroll
     for (int u = 0; u < TB_UNROLL; ++u) {
@@ -249,15 +257,15 @@ __global__ __launch_bounds__(512) void build_table_kernel(
       const c128* rd = rad + d * Q;
       double sr = 0.0, si = 0.0;
 #pragma unroll
-      for (int q = 0; q <= QMAX; ++q) {
+      for (int q = 0; q < Q; ++q) {
         const c128 h = rd[q];
         sr += ar[q] * h.re - ai[q] * h.im;
         si += ar[q] * h.im + ai[q] * h.re;
       }
-      const c128 e = ang[d * (2 * QMAX + 1) + mu];
+      const c128 e = ang[d * (2 * QM + 1) + mu];
       double re = sg * (sr * e.re - si * e.im), im = sg * (sr * e.im + si * e.re);
       if (d == center) re = im = 0.0;
-      const size_t out = ((size_t)d * NCLASS + c) * SLOTS * SLOTS + (size_t)i * SLOTS + j;
+      const size_t out = (size_t)d * blk + (size_t)ent;
       tab64[out] = c128{re, im};
       tab32[out] = c64{(float)re, (float)im};
     }
@@ -268,9 +276,10 @@ static int build_impl(tm_ctx* c, DevBuf& t64, DevBuf& t32, int transpose) {
   const Geometry& g = c->g;
   std::vector<double> coef;
   std::vector<int> dm, sig;
-  host_table_constants(g, coef, dm, sig);
+  const int qmax = 2 * g.lmax;
+  host_table_constants(g, qmax + 1, coef, dm, sig);
   const long long D = g.n_disp();
-  const size_t blk = (size_t)NCLASS * SLOTS * SLOTS;
+  const size_t blk = (size_t)NCLASS * g.S * g.S;
   int rc;
   if ((rc = ensure(c, t64, (size_t)D * blk * sizeof(c128))) != TM_OK) return rc;
   if ((rc = ensure(c, t32, (size_t)D * blk * sizeof(c64))) != TM_OK) return rc;
@@ -280,8 +289,8 @@ static int build_impl(tm_ctx* c, DevBuf& t64, DevBuf& t32, int transpose) {
   TM_HIP(c, hipMalloc((void**)&dcoef, coef.size() * sizeof(double)));
   TM_HIP(c, hipMalloc((void**)&ddm, dm.size() * sizeof(int)));
   TM_HIP(c, hipMalloc((void**)&dsig, sig.size() * sizeof(int)));
-  TM_HIP(c, hipMalloc((void**)&rad, (size_t)D * (QMAX + 1) * sizeof(c128)));
-  TM_HIP(c, hipMalloc((void**)&ang, (size_t)D * (2 * QMAX + 1) * sizeof(c128)));
+  TM_HIP(c, hipMalloc((void**)&rad, (size_t)D * (qmax + 1) * sizeof(c128)));
+  TM_HIP(c, hipMalloc((void**)&ang, (size_t)D * (2 * qmax + 1) * sizeof(c128)));
   TM_HIP(c, hipMemcpyAsync(dcoef, coef.data(), coef.size() * sizeof(double),
                            hipMemcpyHostToDevice, c->stream));
   TM_HIP(c, hipMemcpyAsync(ddm, dm.data(), dm.size() * sizeof(int), hipMemcpyHostToDevice,
@@ -289,11 +298,24 @@ static int build_impl(tm_ctx* c, DevBuf& t64, DevBuf& t32, int transpose) {
   TM_HIP(c, hipMemcpyAsync(dsig, sig.data(), sig.size() * sizeof(int), hipMemcpyHostToDevice,
                            c->stream));
   hipLaunchKernelGGL(table_radial_kernel, dim3((unsigned)((D + 255) / 256)), dim3(256), 0, c->stream,
-                     g.tnx, g.tny, g.pitch, g.k, 2 * g.lmax, D, rad, ang);
-  const unsigned nwg = (unsigned)std::min<long long>(D, 4096);
-  hipLaunchKernelGGL(build_table_kernel, dim3(nwg), dim3(512), 0, c->stream, dcoef, ddm, dsig,
-                     (const c128*)rad, (const c128*)ang, (c128*)t64.p, (c64*)t32.p, g.tnx, g.tny, D,
-                     2 * g.lmax, transpose);
+                     g.tnx, g.tny, g.pitch, g.k, qmax, D, rad, ang);
+  const unsigned nchunk = (unsigned)((blk + 511) / 512);
+  const unsigned nwg = (unsigned)std::min<long long>(D, std::max(1u, 4096u / nchunk));
+  const dim3 grid(nwg, nchunk);
+  // the kernel's coefficient registers are sized by the Legendre/Hankel order
+#define TB_LAUNCH(QM)                                                                           \
+  hipLaunchKernelGGL(build_table_kernel<QM>, grid, dim3(512), 0, c->stream, dcoef, ddm, dsig,   \
+                     (const c128*)rad, (const c128*)ang, (c128*)t64.p, (c64*)t32.p, g.tnx, g.tny, \
+                     D, g.S, transpose)
+  switch (qmax) {
+    case 2: TB_LAUNCH(2); break;
+    case 4: TB_LAUNCH(4); break;
+    case 6: TB_LAUNCH(6); break;
+    case 8: TB_LAUNCH(8); break;
+    case 10: TB_LAUNCH(10); break;
+    default: TB_LAUNCH(12); break;
+  }
+#undef TB_LAUNCH
   TM_HIP(c, hipGetLastError());
   // the host vectors above are read by the async copies; wait before they go
   TM_HIP(c, hipStreamSynchronize(c->stream));

@@ -181,7 +181,7 @@ def test_tm_mie_single_sphere(lmax, radius, m):
         assert abs(d[0, l - 1] + K * db) <= 1e-11 * abs(K * db) + 1e-300
         assert abs(d[1, l - 1] + K * da) <= 1e-11 * abs(K * da) + 1e-300
     with pytest.raises(tmhip.TmError):
-        tmhip.mie(4, K, radius, m)
+        tmhip.mie(7, K, radius, m)
     with pytest.raises(tmhip.TmError):
         tmhip.mie(lmax, K, -radius, m)
 

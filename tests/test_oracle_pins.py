@@ -167,13 +167,14 @@ def test_translation_addition_theorem_pointwise():
         assert np.abs(rhs - lhs).max() / np.abs(lhs).max() < 1e-12
 
 
-def test_translation_by_projection():
+@pytest.mark.parametrize("lmax,xt", [(3, (0.6, -0.6, 0.0)), (6, (0.6, 0.0, 0.0)), (5, (0.4, 0.3, 0.5))])
+def test_translation_by_projection(lmax, xt):
     """Each xi_uv equals the projection of Phi_u(k(x-x_s)) onto R Phi_v on a
     sphere about x_t (Gauss-Legendre x trapezoid quadrature), an independent
-    route to the same coefficients."""
-    lmax = 3
+    route to the same coefficients (up to lmax 6, the nearest-neighbour
+    distance of the lattice included)."""
     xs = np.array([0.0, 0.0, 0.0])
-    xt = np.array([0.6, -0.6, 0.0])
+    xt = np.array(xt)
     rho0 = 0.2
     xg, wg = np.polynomial.legendre.leggauss(36)
     nphi = 72
@@ -203,15 +204,15 @@ def test_translation_by_projection():
         assert np.allclose(coef, X[:, v], atol=1e-11 * np.abs(X).max())
 
 
-def test_translation_inplane_parity_pattern():
+@pytest.mark.parametrize("lmax", [3, 4, 5, 6])
+def test_translation_inplane_parity_pattern(lmax):
     """For d in the z = 0 plane, xi couples only indices with equal
-    (l + m + p) mod 2 (z-mirror symmetry)."""
-    lmax = 3
+    (l + m + p) mod 2 (z-mirror symmetry); each class holds lmax(lmax+2)."""
     X = Translation(K, lmax).blocks(np.array([[0.6, 0.0, 0.0], [1.2, -1.8, 0.0], [-0.6, 2.4, 0.0]]))
     cls = np.array([(l + m + p) % 2 for p, l, m in index_list(lmax)])
     mask = cls[:, None] != cls[None, :]
     assert np.abs(X[:, mask]).max() < 1e-15 * np.abs(X).max() + 1e-300
-    assert np.count_nonzero(cls == 0) == 15
+    assert np.count_nonzero(cls == 0) == np.count_nonzero(cls == 1) == lmax * (lmax + 2)
     # and the sign rule for d -> -d: xi(-d) = sigma xi(d) sigma, sigma = (-1)^(l+p)
     sig = np.array([(-1) ** (l + p) for p, l, m in index_list(lmax)])
     d = np.array([1.2, -1.8, 0.0])
