@@ -14,6 +14,8 @@ from .solver import (LatticeCoupling, coupling_dense, detector_vectors,  # noqa:
                      extinction, far_field, gmres, near_field,
                      objective_and_gradient_dense, rows_A, scattering,
                      solve_dense, system_dense, tmatrix_dense)
+from .position import (detector_vector_gradient, objective_and_position_gradient_dense,  # noqa: F401
+                       objective_dense, translation_gradient)
 from .translation import Translation, ab5  # noqa: F401
 from .vswf import (index_list, n_coeffs, plane_wave_angular,  # noqa: F401
                    plane_wave_coeffs, vswf, vswf_farfield)
