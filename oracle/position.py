@@ -74,10 +74,16 @@ def translation_gradient(tr, d):
 
 
 def regular_at_origin(k):
-    """R Phi_v(0) [6, 3] for the lmax = 1 regular waves (only the N-type
-    ones are nonzero), evaluated at a point 1e-9 wavelengths from the centre
-    (the N-type l = 1 waves vary quadratically there)."""
-    return vswf(1, k, np.array([[0.0, 0.0, 1e-9]]), regular=True)[0]
+    """R Phi_v(0) [6, 3] for the lmax = 1 regular waves, the limit at their
+    own centre: means of the values at +-delta along z cancel the odd part of
+    the expansion about the centre, and Richardson extrapolation over delta
+    and 2 delta (delta = 1e-4 wavelengths) the delta^2 part, leaving
+    O((k delta)^4) ~ 2e-13 (only the N-type waves are nonzero there)."""
+    d = 1e-4
+    v = vswf(1, k, np.array([[0.0, 0.0, d], [0.0, 0.0, -d], [0.0, 0.0, 2 * d], [0.0, 0.0, -2 * d]]),
+             regular=True)
+    m1, m2 = 0.5 * (v[0] + v[1]), 0.5 * (v[2] + v[3])
+    return (4.0 * m1 - m2) / 3.0
 
 
 def detector_vector_gradient(positions, k, lmax, xd):

@@ -48,7 +48,22 @@ def test_detector_vector_gradient_matches_differences():
             p[i] = xi
             return detector_vectors(p, K, lmax, xd)[:, i, :]  # [c, n]
         ref = fd4(f, pos[i], 1e-4)  # [a, c, n]
-        assert np.abs(np.transpose(dv[:, i], (2, 0, 1)) - ref).max() <= 1e-8 * np.abs(ref).max()
+        assert np.abs(np.transpose(dv[:, i], (2, 0, 1)) - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+def test_regular_waves_at_their_centre():
+    """R Phi_v(0): the M-type l = 1 waves vanish there (j_1(0) = 0) and the
+    N-type ones are the constants of the l = 1 limit j_1(x)/x -> 1/3,
+    (x j_1)'/x -> 2/3 of the basis definition."""
+    from oracle.position import regular_at_origin
+
+    R0 = regular_at_origin(K)
+    a, b = np.sqrt(0.75) / 3, np.sqrt(1.5) / 3
+    ref = np.zeros((6, 3), dtype=complex)
+    ref[3] = a * np.array([1, -1j, 0])
+    ref[4] = b * np.array([0, 0, 1])
+    ref[5] = a * np.array([1, 1j, 0])
+    assert np.abs(R0 - ref).max() < 1e-12
 
 
 @pytest.mark.parametrize("khat,pol", [((0, 0, 1.0), (1.0, 0, 0)),
