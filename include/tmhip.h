@@ -239,6 +239,46 @@ int tm_solve_batched(tm_ctx* ctx, int n_sub, const tm_subregion* subs, int n_rhs
                      const double* khat, const tm_c128* pol, tm_c128* s_out,
                      const tm_solve_opts* opts, tm_solve_info* info, int use_graph);
 
+/* tm_solve_batched with the incident coefficients given per subregion (any
+ * source, e.g. the jinc groups of tm_jinc_rhs_batched): a0 device, the
+ * subregions' [R][N_k][L] blocks concatenated in subregion order (the layout
+ * of s_out); everything else as tm_solve_batched. */
+int tm_solve_batched_a0(tm_ctx* ctx, int n_sub, const tm_subregion* subs, int n_rhs,
+                        const tm_c128* a0, tm_c128* s_out, const tm_solve_opts* opts,
+                        tm_solve_info* info, int use_graph);
+
+/* Jinc source (App. II, "Computation of Jinc Sources"): one Nyquist sample
+ * of a band-limited incident field propagating along +z, centred at (x0, y0)
+ * in the plane z = z0 with transverse polarisation (ax, ay).  Its field is the
+ * disk of propagating plane waves
+ *   E(x) = (1/2pi) int_0^{pi/2} int_0^{2pi} A(b, a) e^{i k(b, a).(x - x0)} sin b cos b da db,
+ * A(b, a) = (ax, ay, -tan b (ax cos a + ay sin a)), whose transverse part in
+ * the plane z = z0 is (ax, ay) J_1(k rho)/(k rho) (cylindrical J_1).  A field
+ * band-limited to the light cone equals the sum of the jinc sources of its
+ * lambda/2-grid samples weighted by pi/2 times the sampled field. */
+typedef struct {
+  double x0, y0, z0;
+  tm_c128 ax, ay;
+} tm_jinc;
+
+/* Incident coefficients of jinc sources about every scatterer (App. II, the
+ * expansion in regular waves with the azimuthal integral in closed form,
+ * Gamma_m with Bessel J_{m-1}, J_{m+1}, and Gauss-Legendre quadrature in the
+ * polar angle): src host [R]; a0 device [R][N][L].  n_beta: polar nodes, 0 =
+ * 40 + k r_max (r_max the largest source-to-scatterer distance).  Each
+ * source must lie outside every scatterer's enclosing sphere. */
+int tm_jinc_rhs(tm_ctx* ctx, int n_src, const tm_jinc* src, int n_beta, tm_c128* a0);
+
+/* The same for subregions (the padded source groups of Sec. 2's
+ * distribution): system (k, r) is excited by the sum of the sources
+ * src[groups[k R + r]] .. src[groups[k R + r + 1] - 1] (host; groups [S R + 1],
+ * non-decreasing from 0 to n_src); a0 device, the subregions' [R][N_k][L]
+ * blocks concatenated in subregion order (the layout of tm_solve_batched's
+ * output; site index ly side_x + lx).  n_beta as above (0 = automatic over
+ * every group and its subregion). */
+int tm_jinc_rhs_batched(tm_ctx* ctx, int n_sub, const tm_subregion* subs, int n_rhs, int n_src,
+                        const tm_jinc* src, const int* groups, int n_beta, tm_c128* a0);
+
 /* 1 if the last tm_solve_batched replayed its restart cycles from a
  * captured hipGraph, 0 if it ran them eagerly. */
 int tm_batch_graph_used(const tm_ctx* ctx);
@@ -299,6 +339,28 @@ int tm_detector_vector(tm_ctx* ctx, const double* xd, const tm_c128* w, tm_c128*
  * eq. "grad_geometry_overlap"). */
 int tm_grad_radius(tm_ctx* ctx, int n_rhs, const tm_c128* mu, const tm_c128* s,
                    const tm_c128* a0, double* grad);
+
+/* Position gradient (App. IV, eq. "grad_pos_overlap"): the in-plane
+ * derivatives of an objective O with respect to every scatterer's position,
+ *   grad[r][i][a] = 2 Re[ lam^T (dA/dq_ia s + da0/dq_ia)
+ *                         + sum_c w_c (d v_c / dq_ia)^T s ],   a = x, y,
+ * with lam = T^T mu the adjoint unknown (mu from tm_adjoint_solve of the
+ * objective's weighted detector vector), v_c the detector vectors of
+ * tm_detector_vector.  The coupling term uses derivative blocks
+ * d xi(k d)^T / d d_a per lattice displacement (FP64 tables built on first use,
+ * four of the size of the FP64 translation table); the gradient is taken at
+ * the current lattice positions.
+ * mu, s, a0: device [R][N][L]; grad: device [R][N][2] doubles (written).
+ * khat: host [R][3], the plane-wave directions a0 was made with (the incident
+ * term i k khat_a lam_i . a0_i), or NULL when the incident field does not
+ * move with the scatterers (a0 may then be NULL).  xd: host [3] detector
+ * point and w: host [R][3] weights (w_c = f'(z_c), e.g. conj(E_c) for
+ * O = sum_c |E_c|^2) of the detector term, both NULL to omit it; xd must lie
+ * outside every enclosing sphere.  The out-of-plane derivative is not
+ * computed (it couples the two z-mirror classes of the lattice blocks). */
+int tm_grad_position(tm_ctx* ctx, int n_rhs, const tm_c128* mu, const tm_c128* s,
+                     const tm_c128* a0, const double* khat, const double* xd,
+                     const tm_c128* w, double* grad);
 
 /* ---- matvec launch configuration (autotuner) ----------------------------- */
 

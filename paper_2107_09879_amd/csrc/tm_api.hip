@@ -312,6 +312,8 @@ void tm_destroy(tm_ctx* c) {
   if (!c) return;
   hipSetDevice(c->device);
   hipStreamSynchronize(c->stream);
+  for (tmh::DevBuf* b : {&c->dtab[0], &c->dtab[1], &c->dtab[2], &c->dtab[3], &c->gpos, &c->jinc_buf})
+    tmh::release(*b);
   for (tmh::DevBuf* b : {&c->tab64, &c->tab32, &c->tabT64, &c->tabT32, &c->t64, &c->t32, &c->dt64,
                         &c->tden, &c->ttmp, &c->partial, &c->xlow, &c->work_a, &c->work_b, &c->work_c, &c->basis,
                         &c->dots, &c->dotpart, &c->scal, &c->plan_items[0], &c->plan_items[1],
@@ -377,7 +379,7 @@ int tm_set_geometry(tm_ctx* c, int n, const double* pos, double k, int lmax) {
   g.tnx = nx;
   g.tny = ny;
   tmh::host_slot_maps(lmax, g, c->maps);
-  c->have_geom = c->have_t = c->have_dt = c->have_tabT = c->t_dense = false;
+  c->have_geom = c->have_t = c->have_dt = c->have_tabT = c->have_dtab = c->t_dense = false;
   c->plan_R[0] = c->plan_R[1] = -1;
   int rc;
   if ((rc = tmh::build_tables(c)) != TM_OK) return rc;
@@ -581,6 +583,139 @@ int tm_apply_operator(tm_ctx* c, int R, const tm_c128* x, tm_c128* y, int precis
       TM_OK)
     return rc;
   tmh::unpack_slots(c->stream, g, c->maps, R, (const c128*)c->work_b.p, y);
+  TM_HIP(c, hipGetLastError());
+  return TM_OK;
+}
+
+namespace {
+int check_jinc(tm_ctx* c, int n, const tm_jinc* src) {
+  for (int j = 0; j < n; ++j) {
+    const tm_jinc& q = src[j];
+    const double v[7] = {q.x0, q.y0, q.z0, q.ax.re, q.ax.im, q.ay.re, q.ay.im};
+    for (double x : v)
+      if (!std::isfinite(x)) return tmh::set_err(c, TM_ERR_NAN, "non-finite jinc source " + std::to_string(j));
+  }
+  return TM_OK;
+}
+// polar nodes for the largest source-to-scatterer distance of a lattice box
+int jinc_nodes(const tmh::Geometry& g, int n, const tm_jinc* src, int ox, int oy, int sx, int sy) {
+  double rmax = 0.0;
+  for (int j = 0; j < n; ++j) {
+    const double xs[2] = {g.x0 + g.pitch * ox, g.x0 + g.pitch * (ox + sx - 1)};
+    const double ys[2] = {g.y0 + g.pitch * oy, g.y0 + g.pitch * (oy + sy - 1)};
+    for (double x : xs)
+      for (double y : ys)
+        rmax = std::max(rmax, std::sqrt((x - src[j].x0) * (x - src[j].x0) +
+                                        (y - src[j].y0) * (y - src[j].y0) + src[j].z0 * src[j].z0));
+  }
+  return tmh::jinc_beta_count(g.k, rmax);
+}
+}  // namespace
+
+int tm_jinc_rhs(tm_ctx* c, int R, const tm_jinc* src, int n_beta, tm_c128* a0) {
+  CHECK_CTX(c);
+  if (!c->have_geom) return tmh::set_err(c, TM_ERR_STATE, "set geometry first");
+  if (R < 1 || !src || !a0 || n_beta < 0 || n_beta > 100000)
+    return tmh::set_err(c, TM_ERR_INVALID_ARG, "bad arguments");
+  int rc;
+  if ((rc = check_jinc(c, R, src)) != TM_OK) return rc;
+  const tmh::Geometry& g = c->g;
+  const int nb = n_beta > 0 ? n_beta : jinc_nodes(g, R, src, 0, 0, g.nx, g.ny);
+  return tmh::launch_jinc_rhs(c, R, src, nb, a0);
+}
+
+int tm_jinc_rhs_batched(tm_ctx* c, int n_sub, const tm_subregion* subs, int R, int n_src,
+                        const tm_jinc* src, const int* groups, int n_beta, tm_c128* a0) {
+  CHECK_CTX(c);
+  if (!c->have_geom) return tmh::set_err(c, TM_ERR_STATE, "set geometry first");
+  if (n_sub < 1 || R < 1 || n_src < 0 || !subs || !groups || !a0 || (n_src > 0 && !src) || n_beta < 0 ||
+      n_beta > 100000)
+    return tmh::set_err(c, TM_ERR_INVALID_ARG, "bad arguments");
+  const tmh::Geometry& g = c->g;
+  if (groups[0] != 0 || groups[n_sub * R] != n_src)
+    return tmh::set_err(c, TM_ERR_INVALID_ARG, "groups must run from 0 to n_src");
+  for (int q = 0; q < n_sub * R; ++q)
+    if (groups[q + 1] < groups[q]) return tmh::set_err(c, TM_ERR_INVALID_ARG, "groups must not decrease");
+  for (int k = 0; k < n_sub; ++k) {
+    const tm_subregion& q = subs[k];
+    if (q.side_x < 1 || q.side_y < 1 || q.origin_x < 0 || q.origin_y < 0 ||
+        q.origin_x + q.side_x > g.nx || q.origin_y + q.side_y > g.ny)
+      return tmh::set_err(c, TM_ERR_INVALID_ARG, "subregion " + std::to_string(k) + " outside the lattice");
+  }
+  int rc;
+  if ((rc = check_jinc(c, n_src, src)) != TM_OK) return rc;
+  int nb = n_beta;
+  if (nb == 0) {
+    nb = 1;
+    for (int k = 0; k < n_sub; ++k)
+      for (int r = 0; r < R; ++r) {
+        const int j0 = groups[k * R + r], j1 = groups[k * R + r + 1];
+        if (j1 > j0)
+          nb = std::max(nb, jinc_nodes(g, j1 - j0, src + j0, subs[k].origin_x, subs[k].origin_y,
+                                       subs[k].side_x, subs[k].side_y));
+      }
+  }
+  return tmh::launch_jinc_rhs_packed(c, n_sub, subs, R, n_src, src, groups, nb, a0);
+}
+
+int tm_grad_position(tm_ctx* c, int R, const tm_c128* mu, const tm_c128* s, const tm_c128* a0,
+                     const double* khat, const double* xd, const tm_c128* w, double* grad) {
+  CHECK_CTX(c);
+  if (!c->have_geom || !c->have_t) return tmh::set_err(c, TM_ERR_STATE, "geometry and T must be set");
+  if (R < 1 || !mu || !s || !grad || (khat && !a0) || (!xd) != (!w))
+    return tmh::set_err(c, TM_ERR_INVALID_ARG, "bad arguments");
+  if (khat)
+    for (int q = 0; q < 3 * R; ++q)
+      if (!std::isfinite(khat[q])) return tmh::set_err(c, TM_ERR_NAN, "non-finite khat");
+  if (xd) {
+    for (int q = 0; q < 3; ++q)
+      if (!std::isfinite(xd[q])) return tmh::set_err(c, TM_ERR_NAN, "non-finite detector point");
+    for (int q = 0; q < 3 * R; ++q)
+      if (!std::isfinite(w[q].re) || !std::isfinite(w[q].im))
+        return tmh::set_err(c, TM_ERR_NAN, "non-finite detector weight");
+  }
+  const tmh::Geometry& g = c->g;
+  int rc;
+  if (!c->have_dtab && (rc = tmh::build_derivative_tables(c)) != TM_OK) return rc;
+  const long long vec = g.vec_len(), tot = (long long)R * vec;
+  std::vector<c128> dcoef;
+  std::vector<int> ddm;
+  tmh::detector_grad_constants(g.lmax, dcoef, ddm);
+  const size_t vb = (size_t)tot * sizeof(c128);
+  const size_t cb = dcoef.size() * sizeof(c128), db = ddm.size() * sizeof(int);
+  if ((rc = tmh::ensure(c, c->gpos, 7 * vb + cb + db)) != TM_OK) return rc;
+  c128* base = (c128*)c->gpos.p;
+  c128 *lam = base, *ss = base + tot, *aa = base + 2 * tot, *dxs = base + 3 * tot,
+       *dys = base + 4 * tot, *dxtl = base + 5 * tot, *dytl = base + 6 * tot;
+  c128* coef = base + 7 * tot;
+  int* dm = (int*)(coef + dcoef.size());
+  // lambda = T^T mu (the paper's adjoint unknown), in slot layout
+  tmh::pack_slots(c->stream, g, c->maps, R, mu, aa);
+  if (c->t_dense) {
+    if ((rc = tmh::launch_tdense(c, R, 2, nullptr, aa, lam)) != TM_OK) return rc;
+  } else {
+    tmh::k_mul_t(c->stream, lam, (const c128*)c->t64.p, aa, vec, R);
+  }
+  tmh::pack_slots(c->stream, g, c->maps, R, s, ss);
+  if (khat) tmh::pack_slots(c->stream, g, c->maps, R, a0, aa);
+  // the four derivative products (FP64 block matvec on the derivative tables)
+  const int tgt = c->mv_items[0] > 0 ? c->mv_items[0] : std::max(1, (16384 + 2 * R - 1) / (2 * R));
+  const void* src[4] = {ss, ss, lam, lam};
+  c128* dst[4] = {dxs, dys, dxtl, dytl};
+  for (int t = 0; t < 4; ++t)
+    if ((rc = tmh::lds_apply<double>(c, 0, R, c->dtab[t].p, src[t], nullptr, dst[t], TM_OP_COUPLING,
+                                     tgt, nullptr, nullptr, 2)) != TM_OK)
+      return rc;
+  if ((rc = tmh::launch_gpos_contract(c, R, lam, ss, khat ? aa : nullptr, dxs, dys, dxtl, dytl, khat,
+                                      grad)) != TM_OK)
+    return rc;
+  if (xd) {
+    TM_HIP(c, hipMemcpyAsync(coef, dcoef.data(), cb, hipMemcpyHostToDevice, c->stream));
+    TM_HIP(c, hipMemcpyAsync(dm, ddm.data(), db, hipMemcpyHostToDevice, c->stream));
+    if ((rc = tmh::launch_gpos_detector(c, R, s, coef, dm, xd, w, grad)) != TM_OK) return rc;
+    // the host constants are read by the asynchronous copies
+    TM_HIP(c, hipStreamSynchronize(c->stream));
+  }
   TM_HIP(c, hipGetLastError());
   return TM_OK;
 }

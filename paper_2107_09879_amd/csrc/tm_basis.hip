@@ -13,6 +13,7 @@
 // e^{im phi} / sqrt(2l(l+1)), Pbar normalised without Condon-Shortley phase,
 // pi = m Pbar / sin(theta), tau = d Pbar / d theta.
 #include <cmath>
+#include <vector>
 
 #include "tm_internal.h"
 
@@ -724,6 +725,426 @@ __global__ void grad_kernel(const c128* __restrict__ mu, const c128* __restrict_
 }
 
 static inline unsigned nblk(long long n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+// ---------------------------------------------------------------- position gradient
+// Coupling and incident terms of dO/dx_i, dO/dy_i (slot layout inputs):
+//   g_a = 2 Re[ lam_i . (D_a s)_i - s_i . (D_a^T lam)_i + i k khat_a lam_i . a0_i ],
+// lam = T^T mu, D_a the derivative blocks of the coupling operator.  One
+// thread per (rhs, scatterer); grad [R][N][2].
+struct GposArgs {
+  double kk[2 * 16];  // k khat_x, k khat_y per right-hand side of the chunk
+  int use_inc;
+};
+__global__ void gpos_contract_kernel(const c128* __restrict__ lam, const c128* __restrict__ s,
+                                     const c128* __restrict__ a0, const c128* __restrict__ dxs,
+                                     const c128* __restrict__ dys, const c128* __restrict__ dxtl,
+                                     const c128* __restrict__ dytl, int R, int N, int S, GposArgs ga,
+                                     double* __restrict__ grad) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)R * N) return;
+  const int r = (int)(e / N);
+  const long long i = e % N;
+  double gxr = 0.0, gyr = 0.0, ir = 0.0, ii = 0.0;
+  for (int c = 0; c < NCLASS; ++c) {
+    for (int sl = 0; sl < S; ++sl) {
+      const size_t o = (((size_t)r * NCLASS + c) * N + i) * S + sl;
+      const c128 l = lam[o], x = s[o];
+      const c128 p = dxs[o], q = dys[o], u = dxtl[o], v = dytl[o];
+      // Re(l p) - Re(x u)
+      gxr += (l.re * p.re - l.im * p.im) - (x.re * u.re - x.im * u.im);
+      gyr += (l.re * q.re - l.im * q.im) - (x.re * v.re - x.im * v.im);
+      if (ga.use_inc) {
+        const c128 b = a0[o];
+        ir += l.re * b.re - l.im * b.im;
+        ii += l.re * b.im + l.im * b.re;
+      }
+    }
+  }
+  // Re(i kk (ir + i ii)) = -kk ii
+  grad[e * 2 + 0] = 2.0 * (gxr - ga.kk[2 * r] * ii);
+  grad[e * 2 + 1] = 2.0 * (gyr - ga.kk[2 * r + 1] * ii);
+}
+
+// Detector term: grad[r][i][a] += 2 Re[ sum_u s_iu d/dx_i,a (sum_c w_c Phi_u(k(xd - x_i))_c) ]
+// for a = x, y.  By the addition theorem about x_d, Phi_u(k(xd - x_i)) =
+// sum_v xi_uv(k(xd - x_i)) R Phi_v(0); only the three N-type l' = 1 regular
+// waves are nonzero at their centre, so the derivative is
+// -sum_v grad xi_uv(d) W_v with W_v = w . R Phi_v(0) and
+// grad xi_uv = e^{i mu phi} sum_q C_uvq [k h_q' Pbar rhat + h_q tau thhat / r
+//                                         + i mu h_q (Pbar/sin) phhat / r].
+struct DgradArgs {
+  double W[16 * 3 * 2];  // W_v per right-hand side of the chunk (re, im)
+};
+__global__ void gpos_detector_kernel(const tm_c128* __restrict__ s, const c128* __restrict__ coef,
+                                     const int* __restrict__ dm, int R, int N, int L, int lmax,
+                                     int nx, double x0, double y0, double pitch, double k,
+                                     double xdx, double xdy, double xdz, DgradArgs wa,
+                                     double* __restrict__ grad) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)R * N) return;
+  const int r = (int)(e / N);
+  const long long i = e % N;
+  const double dx = xdx - (x0 + pitch * (double)(i % nx));
+  const double dy = xdy - (y0 + pitch * (double)(i / nx));
+  const double dz = xdz;
+  const double rho2 = dx * dx + dy * dy;
+  const double rr = sqrt(rho2 + dz * dz);
+  const double x = k * rr;
+  double sn, cs;
+  sincos(x, &sn, &cs);
+  cx<double> h[LMAX_SUPPORTED + 3];
+  hankel_set<double>(x, cs, sn, lmax + 2, h);
+  const double ct = dz / rr, st = sqrt(rho2) / rr;
+  double cf = 1.0, sf = 0.0;
+  if (rho2 > 0.0) {
+    cf = dx / sqrt(rho2);
+    sf = dy / sqrt(rho2);
+  }
+  const double rh[2] = {st * cf, st * sf}, th[2] = {ct * cf, ct * sf}, ph[2] = {-sf, cf};
+  const int Q = lmax + 2;
+  cx<double> acc[2];
+  const tm_c128* si = s + ((size_t)r * N + i) * L;
+  for (int u = 0; u < L; ++u) {
+    const cx<double> su(si[u].re, si[u].im);
+    for (int v = 0; v < 3; ++v) {
+      const cx<double> W(wa.W[(r * 3 + v) * 2], wa.W[(r * 3 + v) * 2 + 1]);
+      const int mu = dm[u * 3 + v], am = mu < 0 ? -mu : mu;
+      cx<double> gr, gt, gp;
+      for (int q = am; q < Q; ++q) {
+        const c128 cq = coef[((size_t)u * 3 + v) * Q + q];
+        if (cq.re == 0.0 && cq.im == 0.0) continue;
+        const cx<double> C(cq.re, cq.im);
+        double P, U, tau;
+        legendre_one<double>(q, am, ct, st, P, U, tau);
+        const cx<double> hq = h[q];
+        const cx<double> hp = (q == 0) ? cx<double>(-h[1].re, -h[1].im)
+                                       : h[q - 1] - ((double)(q + 1) / x) * hq;
+        gr = gr + (k * P) * (C * hp);
+        gt = gt + (tau / rr) * (C * hq);
+        gp = gp + ((double)mu * U / rr) * mul_i(C * hq);
+      }
+      double sm, cm;
+      sincos((double)mu * atan2(sf, cf), &sm, &cm);
+      const cx<double> em(cm, sm);
+      for (int a = 0; a < 2; ++a) {
+        const cx<double> G = em * (rh[a] * gr + th[a] * gt + ph[a] * gp);
+        acc[a] = acc[a] - su * (G * W);
+      }
+    }
+  }
+  grad[e * 2 + 0] += 2.0 * acc[0].re;
+  grad[e * 2 + 1] += 2.0 * acc[1].re;
+}
+
+int launch_gpos_contract(tm_ctx* c, int R, const c128* lam, const c128* s, const c128* a0,
+                         const c128* dxs, const c128* dys, const c128* dxtl, const c128* dytl,
+                         const double* khat, double* grad) {
+  const Geometry& g = c->g;
+  const long long vec = g.vec_len();
+  for (int r0 = 0; r0 < R; r0 += 16) {
+    const int nr = std::min(16, R - r0);
+    GposArgs ga{};
+    ga.use_inc = khat ? 1 : 0;
+    for (int r = 0; r < nr && khat; ++r) {
+      ga.kk[2 * r] = g.k * khat[3 * (r0 + r)];
+      ga.kk[2 * r + 1] = g.k * khat[3 * (r0 + r) + 1];
+    }
+    const size_t off = (size_t)r0 * vec;
+    hipLaunchKernelGGL(gpos_contract_kernel, dim3(nblk((long long)nr * g.n)), dim3(256), 0,
+                       c->stream, lam + off, s + off, a0 ? a0 + off : nullptr, dxs + off, dys + off,
+                       dxtl + off, dytl + off, nr, g.n, g.S, ga, grad + (size_t)r0 * g.n * 2);
+  }
+  TM_HIP(c, hipGetLastError());
+  return TM_OK;
+}
+
+int launch_gpos_detector(tm_ctx* c, int R, const tm_c128* s, const c128* coef, const int* dm,
+                         const double* xd, const tm_c128* w, double* grad) {
+  const Geometry& g = c->g;
+  // w . R Phi_v(0) for the N-type l' = 1 regular waves at their centre:
+  // R Phi_{1,-1}(0) = (1/3) sqrt(3/4) (1, -i, 0), R Phi_{1,0}(0) = (1/3) sqrt(3/2) (0, 0, 1),
+  // R Phi_{1,+1}(0) = (1/3) sqrt(3/4) (1, i, 0)  (j_1(r)/r -> 1/3, (r j_1)'/r -> 2/3)
+  const double a = sqrt(0.75) / 3.0, b = sqrt(1.5) / 3.0;
+  for (int r0 = 0; r0 < R; r0 += 16) {
+    const int nr = std::min(16, R - r0);
+    DgradArgs wa{};
+    for (int r = 0; r < nr; ++r) {
+      const tm_c128* wr = w + 3 * (r0 + r);
+      // (1, -i, 0) . w = wx - i wy ; (1, i, 0) . w = wx + i wy
+      wa.W[(r * 3 + 0) * 2] = a * (wr[0].re + wr[1].im);
+      wa.W[(r * 3 + 0) * 2 + 1] = a * (wr[0].im - wr[1].re);
+      wa.W[(r * 3 + 1) * 2] = b * wr[2].re;
+      wa.W[(r * 3 + 1) * 2 + 1] = b * wr[2].im;
+      wa.W[(r * 3 + 2) * 2] = a * (wr[0].re - wr[1].im);
+      wa.W[(r * 3 + 2) * 2 + 1] = a * (wr[0].im + wr[1].re);
+    }
+    hipLaunchKernelGGL(gpos_detector_kernel, dim3(nblk((long long)nr * g.n)), dim3(256), 0,
+                       c->stream, s + (size_t)r0 * g.n * g.L, coef, dm, nr, g.n, g.L, g.lmax, g.nx,
+                       g.x0, g.y0, g.pitch, g.k, xd[0], xd[1], xd[2], wa,
+                       grad + (size_t)r0 * g.n * 2);
+  }
+  TM_HIP(c, hipGetLastError());
+  return TM_OK;
+}
+
+
+
+// ---------------------------------------------------------------- jinc sources
+// Expansion coefficients of a jinc source (App. II, "Implementing jinc source
+// in the vector spherical harmonic basis") about every scatterer: the source
+// field is the disk of plane waves
+//   E(x) = (1/2pi) int int A(b, a) e^{i k(b, a).(x - x0)} sin b cos b da db,
+// and its coefficients about x_i integrate the plane-wave coefficients of App.
+// II over the disk with the field phase e^{i k.(x_i - x0)}.  The azimuthal
+// integral is taken in closed form,
+//   Gamma_m(xi, eta, rho) = (i^{m-1} e^{-i m xi}/2) [e^{i(xi-eta)} J_{m-1}(rho)
+//                                                   - e^{-i(xi-eta)} J_{m+1}(rho)],
+// with (rho_t, phi0, z_c) the cylindrical coordinates of x_i - x0 and
+// rho = k rho_t sin b; the polar integral is Gauss-Legendre on [0, pi/2].
+// One thread per (source, scatterer, coefficient), as the paper assigns them.
+
+// J_n(x) for |n| <= 8 and x >= 0: power series below x = 8 (at most three
+// digits of cancellation), else upward recurrence from J_0, J_1 (stable
+// while n < x); J_{-n} = (-1)^n J_n.
+__device__ inline double bessel_jn(int n, double x) {
+  const int an = n < 0 ? -n : n;
+  const double sg = (n < 0 && (an & 1)) ? -1.0 : 1.0;
+  double v;
+  if (x < 8.0) {
+    const double h = 0.5 * x, h2 = -h * h;
+    double term = 1.0;
+    for (int q = 1; q <= an; ++q) term *= h / (double)q;  // (x/2)^n / n!
+    double sum = term;
+    for (int kk = 1; kk < 60; ++kk) {
+      term *= h2 / ((double)kk * (double)(kk + an));
+      sum += term;
+      if (fabs(term) < 1e-17 * fabs(sum)) break;
+    }
+    v = sum;
+  } else {
+    double jm = j0(x), jc = j1(x);
+    if (an == 0) {
+      v = jm;
+    } else {
+      for (int q = 1; q < an; ++q) {
+        const double jn = (2.0 * q / x) * jc - jm;
+        jm = jc;
+        jc = jn;
+      }
+      v = jc;
+    }
+  }
+  return sg * v;
+}
+
+// Gamma_m(xi, eta, rho) from J_{m-1}(rho), J_{m+1}(rho)
+__device__ inline cx<double> gamma_m(int m, double xi, double eta, double jm1, double jp1) {
+  double s1, c1, s2, c2;
+  sincos(-(double)m * xi, &s1, &c1);
+  sincos(xi - eta, &s2, &c2);
+  const cx<double> pre = ipow<double>(m - 1) * cx<double>(0.5 * c1, 0.5 * s1);
+  const cx<double> br(c2 * jm1 - c2 * jp1, s2 * jm1 + s2 * jp1);  // e^{i d} J- - e^{-i d} J+
+  return pre * br;
+}
+
+// nodes: [nb][3] = (sin b, cos b, weight) of Gauss-Legendre on [0, pi/2]
+__device__ cx<double> jinc_coeff(int n, int lmax, double dx, double dy, double dz, double k,
+                                 cx<double> Ax, cx<double> Ay, const double* __restrict__ nodes,
+                                 int nb) {
+  int p, l, m;
+  plm_of_n(n, lmax, p, l, m);
+  const int am = m < 0 ? -m : m;
+  const double rho_t = sqrt(dx * dx + dy * dy);
+  const double phi0 = rho_t > 0.0 ? atan2(dy, dx) : 0.0;
+  const double nrm = -4.0 / sqrt(2.0 * l * (l + 1));
+  const cx<double> il = ipow<double>(p == 0 ? l : l + 1);
+  cx<double> acc;
+  for (int q = 0; q < nb; ++q) {
+    const double sb = nodes[3 * q], cb = nodes[3 * q + 1], w = nodes[3 * q + 2];
+    double P, U, tau;
+    legendre_one<double>(l, am, cb, sb, P, U, tau);
+    const double pi = (double)m * U;  // m Pbar / sin b
+    const double rho = k * rho_t * sb;
+    const double jm1 = bessel_jn(m - 1, rho), jp1 = bessel_jn(m + 1, rho);
+    const cx<double> g0 = gamma_m(m, phi0, 0.0, jm1, jp1);
+    const cx<double> g1 = gamma_m(m, phi0, 0.5 * 3.14159265358979323846, jm1, jp1);
+    cx<double> c0, c1;
+    if (p == 0) {
+      c0 = mul_i(pi * Ax) + (tau * cb) * Ay;
+      c1 = mul_i(pi * Ay) - (tau * cb) * Ax;
+    } else {
+      c0 = tau * Ax - mul_i((pi * cb) * Ay);
+      c1 = tau * Ay + mul_i((pi * cb) * Ax);
+    }
+    double sz, cz;
+    sincos(k * dz * cb, &sz, &cz);
+    acc = acc + (w * nrm * sb) * (cx<double>(cz, sz) * (c0 * g0 + c1 * g1));
+  }
+  return il * acc;
+}
+
+struct JincSrc {
+  double x0, y0, z0;
+  double axr, axi, ayr, ayi;
+};
+
+// a0[r][i][n] = coefficients of source r about scatterer i (one lattice)
+__global__ void jinc_rhs_kernel(const JincSrc* __restrict__ src, int R, int N, int L, int lmax,
+                                int nx, double x0, double y0, double pitch, double k,
+                                const double* __restrict__ nodes, int nb, tm_c128* __restrict__ a0) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)R * N * L) return;
+  const int n = (int)(e % L);
+  const long long i = (e / L) % N;
+  const int r = (int)(e / ((long long)L * N));
+  const JincSrc s = src[r];
+  const double xi = x0 + pitch * (double)(i % nx), yi = y0 + pitch * (double)(i / nx);
+  const cx<double> v = jinc_coeff(n, lmax, xi - s.x0, yi - s.y0, -s.z0, k, cx<double>(s.axr, s.axi),
+                                  cx<double>(s.ayr, s.ayi), nodes, nb);
+  a0[e] = tm_c128{v.re, v.im};
+}
+
+// Packed subregion layout [S][R][N_k][L] (concatenated): system (k, r) gets
+// the sum over its group of sources src[grp[k R + r] .. grp[k R + r + 1]).
+__global__ void jinc_rhs_packed_kernel(const JincSrc* __restrict__ src, const int* __restrict__ grp,
+                                       const SubParams* __restrict__ sp,
+                                       const long long* __restrict__ out_off, int S, int R, int L,
+                                       int lmax, double x0, double y0, double pitch, double k,
+                                       const double* __restrict__ nodes, int nb, long long total,
+                                       tm_c128* __restrict__ a0) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  int lo = 0, hi = S - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (out_off[mid] <= e) lo = mid;
+    else hi = mid - 1;
+  }
+  const SubParams p = sp[lo];
+  const long long Nk = (long long)p.nx * p.ny;
+  long long q = e - out_off[lo];
+  const int n = (int)(q % L);
+  q /= L;
+  const long long site = q % Nk;
+  const int r = (int)(q / Nk);
+  const double xi = x0 + pitch * (double)(p.ox + site % p.nx);
+  const double yi = y0 + pitch * (double)(p.oy + site / p.nx);
+  cx<double> acc;
+  for (int j = grp[lo * R + r]; j < grp[lo * R + r + 1]; ++j) {
+    const JincSrc s = src[j];
+    acc = acc + jinc_coeff(n, lmax, xi - s.x0, yi - s.y0, -s.z0, k, cx<double>(s.axr, s.axi),
+                           cx<double>(s.ayr, s.ayi), nodes, nb);
+  }
+  a0[e] = tm_c128{acc.re, acc.im};
+}
+
+// Gauss-Legendre nodes on [0, pi/2] (Newton on P_n from the Chebyshev-like
+// first guesses) as (sin b, cos b, weight) triples.
+static void beta_nodes(int n, std::vector<double>& out) {
+  out.assign((size_t)3 * n, 0.0);
+  const double pi = 3.14159265358979323846;
+  for (int i = 0; i < n; ++i) {
+    double z = cos(pi * (i + 0.75) / (n + 0.5)), pp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int j = 2; j <= n; ++j) {
+        const double p2 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p0) / j;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (n == 1) {
+        p1 = z;
+        p0 = 1.0;
+      }
+      pp = n * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / pp;
+      z -= dz;
+      if (fabs(dz) < 1e-16) break;
+    }
+    const double w = 2.0 / ((1.0 - z * z) * pp * pp);
+    const double b = 0.25 * pi * (z + 1.0);
+    out[3 * i] = sin(b);
+    out[3 * i + 1] = cos(b);
+    out[3 * i + 2] = 0.25 * pi * w;
+  }
+}
+
+// Polar nodes for sources up to a distance rmax from the scatterers: the
+// integrand oscillates like e^{i k z cos b} J(k rho sin b), k rmax radians over
+// the interval.
+int jinc_beta_count(double k, double rmax) { return 40 + (int)ceil(k * rmax); }
+
+static int upload_jinc(tm_ctx* c, int nsrc, const tm_jinc* src, int nb, DevBuf& buf,
+                       JincSrc** dsrc, double** dnodes, size_t extra, void** dextra) {
+  std::vector<JincSrc> hs((size_t)nsrc);
+  for (int j = 0; j < nsrc; ++j)
+    hs[j] = JincSrc{src[j].x0, src[j].y0, src[j].z0, src[j].ax.re, src[j].ax.im, src[j].ay.re,
+                    src[j].ay.im};
+  std::vector<double> nodes;
+  beta_nodes(nb, nodes);
+  const size_t sb = ((hs.size() * sizeof(JincSrc)) + 255) & ~(size_t)255;
+  const size_t nbb = ((nodes.size() * sizeof(double)) + 255) & ~(size_t)255;
+  int rc;
+  if ((rc = ensure(c, buf, sb + nbb + extra)) != TM_OK) return rc;
+  *dsrc = (JincSrc*)buf.p;
+  *dnodes = (double*)((char*)buf.p + sb);
+  if (dextra) *dextra = (char*)buf.p + sb + nbb;
+  TM_HIP(c, hipMemcpyAsync(*dsrc, hs.data(), hs.size() * sizeof(JincSrc), hipMemcpyHostToDevice,
+                           c->stream));
+  TM_HIP(c, hipMemcpyAsync(*dnodes, nodes.data(), nodes.size() * sizeof(double),
+                           hipMemcpyHostToDevice, c->stream));
+  // the host vectors die with this call: wait for the copies
+  TM_HIP(c, hipStreamSynchronize(c->stream));
+  return TM_OK;
+}
+
+int launch_jinc_rhs(tm_ctx* c, int R, const tm_jinc* src, int nb, tm_c128* a0) {
+  const Geometry& g = c->g;
+  JincSrc* dsrc;
+  double* dnodes;
+  int rc;
+  if ((rc = upload_jinc(c, R, src, nb, c->jinc_buf, &dsrc, &dnodes, 0, nullptr)) != TM_OK) return rc;
+  const long long total = (long long)R * g.n * g.L;
+  hipLaunchKernelGGL(jinc_rhs_kernel, dim3(nblk(total)), dim3(256), 0, c->stream, dsrc, R, g.n, g.L,
+                     g.lmax, g.nx, g.x0, g.y0, g.pitch, g.k, dnodes, nb, a0);
+  TM_HIP(c, hipGetLastError());
+  return TM_OK;
+}
+
+int launch_jinc_rhs_packed(tm_ctx* c, int S, const tm_subregion* subs, int R, int nsrc,
+                           const tm_jinc* src, const int* grp, int nb, tm_c128* a0) {
+  const Geometry& g = c->g;
+  std::vector<SubParams> sp((size_t)S);
+  std::vector<long long> off((size_t)S);
+  long long tot = 0;
+  for (int k = 0; k < S; ++k) {
+    sp[k] = SubParams{subs[k].side_x, subs[k].side_y, 0, subs[k].origin_x, subs[k].origin_y, 0, 0};
+    off[k] = tot;
+    tot += (long long)R * subs[k].side_x * subs[k].side_y * g.L;
+  }
+  const size_t b_sp = ((sp.size() * sizeof(SubParams)) + 255) & ~(size_t)255;
+  const size_t b_off = ((off.size() * sizeof(long long)) + 255) & ~(size_t)255;
+  const size_t b_grp = (size_t)(S * R + 1) * sizeof(int);
+  JincSrc* dsrc;
+  double* dnodes;
+  void* dx;
+  int rc;
+  if ((rc = upload_jinc(c, nsrc, src, nb, c->jinc_buf, &dsrc, &dnodes, b_sp + b_off + b_grp, &dx)) !=
+      TM_OK)
+    return rc;
+  SubParams* dsp = (SubParams*)dx;
+  long long* doff = (long long*)((char*)dx + b_sp);
+  int* dgrp = (int*)((char*)dx + b_sp + b_off);
+  TM_HIP(c, hipMemcpyAsync(dsp, sp.data(), sp.size() * sizeof(SubParams), hipMemcpyHostToDevice, c->stream));
+  TM_HIP(c, hipMemcpyAsync(doff, off.data(), off.size() * sizeof(long long), hipMemcpyHostToDevice, c->stream));
+  TM_HIP(c, hipMemcpyAsync(dgrp, grp, b_grp, hipMemcpyHostToDevice, c->stream));
+  hipLaunchKernelGGL(jinc_rhs_packed_kernel, dim3(nblk(tot)), dim3(256), 0, c->stream, dsrc, dgrp, dsp,
+                     doff, S, R, g.L, g.lmax, g.x0, g.y0, g.pitch, g.k, dnodes, nb, tot, a0);
+  TM_HIP(c, hipGetLastError());
+  // the host arrays above are read by the asynchronous copies
+  TM_HIP(c, hipStreamSynchronize(c->stream));
+  return TM_OK;
+}
 
 int launch_mie(tm_ctx* c, const double* radii, double n_re, double n_im) {
   const Geometry& g = c->g;

@@ -100,6 +100,35 @@ __global__ void b_gather_rhs(const tm_c128* __restrict__ a0, const c128* __restr
   out[e] = v;
 }
 
+// b = t * a0 from caller-given subregion coefficients: a0 boundary
+// [S][R][N_k][L] (concatenated, the output layout) -> packed slot layout
+__global__ void b_gather_packed_rhs(const tm_c128* __restrict__ a0, const long long* __restrict__ out_off,
+                                    const c128* __restrict__ t, const SubParams* __restrict__ sp,
+                                    int S, int R, int nxf, long long Nf, SlotMaps m, long long total,
+                                    c128* __restrict__ out) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const int k = find_sub(sp, S, e, R);
+  const SubParams p = sp[k];
+  const long long Nk = (long long)p.nx * p.ny;
+  long long q = e - p.vec_off;
+  const int slot = (int)(q % m.S);
+  q /= m.S;
+  const long long site = q % Nk;
+  q /= Nk;
+  const int cls = (int)(q % NCLASS);
+  const int r = (int)(q / NCLASS);
+  const long long fs = (long long)(p.oy + site / p.nx) * nxf + (p.ox + site % p.nx);
+  const int n = m.n_of[cls][slot];
+  c128 v{0.0, 0.0};
+  if (n >= 0) {
+    const tm_c128 a = a0[out_off[k] + ((long long)r * Nk + site) * m.L + n];
+    const c128 tv = t[((long long)cls * Nf + fs) * m.S + slot];
+    v = c128{tv.re * a.re - tv.im * a.im, tv.re * a.im + tv.im * a.re};
+  }
+  out[e] = v;
+}
+
 // packed slot layout -> boundary [S][R][N_k][L] (concatenated, same order)
 __global__ void b_unpack(const c128* __restrict__ in, const SubParams* __restrict__ sp,
                          const long long* __restrict__ out_off, int S, int R, SlotMaps m,
@@ -733,8 +762,8 @@ static int run_cycle(tm_ctx* c, Batch& B, bool use_graph, bool& graphed) {
 }
 
 static int batched_impl(tm_ctx* c, int S, const tm_subregion* subs, int R, const double* khat,
-                        const tm_c128* pol, tm_c128* s_out, const tm_solve_opts& o,
-                        tm_solve_info* info, int use_graph) {
+                        const tm_c128* pol, const tm_c128* a0_packed, tm_c128* s_out,
+                        const tm_solve_opts& o, tm_solve_info* info, int use_graph) {
   const Geometry& g = c->g;
   Batch B;
   B.ctx_stream = c->stream;
@@ -832,14 +861,21 @@ static int batched_impl(tm_ctx* c, int S, const tm_subregion* subs, int R, const
     B.TW = w ? TW : TW64;
   };
 
-  // right-hand side: plane waves on the full lattice, gathered and times T
+  // right-hand side: plane waves on the full lattice, gathered and times T,
+  // or the caller's per-subregion coefficients times T
   DevBuf& a0full = B.a0full;
-  if ((rc = ensure_b(c, a0full, (size_t)R * g.n * g.L * cb)) != TM_OK) return rc;
-  if ((rc = launch_plane_wave(c, R, khat, pol, (tm_c128*)a0full.p)) != TM_OK) return rc;
   use_sp(1);
-  hipLaunchKernelGGL(b_gather_rhs, dim3(nbk(Lt)), dim3(BT), 0, c->stream, (const tm_c128*)a0full.p,
-                     (const c128*)c->t64.p, B.sp_cur, S, R, g.nx, (long long)g.n,
-                     c->maps, Lt, (c128*)B.b.p);
+  if (a0_packed) {
+    hipLaunchKernelGGL(b_gather_packed_rhs, dim3(nbk(Lt)), dim3(BT), 0, c->stream, a0_packed,
+                       (const long long*)B.d_out_off.p, (const c128*)c->t64.p, B.sp_cur, S, R, g.nx,
+                       (long long)g.n, c->maps, Lt, (c128*)B.b.p);
+  } else {
+    if ((rc = ensure_b(c, a0full, (size_t)R * g.n * g.L * cb)) != TM_OK) return rc;
+    if ((rc = launch_plane_wave(c, R, khat, pol, (tm_c128*)a0full.p)) != TM_OK) return rc;
+    hipLaunchKernelGGL(b_gather_rhs, dim3(nbk(Lt)), dim3(BT), 0, c->stream, (const tm_c128*)a0full.p,
+                       (const c128*)c->t64.p, B.sp_cur, S, R, g.nx, (long long)g.n,
+                       c->maps, Lt, (c128*)B.b.p);
+  }
   std::vector<double> bn, beta;
   if ((rc = b_norms(c, B, (const c128*)B.b.p, nullptr, bn)) != TM_OK) return rc;
   release(a0full);
@@ -986,29 +1022,44 @@ extern "C" int tm_get_batch_config(const tm_ctx* c, int precision, int* prefetch
   return TM_OK;
 }
 
-extern "C" int tm_solve_batched(tm_ctx* c, int n_sub, const tm_subregion* subs, int n_rhs,
-                                const double* khat, const tm_c128* pol, tm_c128* s_out,
-                                const tm_solve_opts* o, tm_solve_info* info, int use_graph) {
+static int batched_entry(tm_ctx* c, int n_sub, const tm_subregion* subs, int n_rhs,
+                         const double* khat, const tm_c128* pol, const tm_c128* a0_packed,
+                         tm_c128* s_out, const tm_solve_opts* o, tm_solve_info* info, int use_graph) {
   if (!c) return TM_ERR_INVALID_ARG;
   hipSetDevice(c->device);
   if (!c->have_geom || !c->have_t) return tmh::set_err(c, TM_ERR_STATE, "geometry and T must be set");
   if (c->t_dense)
     return tmh::set_err(c, TM_ERR_STATE, "the batched solver takes diagonal T (spheres or tm_set_tmatrix_diag)");
-  if (n_sub < 1 || n_rhs < 1 || n_rhs > 8 || !subs || !khat || !pol || !s_out || !o || !info)
+  if (n_sub < 1 || n_rhs < 1 || n_rhs > 8 || !subs || (!a0_packed && (!khat || !pol)) || !s_out || !o ||
+      !info)
     return tmh::set_err(c, TM_ERR_INVALID_ARG, "bad arguments");
   if (!(o->tol > 0.0) || o->restart < 1 || o->restart > 200 || o->max_iter < 1 ||
       (o->precision != TM_PREC_FP64 && o->precision != TM_PREC_MIXED) ||
       (o->precision == TM_PREC_MIXED && !(o->inner_tol > 0.0 && o->inner_tol < 1.0)) || o->use_x0)
     return tmh::set_err(c, TM_ERR_INVALID_ARG, "invalid solver options (x0 not supported in batch)");
   int rc;
-  if ((rc = tmh::validate_incidence(c, n_rhs, khat, pol)) != TM_OK) return rc;
+  if (!a0_packed && (rc = tmh::validate_incidence(c, n_rhs, khat, pol)) != TM_OK) return rc;
   for (int k = 0; k < n_sub; ++k) {
     const tm_subregion& q = subs[k];
     if (q.side_x < 1 || q.side_y < 1 || q.origin_x < 0 || q.origin_y < 0 ||
         q.origin_x + q.side_x > c->g.nx || q.origin_y + q.side_y > c->g.ny)
       return tmh::set_err(c, TM_ERR_INVALID_ARG, "subregion " + std::to_string(k) + " outside the lattice");
   }
-  return tmh::batched_impl(c, n_sub, subs, n_rhs, khat, pol, s_out, *o, info, use_graph);
+  return tmh::batched_impl(c, n_sub, subs, n_rhs, khat, pol, a0_packed, s_out, *o, info, use_graph);
+}
+
+extern "C" int tm_solve_batched(tm_ctx* c, int n_sub, const tm_subregion* subs, int n_rhs,
+                                const double* khat, const tm_c128* pol, tm_c128* s_out,
+                                const tm_solve_opts* o, tm_solve_info* info, int use_graph) {
+  if (!khat || !pol) return tmh::set_err(c, TM_ERR_INVALID_ARG, "bad arguments");
+  return batched_entry(c, n_sub, subs, n_rhs, khat, pol, nullptr, s_out, o, info, use_graph);
+}
+
+extern "C" int tm_solve_batched_a0(tm_ctx* c, int n_sub, const tm_subregion* subs, int n_rhs,
+                                   const tm_c128* a0, tm_c128* s_out, const tm_solve_opts* o,
+                                   tm_solve_info* info, int use_graph) {
+  if (!a0) return tmh::set_err(c, TM_ERR_INVALID_ARG, "bad arguments");
+  return batched_entry(c, n_sub, subs, n_rhs, nullptr, nullptr, a0, s_out, o, info, use_graph);
 }
 
 extern "C" int tm_batch_graph_used(const tm_ctx* c) { return c ? c->last_batch_graphed : 0; }

@@ -103,6 +103,12 @@ struct tm_ctx {
   // translation tables [D][2][S][S]
   tmh::DevBuf tab64, tab32, tabT64, tabT32;
   bool have_tabT = false;
+  // FP64 derivative tables of the position gradient: d/dx, d/dy, and the
+  // transposed operator's d/dx, d/dy (built on first use)
+  tmh::DevBuf dtab[4];
+  bool have_dtab = false;
+  tmh::DevBuf gpos;  // position-gradient workspace (slot-layout vectors)
+  tmh::DevBuf jinc_buf;  // jinc sources, polar nodes and subregion tables
   // T and dT/dr in slot layout [2][N][S]
   tmh::DevBuf t64, t32, dt64;
   tmh::DevBuf tden, ttmp;  // dense T [N][L][L] (boundary order); its scratch vector
@@ -156,6 +162,8 @@ void release(DevBuf& b);
 // tables (tm_table.hip)
 int build_tables(tm_ctx* c);            // forward tables, FP64 + c64
 int build_transposed_tables(tm_ctx* c); // A^T tables
+int build_derivative_tables(tm_ctx* c); // position-gradient tables (FP64)
+void detector_grad_constants(int lmax, std::vector<c128>& coef, std::vector<int>& dm);
 void host_slot_maps(int lmax, Geometry& g, SlotMaps& m);
 
 // basis kernels (tm_basis.hip)
@@ -173,6 +181,21 @@ int launch_mie_one(hipStream_t st, double radius, double k, double nre, double n
                    tm_c128* out);
 int launch_near_field_t(tm_ctx* c, int R, int P, const double* pts, const tm_c128* w, tm_c128* v);
 int launch_grad(tm_ctx* c, int R, const c128* mu_slot, const c128* aexc_slot, double* grad);
+// position gradient (slot-layout inputs; khat host [R][3] or null)
+int launch_gpos_contract(tm_ctx* c, int R, const c128* lam, const c128* s, const c128* a0,
+                         const c128* dxs, const c128* dys, const c128* dxtl, const c128* dytl,
+                         const double* khat, double* grad);
+// detector term of the position gradient (boundary-layout s; xd, w host)
+int launch_gpos_detector(tm_ctx* c, int R, const tm_c128* s, const c128* coef, const int* dm,
+                         const double* xd, const tm_c128* w, double* grad);
+
+// jinc sources (tm_basis.hip): one lattice [R][N][L], or packed subregions
+// with one source group per (subregion, rhs)
+int jinc_beta_count(double k, double rmax);
+int launch_jinc_rhs(tm_ctx* c, int R, const tm_jinc* src, int nb, tm_c128* a0);
+int launch_jinc_rhs_packed(tm_ctx* c, int S, const tm_subregion* subs, int R, int nsrc,
+                           const tm_jinc* src, const int* grp, int nb, tm_c128* a0);
+
 // layout conversions (tm_krylov.hip)
 void pack_slots(hipStream_t st, const Geometry& g, const SlotMaps& m, int R, const tm_c128* in,
                 c128* out);

@@ -173,6 +173,46 @@ static void host_table_constants(const Geometry& g, int Q, std::vector<double>& 
   }
 }
 
+// Coefficients of xi_uv for source truncation lmax and the three N-type l' = 1
+// targets v = (p' = 1, l' = 1, m' = -1, 0, 1) at a general displacement (no
+// Legendre factor folded in): coef[(u * 3 + v) * (lmax + 2) + q] for
+// q = 0..lmax+1, dm[u * 3 + v] = m_u - m'.  Used by the detector term of the
+// position gradient, whose displacement x_d - x_i leaves the lattice plane.
+void detector_grad_constants(int lmax, std::vector<c128>& coef, std::vector<int>& dm) {
+  const int L = 2 * lmax * (lmax + 2), Q = lmax + 2;
+  coef.assign((size_t)L * 3 * Q, c128{0.0, 0.0});
+  dm.assign((size_t)L * 3, 0);
+  for (int u = 0; u < L; ++u) {
+    int p, l, m;
+    plm_of(u, lmax, p, l, m);
+    for (int v = 0; v < 3; ++v) {
+      const int pp = 1, lp = 1, mp = v - 1;
+      dm[u * 3 + v] = m - mp;
+      const double root = std::sqrt((2.0 * l + 1) * (2.0 * lp + 1) / (2.0 * l * (l + 1) * lp * (lp + 1)));
+      const double sgn = ((std::abs(m - mp)) & 1) ? -1.0 : 1.0;
+      for (int q = std::abs(l - lp); q <= l + lp; ++q) {
+        const double w1 = wigner3j(l, lp, q, m, -mp, mp - m);
+        double val;
+        if (p == pp) {
+          const double wa = wigner3j(l, lp, q, 0, 0, 0);
+          val = (l * (l + 1) + lp * (lp + 1) - q * (q + 1)) * std::sqrt(2.0 * q + 1) * w1 * wa;
+        } else {
+          if (q < 1) continue;
+          const double wb = wigner3j(l, lp, q - 1, 0, 0, 0);
+          const double arg =
+              (double)(l + lp + 1 + q) * (l + lp + 1 - q) * (q + l - lp) * (q - l + lp) * (2 * q + 1);
+          if (arg <= 0) continue;
+          val = std::sqrt(arg) * w1 * wb;
+        }
+        val *= root * sgn;
+        double re, im;
+        ipow(std::abs(m - mp) - std::abs(m) - std::abs(mp) + lp - l + q, re, im);
+        coef[((size_t)u * 3 + v) * Q + q] = c128{re * val, im * val};
+      }
+    }
+  }
+}
+
 // Spherical Hankel functions h_0..h_qmax of the first kind by upward
 // recurrence h_{q+1} = (2q+1)/x h_q - h_{q-1} from h_0 = -i e^{ix}/x,
 // h_1 = -e^{ix}(x + i)/x^2 (stable for h: the growing y_q dominates).
@@ -270,6 +310,128 @@ __global__ __launch_bounds__(512) void build_table_kernel(
       tab32[out] = c64{(float)re, (float)im};
     }
   }
+}
+
+// Derivative blocks for the position gradient: D_a(d) = d xi(k d)^T / d d_a
+// for the in-plane directions a = x, y (physical units, 1/length).  In the
+// plane theta = pi/2, so the theta_hat term of the gradient has no x, y
+// component and the z-mirror class structure of the blocks is kept:
+//   D_a[i][j](d) = k e^{i dm phi} sum_q coef_q [ h_q'(kd) rhat_a + i dm h_q(kd)/(kd) phihat_a ],
+// rhat = (cos phi, sin phi), phihat = (-sin phi, cos phi), h_q' = h_{q-1} - (q+1)/x h_q.
+// The transposed variant holds the blocks of the transposed operator:
+// xi(-d) = S xi(d) S gives d xi(-d)/dd = -S (d xi(d)/dd) S, so
+// DT_a[i][j] = -sig_i sig_j D_a[j][i].
+template <int QM>
+__global__ __launch_bounds__(512) void build_dtable_kernel(
+    const double* __restrict__ coef, const int* __restrict__ dm, const int* __restrict__ sig,
+    c128* __restrict__ tab, int tnx, int tny, long long D, int S, double pitch, double k, int axis,
+    int transpose) {
+  const int ent = blockIdx.y * 512 + threadIdx.x;
+  if (ent >= NCLASS * S * S) return;
+  const int c = ent / (S * S);
+  const int i = (ent / S) % S;
+  const int j = ent % S;
+  const int ii = transpose ? j : i, jj = transpose ? i : j;
+  constexpr int Q = QM + 1;
+  const double* cf = coef + ((((size_t)c * S + ii) * S + jj) * Q) * 2;
+  double ar[Q], ai[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    ar[q] = cf[2 * q];
+    ai[q] = cf[2 * q + 1];
+  }
+  const int mu = dm[(c * S + ii) * S + jj];
+  const double sg = transpose ? -(double)(sig[c * S + i] * sig[c * S + j]) : 1.0;
+  const int wx = 2 * tnx - 1;
+  const size_t blk = (size_t)NCLASS * S * S;
+  for (long long d = blockIdx.x; d < D; d += gridDim.x) {
+    const int dx = (int)(d % wx) - (tnx - 1);
+    const int dy = (int)(d / wx) - (tny - 1);
+    double re = 0.0, im = 0.0;
+    if (dx != 0 || dy != 0) {
+      const double X = pitch * dx, Y = pitch * dy;
+      const double rr = sqrt(X * X + Y * Y);
+      const double cph = X / rr, sph = Y / rr;
+      const double x = k * rr;
+      double hr[Q + 1], hi[Q + 1];
+      hankel_up(x, QM + 1, hr, hi);
+      const double ra = axis == 0 ? cph : sph;    // rhat_a
+      const double pa = axis == 0 ? -sph : cph;   // phihat_a
+      double sr = 0.0, si = 0.0;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        // h_q' (x)
+        double dr, di;
+        if (q == 0) {
+          dr = -hr[1];
+          di = -hi[1];
+        } else {
+          dr = hr[q - 1] - (q + 1) / x * hr[q];
+          di = hi[q - 1] - (q + 1) / x * hi[q];
+        }
+        // f_q = h_q' ra + i mu h_q / x pa
+        const double fr = dr * ra - mu * hi[q] / x * pa;
+        const double fi = di * ra + mu * hr[q] / x * pa;
+        sr += ar[q] * fr - ai[q] * fi;
+        si += ar[q] * fi + ai[q] * fr;
+      }
+      double s_, c_;
+      sincos((double)mu * atan2(Y, X), &s_, &c_);
+      re = sg * k * (sr * c_ - si * s_);
+      im = sg * k * (sr * s_ + si * c_);
+    }
+    tab[(size_t)d * blk + (size_t)ent] = c128{re, im};
+  }
+}
+
+// The four FP64 derivative tables (x, y; forward and transposed).
+int build_derivative_tables(tm_ctx* c) {
+  const Geometry& g = c->g;
+  std::vector<double> coef;
+  std::vector<int> dm, sig;
+  const int qmax = 2 * g.lmax;
+  host_table_constants(g, qmax + 1, coef, dm, sig);
+  const long long D = g.n_disp();
+  const size_t blk = (size_t)NCLASS * g.S * g.S;
+  int rc;
+  for (int t = 0; t < 4; ++t)
+    if ((rc = ensure(c, c->dtab[t], (size_t)D * blk * sizeof(c128))) != TM_OK) return rc;
+  double* dcoef = nullptr;
+  int *ddm = nullptr, *dsig = nullptr;
+  TM_HIP(c, hipMalloc((void**)&dcoef, coef.size() * sizeof(double)));
+  TM_HIP(c, hipMalloc((void**)&ddm, dm.size() * sizeof(int)));
+  TM_HIP(c, hipMalloc((void**)&dsig, sig.size() * sizeof(int)));
+  TM_HIP(c, hipMemcpyAsync(dcoef, coef.data(), coef.size() * sizeof(double),
+                           hipMemcpyHostToDevice, c->stream));
+  TM_HIP(c, hipMemcpyAsync(ddm, dm.data(), dm.size() * sizeof(int), hipMemcpyHostToDevice,
+                           c->stream));
+  TM_HIP(c, hipMemcpyAsync(dsig, sig.data(), sig.size() * sizeof(int), hipMemcpyHostToDevice,
+                           c->stream));
+  const unsigned nchunk = (unsigned)((blk + 511) / 512);
+  const unsigned nwg = (unsigned)std::min<long long>(D, std::max(1u, 4096u / nchunk));
+  const dim3 grid(nwg, nchunk);
+  for (int t = 0; t < 4; ++t) {
+    const int axis = t & 1, transpose = t >> 1;
+#define DT_LAUNCH(QM)                                                                        \
+  hipLaunchKernelGGL(build_dtable_kernel<QM>, grid, dim3(512), 0, c->stream, dcoef, ddm, dsig, \
+                     (c128*)c->dtab[t].p, g.tnx, g.tny, D, g.S, g.pitch, g.k, axis, transpose)
+    switch (qmax) {
+      case 2: DT_LAUNCH(2); break;
+      case 4: DT_LAUNCH(4); break;
+      case 6: DT_LAUNCH(6); break;
+      case 8: DT_LAUNCH(8); break;
+      case 10: DT_LAUNCH(10); break;
+      default: DT_LAUNCH(12); break;
+    }
+#undef DT_LAUNCH
+  }
+  TM_HIP(c, hipGetLastError());
+  TM_HIP(c, hipStreamSynchronize(c->stream));
+  TM_HIP(c, hipFree(dcoef));
+  TM_HIP(c, hipFree(ddm));
+  TM_HIP(c, hipFree(dsig));
+  c->have_dtab = true;
+  return TM_OK;
 }
 
 static int build_impl(tm_ctx* c, DevBuf& t64, DevBuf& t32, int transpose) {

@@ -45,6 +45,21 @@ class SolveInfo(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class Jinc(ctypes.Structure):
+    _fields_ = [("x0", ctypes.c_double), ("y0", ctypes.c_double), ("z0", ctypes.c_double),
+                ("axr", ctypes.c_double), ("axi", ctypes.c_double), ("ayr", ctypes.c_double),
+                ("ayi", ctypes.c_double)]
+
+
+def _jinc_array(sources):
+    """[(x0, y0, z0, ax, ay)] -> a ctypes array of tm_jinc."""
+    arr = (Jinc * max(1, len(sources)))()
+    for j, (x0, y0, z0, ax, ay) in enumerate(sources):
+        ax, ay = complex(ax), complex(ay)
+        arr[j] = Jinc(float(x0), float(y0), float(z0), ax.real, ax.imag, ay.real, ay.imag)
+    return arr
+
+
 class Subregion(ctypes.Structure):
     _fields_ = [("origin_x", ctypes.c_int), ("origin_y", ctypes.c_int), ("side_x", ctypes.c_int),
                 ("side_y", ctypes.c_int)]
@@ -97,6 +112,10 @@ def load():
         "tm_adjoint_solve": (I, [P, I, P, P, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo)]),
         "tm_apply_operator": (I, [P, I, P, P, I, I]),
         "tm_apply_operator_noalloc": (I, [P, I, P, P, I, I]),
+        "tm_grad_position": (I, [P, I, P, P, P, P, P, P, P]),
+        "tm_jinc_rhs": (I, [P, I, P, I, P]),
+        "tm_jinc_rhs_batched": (I, [P, I, P, I, I, P, P, I, P]),
+        "tm_solve_batched_a0": (I, [P, I, P, I, P, P, P, P, I]),
         "tm_near_field": (I, [P, I, P, I, P, P, I]),
         "tm_near_field_adjoint": (I, [P, I, I, P, P, P]),
         "tm_mie": (I, [I, D, D, D, D, P, P]),
@@ -348,6 +367,59 @@ class Context:
         info = [[infos[k * R + r].as_dict() for r in range(R)] for k in range(S)]
         return res, info
 
+    def jinc_rhs(self, sources, n_beta=0):
+        """tm_jinc_rhs: [R, N, L] incident coefficients of jinc sources
+        [(x0, y0, z0, ax, ay)] (App. II)."""
+        R = len(sources)
+        if R < 1:
+            raise ValueError("need at least one source")
+        a0 = torch.empty(R, self.n, self.L, dtype=torch.complex128, device=self.device)
+        self._check(self.lib.tm_jinc_rhs(self.h, R, _jinc_array(sources), int(n_beta), _ptr(a0)))
+        return a0
+
+    def jinc_rhs_batched(self, subs, groups, n_beta=0):
+        """tm_jinc_rhs_batched: groups[k][r] is the list of jinc sources
+        exciting system (subregion k, rhs r); returns the packed coefficients
+        (flat, the layout tm_solve_batched_a0 takes)."""
+        S = len(subs)
+        R = len(groups[0])
+        if len(groups) != S or any(len(g) != R for g in groups):
+            raise ValueError("groups must be [n_sub][n_rhs] lists of sources")
+        flat, off = [], [0]
+        for k in range(S):
+            for r in range(R):
+                flat.extend(groups[k][r])
+                off.append(len(flat))
+        arr = (Subregion * S)(*[Subregion(*map(int, q)) for q in subs])
+        grp = np.ascontiguousarray(off, dtype=np.int32)
+        n = sum(R * q[2] * q[3] * self.L for q in subs)
+        a0 = torch.empty(n, dtype=torch.complex128, device=self.device)
+        self._check(self.lib.tm_jinc_rhs_batched(self.h, S, arr, R, len(flat), _jinc_array(flat),
+                                                 grp.ctypes.data_as(ctypes.c_void_p), int(n_beta),
+                                                 _ptr(a0)))
+        return a0
+
+    def solve_batched_a0(self, subs, a0, n_rhs, use_graph=True, **kw):
+        """tm_solve_batched_a0: a0 flat packed [sum_k R N_k L]; returns
+        ([s_k [R, N_k, L]], infos [S][R])."""
+        S = len(subs)
+        R = int(n_rhs)
+        sizes = [R * q[2] * q[3] * self.L for q in subs]
+        (a0,) = _devs(self.device, (a0, torch.complex128, "a0", (sum(sizes),), None))
+        arr = (Subregion * S)(*[Subregion(*map(int, q)) for q in subs])
+        out = torch.empty(sum(sizes), dtype=torch.complex128, device=self.device)
+        o = self.make_opts(**kw)
+        infos = (SolveInfo * (S * R))()
+        self._check(self.lib.tm_solve_batched_a0(self.h, S, arr, R, _ptr(a0), _ptr(out), ctypes.byref(o),
+                                                 infos, int(bool(use_graph))),
+                    allow=(TM_OK, TM_NOT_CONVERGED))
+        res, off = [], 0
+        for q, n in zip(subs, sizes):
+            res.append(out[off:off + n].view(R, q[2] * q[3], self.L))
+            off += n
+        info = [[infos[k * R + r].as_dict() for r in range(R)] for k in range(S)]
+        return res, info
+
     def batch_graph_used(self):
         return bool(self.lib.tm_batch_graph_used(self.h))
 
@@ -431,6 +503,37 @@ class Context:
         return g
 
     # ---- matvec configuration / autotuner
+    def grad_position(self, mu, s, a0=None, khat=None, xd=None, w=None):
+        """tm_grad_position: [R, N, 2] in-plane position gradient.  khat (host
+        [R, 3]) adds the plane-wave incident term (a0 required); xd (host [3])
+        with w (host [R, 3]) adds the point-detector term."""
+        mu, s = _devs(self.device, (mu, torch.complex128, "mu", (self.n, self.L), 1),
+                      (s, torch.complex128, "s", (self.n, self.L), 1))
+        R = _nrhs(mu, 2)
+        if _nrhs(s, 2) != R:
+            raise ValueError("mu and s must have the same number of right-hand sides")
+        kh = a0p = None
+        if khat is not None:
+            if a0 is None:
+                raise ValueError("khat needs a0")
+            (a0,) = _devs(self.device, (a0, torch.complex128, "a0", (self.n, self.L), 1))
+            if _nrhs(a0, 2) != R:
+                raise ValueError("a0 must have the same number of right-hand sides as mu")
+            kh = _host(np.atleast_2d(khat), np.float64, "khat", (R, 3))
+            a0p = _ptr(a0)
+        xdp = wp = None
+        if (xd is None) != (w is None):
+            raise ValueError("xd and w go together")
+        if xd is not None:
+            xdh = _host(xd, np.float64, "xd", (3,))
+            wh = _host(np.atleast_2d(w), np.complex128, "w", (R, 3))
+            xdp, wp = xdh.ctypes.data_as(ctypes.c_void_p), wh.ctypes.data_as(ctypes.c_void_p)
+        g = torch.empty(R, self.n, 2, dtype=torch.float64, device=self.device)
+        self._check(self.lib.tm_grad_position(
+            self.h, R, _ptr(mu), _ptr(s), a0p, None if kh is None else kh.ctypes.data_as(ctypes.c_void_p),
+            xdp, wp, _ptr(g)))
+        return g
+
     def set_matvec_config(self, precision, variant, items=0):
         self._check(self.lib.tm_set_matvec_config(self.h, PRECISIONS[precision], int(variant), int(items)))
 
