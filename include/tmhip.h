@@ -35,9 +35,12 @@
  *     return a tm_status.  tm_last_error gives a message for the last failing
  *     call on a context.
  *
- * Scope: scatterers on a rectangular lattice in the z = 0 plane (the
- * metasurface setting of the paper), which lets the library tabulate one
- * translation block per lattice displacement.  lmax 1..6 (App. I.B's
+ * Scope: scatterers in the z = 0 plane (the metasurface setting of the
+ * paper).  On a rectangular lattice the library tabulates one translation
+ * block per lattice displacement; elsewhere in the plane it forms the blocks
+ * on the fly per pair (the lattice-only calls -- batched subregions, position
+ * gradients, the allocation-free operator, the autotuner -- then return
+ * TM_ERR_NOT_LATTICE).  lmax 1..6 (App. I.B's
  * truncation; the paper's cylinders use lmax 6).
  */
 #ifndef TMHIP_H
@@ -58,7 +61,7 @@ typedef enum {
   TM_NOT_CONVERGED = 1,     /* result written, residual above tolerance */
   TM_ERR_INVALID_ARG = -1,  /* null pointer, size or range out of bounds   */
   TM_ERR_OVERLAP = -2,      /* enclosing spheres intersect (App. I.C)      */
-  TM_ERR_NOT_LATTICE = -3,  /* positions are not a z = 0 rectangular grid  */
+  TM_ERR_NOT_LATTICE = -3,  /* off the z = 0 plane, or a lattice-only call  */
   TM_ERR_OOM = -4,          /* device allocation failed                    */
   TM_ERR_HIP = -5,          /* a HIP runtime call failed                   */
   TM_ERR_NAN = -6,          /* non-finite input                            */
@@ -83,14 +86,17 @@ int tm_abi_version(void);
 
 /* ---- problem set-up ------------------------------------------------------ */
 
-/* Scatterer centres and host wavenumber.  pos: host, [n][3] (x, y, z).  The
- * centres must form an nx-by-ny grid with equal pitch in x and y, z = 0,
- * ordered index = iy*nx + ix (TM_ERR_NOT_LATTICE otherwise).  Builds the
- * translation tables (one block per lattice displacement, App. I.C, eq.
- * "tran_coeff") on the device in FP64 and complex64.  Invalidates T. */
+/* Scatterer centres and host wavenumber.  pos: host, [n][3] (x, y, z), every
+ * z = 0 (TM_ERR_NOT_LATTICE otherwise), no two centres equal (TM_ERR_OVERLAP).
+ * When the centres form an nx-by-ny grid of equal pitch in x and y ordered
+ * index = iy*nx + ix, builds the translation tables (one block per lattice
+ * displacement, App. I.C, eq. "tran_coeff") on the device in FP64 and
+ * complex64; otherwise keeps the centres and the per-entry constants of
+ * eq. "tran_coeff" for the on-the-fly block matvec.  Invalidates T. */
 int tm_set_geometry(tm_ctx* ctx, int n, const double* pos, double k, int lmax);
 
-/* Lattice dimensions of the current geometry (host outputs). */
+/* Lattice dimensions of the current geometry (host outputs); an off-lattice
+ * geometry reports nx = n, ny = 1, pitch = 0. */
 int tm_get_lattice(const tm_ctx* ctx, int* nx, int* ny, double* pitch);
 
 /* General per-scatterer T-matrices (App. I.B, eq. "def_tmatrix": s_i =
@@ -121,6 +127,27 @@ int tm_mie(int lmax, double k, double radius, double n_re, double n_im, tm_c128*
  * relative refractive index n_re + i n_im (n_im >= 0).  Computes the
  * diagonal T and dT/dr on the device. */
 int tm_set_spheres(tm_ctx* ctx, const double* radii, double n_re, double n_im);
+
+/* Null-field (EBCM) T-matrices of dielectric cylinders, the paper's
+ * meta-atoms (App. I.B, eq. "def_tmatrix" with the surface-integral matrices
+ * P, Q): scatterer i is a cylinder of radius radii[i] (device, [N]) and the
+ * given height, axis along z, centred on its site, relative index
+ * n_re + i n_im (n_im >= 0).  For each azimuthal order m the surface
+ * integrals over the caps and the side (n_quad Gauss-Legendre nodes per face,
+ * 0 = 96) give the outgoing- and regular-test matrices O_m, R_m and
+ * T_m = -R_m O_m^{-1}; the T of every scatterer is computed on the device and
+ * set as a dense T (as tm_set_tmatrix_dense).  The enclosing spheres
+ * (radius sqrt(r^2 + h^2/4)) must not intersect (TM_ERR_OVERLAP), and
+ * k r_enclosing |n| <= 12.  The null-field method converges slowly in lmax
+ * for bodies with edges; lmax 6 is the paper's choice. */
+int tm_set_cylinders(tm_ctx* ctx, const double* radii, double height, double n_re, double n_im,
+                     int n_quad);
+
+/* The T-matrix of one cylinder as tm_set_cylinders computes it, no context
+ * needed: T_out host [L][L] in the coefficient order above.  Synchronous;
+ * allocates and frees small device buffers on the current device. */
+int tm_ebcm_cylinder(int lmax, double k, double radius, double height, double n_re, double n_im,
+                     int n_quad, tm_c128* T_out);
 
 /* Arbitrary diagonal T-matrices: t: device, [N][L] (entry n of T_i's
  * diagonal).  Clears dT/dr (tm_grad_radius then returns TM_ERR_STATE). */

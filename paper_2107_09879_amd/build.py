@@ -14,7 +14,7 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtmhip.so")
 ROOT = os.path.dirname(HERE)
 
-SOURCES = ["tm_api.hip", "tm_table.hip", "tm_matvec.hip", "tm_matvec_lds.hip", "tm_batched.hip", "tm_krylov.hip", "tm_basis.hip", "tm_noalloc.hip"]
+SOURCES = ["tm_api.hip", "tm_table.hip", "tm_matvec.hip", "tm_matvec_lds.hip", "tm_batched.hip", "tm_krylov.hip", "tm_basis.hip", "tm_noalloc.hip", "tm_offlattice.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

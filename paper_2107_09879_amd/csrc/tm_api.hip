@@ -340,6 +340,27 @@ void tm_destroy(tm_ctx* c) {
     hipSetDevice((c)->device);        \
   } while (0)
 
+// Lattice detection: row-major nx x ny grid of equal pitch in z = 0.
+static bool detect_lattice(int n, const double* pos, int& nx, int& ny, double& pitch) {
+  const double x0 = pos[0], y0 = pos[1];
+  nx = 1;
+  while (nx < n && pos[3 * nx + 1] == y0) ++nx;
+  if (n % nx != 0) return false;
+  ny = n / nx;
+  pitch = 1.0;
+  if (nx > 1) pitch = pos[3] - pos[0];
+  else if (ny > 1) pitch = pos[3 * nx + 1] - pos[1];
+  if (!(pitch > 0.0)) return false;
+  const double tolp = 1e-9 * pitch;
+  for (int i = 0; i < n; ++i) {
+    const int ix = i % nx, iy = i / nx;
+    if (std::fabs(pos[3 * i] - (x0 + ix * pitch)) > tolp ||
+        std::fabs(pos[3 * i + 1] - (y0 + iy * pitch)) > tolp || std::fabs(pos[3 * i + 2]) > tolp)
+      return false;
+  }
+  return true;
+}
+
 int tm_set_geometry(tm_ctx* c, int n, const double* pos, double k, int lmax) {
   CHECK_CTX(c);
   if (n < 1 || !pos) return tmh::set_err(c, TM_ERR_INVALID_ARG, "need n >= 1 positions");
@@ -348,41 +369,61 @@ int tm_set_geometry(tm_ctx* c, int n, const double* pos, double k, int lmax) {
   if (!(k > 0.0) || !std::isfinite(k)) return tmh::set_err(c, TM_ERR_INVALID_ARG, "k must be > 0");
   for (int i = 0; i < 3 * n; ++i)
     if (!std::isfinite(pos[i])) return tmh::set_err(c, TM_ERR_NAN, "non-finite position");
-  // lattice detection: row-major nx x ny grid, equal pitch, z = 0
-  const double x0 = pos[0], y0 = pos[1];
-  int nx = 1;
-  while (nx < n && pos[3 * nx + 1] == y0) ++nx;
-  if (n % nx != 0) return tmh::set_err(c, TM_ERR_NOT_LATTICE, "row length does not divide n");
-  const int ny = n / nx;
-  double pitch = 1.0;
-  if (nx > 1) pitch = pos[3] - pos[0];
-  else if (ny > 1) pitch = pos[3 * nx + 1] - pos[1];
-  if (!(pitch > 0.0)) return tmh::set_err(c, TM_ERR_NOT_LATTICE, "non-positive pitch");
-  const double tolp = 1e-9 * pitch;
-  for (int i = 0; i < n; ++i) {
-    const int ix = i % nx, iy = i / nx;
-    if (std::fabs(pos[3 * i] - (x0 + ix * pitch)) > tolp ||
-        std::fabs(pos[3 * i + 1] - (y0 + iy * pitch)) > tolp || std::fabs(pos[3 * i + 2]) > tolp)
-      return tmh::set_err(c, TM_ERR_NOT_LATTICE,
-                         "site " + std::to_string(i) + " is off the z=0 lattice");
+  int nx = 0, ny = 0;
+  double pitch = 0.0;
+  const bool lattice = detect_lattice(n, pos, nx, ny, pitch);
+  if (!lattice) {
+    // arbitrary centres in the plane z = 0 (the z-mirror class split holds)
+    double scale = 0.0;
+    for (int i = 0; i < n; ++i) scale = std::max(scale, std::hypot(pos[3 * i], pos[3 * i + 1]));
+    const double tolz = 1e-9 * std::max(scale, 1.0 / k);
+    for (int i = 0; i < n; ++i)
+      if (std::fabs(pos[3 * i + 2]) > tolz)
+        return tmh::set_err(c, TM_ERR_NOT_LATTICE,
+                            "scatterer " + std::to_string(i) + " is off the z = 0 plane");
   }
   tmh::Geometry& g = c->g;
   g = tmh::Geometry{};
   g.n = n;
-  g.nx = nx;
-  g.ny = ny;
+  g.lattice = lattice;
+  g.nx = lattice ? nx : n;
+  g.ny = lattice ? ny : 1;
   g.lmax = lmax;
-  g.pitch = pitch;
+  g.pitch = lattice ? pitch : 0.0;
   g.k = k;
-  g.x0 = x0;
-  g.y0 = y0;
-  g.tnx = nx;
-  g.tny = ny;
+  g.x0 = pos[0];
+  g.y0 = pos[1];
+  g.tnx = g.nx;
+  g.tny = g.ny;
   tmh::host_slot_maps(lmax, g, c->maps);
   c->have_geom = c->have_t = c->have_dt = c->have_tabT = c->have_dtab = c->t_dense = false;
   c->plan_R[0] = c->plan_R[1] = -1;
   int rc;
-  if ((rc = tmh::build_tables(c)) != TM_OK) return rc;
+  if (lattice) {
+    if ((rc = tmh::build_tables(c)) != TM_OK) return rc;
+    c->host_xy.clear();
+  } else {
+    // no displacement tables: release a previous lattice's
+    for (tmh::DevBuf* b : {&c->tab64, &c->tab32, &c->tabT64, &c->tabT32})
+      if (b->p) {
+        TM_HIP(c, hipStreamSynchronize(c->stream));
+        tmh::release(*b);
+      }
+    c->host_xy.assign((size_t)2 * n, 0.0);
+    for (int i = 0; i < n; ++i) {
+      c->host_xy[2 * i] = pos[3 * i];
+      c->host_xy[2 * i + 1] = pos[3 * i + 1];
+    }
+    // coincident centres leave a block undefined
+    std::vector<std::pair<double, double>> sorted(n);
+    for (int i = 0; i < n; ++i) sorted[i] = {pos[3 * i], pos[3 * i + 1]};
+    std::sort(sorted.begin(), sorted.end());
+    for (int i = 1; i < n; ++i)
+      if (sorted[i] == sorted[i - 1]) return tmh::set_err(c, TM_ERR_OVERLAP, "two scatterers share a centre");
+    if ((rc = tmh::ensure(c, c->xy, (size_t)2 * n * sizeof(double))) != TM_OK) return rc;
+    TM_HIP(c, hipMemcpy(c->xy.p, c->host_xy.data(), (size_t)2 * n * sizeof(double), hipMemcpyHostToDevice));
+    if ((rc = tmh::build_offlattice_constants(c)) != TM_OK) return rc;
+  }
   const size_t vb = (size_t)g.vec_len();
   if ((rc = tmh::ensure(c, c->t64, vb * sizeof(c128))) != TM_OK) return rc;
   if ((rc = tmh::ensure(c, c->t32, vb * sizeof(tmh::c64))) != TM_OK) return rc;
@@ -425,6 +466,64 @@ int tm_mie(int lmax, double k, double radius, double n_re, double n_im, tm_c128*
   return TM_OK;
 }
 
+namespace {
+// Enclosing spheres of radii `re` must not intersect (App. I.C): on a
+// lattice every pair closer than twice the largest radius is visited by
+// displacement; off a lattice, by a cell grid of that size.
+int check_enclosing(tm_ctx* c, const std::vector<double>& re, const char* what) {
+  const tmh::Geometry& g = c->g;
+  double rmax = 0.0;
+  for (double v : re) rmax = std::max(rmax, v);
+  auto fail = [&](int i, int j) {
+    return tmh::set_err(c, TM_ERR_OVERLAP, std::string(what) + " " + std::to_string(i) + " and " +
+                                              std::to_string(j) + " overlap");
+  };
+  if (g.lattice) {
+    const int reach = (int)std::floor(2.0 * rmax / g.pitch);
+    for (int dy = 0; dy <= reach; ++dy)
+      for (int dx = (dy == 0 ? 1 : -reach); dx <= reach; ++dx) {
+        const double dist = g.pitch * std::hypot((double)dx, (double)dy);
+        if (dist > 2.0 * rmax) continue;
+        for (int iy = 0; iy + dy < g.ny; ++iy)
+          for (int ix = std::max(0, -dx); ix < g.nx && ix + dx < g.nx; ++ix) {
+            const int i = iy * g.nx + ix, j = (iy + dy) * g.nx + ix + dx;
+            if (re[i] + re[j] >= dist) return fail(i, j);
+          }
+      }
+    return TM_OK;
+  }
+  const std::vector<double>& xy = c->host_xy;
+  const double cell = std::max(2.0 * rmax, 1e-300);
+  double xmin = xy[0], ymin = xy[1];
+  for (int i = 0; i < g.n; ++i) {
+    xmin = std::min(xmin, xy[2 * i]);
+    ymin = std::min(ymin, xy[2 * i + 1]);
+  }
+  std::vector<std::pair<long long, int>> key(g.n);
+  auto cx_of = [&](int i) { return (long long)std::floor((xy[2 * i] - xmin) / cell); };
+  auto cy_of = [&](int i) { return (long long)std::floor((xy[2 * i + 1] - ymin) / cell); };
+  const long long W = 1 << 30;
+  for (int i = 0; i < g.n; ++i) key[i] = {cy_of(i) * W + cx_of(i), i};
+  std::sort(key.begin(), key.end());
+  for (int a = 0; a < g.n; ++a) {
+    const int i = key[a].second;
+    const long long cxi = cx_of(i), cyi = cy_of(i);
+    for (long long dyc = -1; dyc <= 1; ++dyc)
+      for (long long dxc = -1; dxc <= 1; ++dxc) {
+        const long long kk = (cyi + dyc) * W + (cxi + dxc);
+        auto it = std::lower_bound(key.begin(), key.end(), std::make_pair(kk, -1));
+        for (; it != key.end() && it->first == kk; ++it) {
+          const int j = it->second;
+          if (j <= i) continue;
+          const double d = std::hypot(xy[2 * i] - xy[2 * j], xy[2 * i + 1] - xy[2 * j + 1]);
+          if (re[i] + re[j] >= d) return fail(std::min(i, j), std::max(i, j));
+        }
+      }
+  }
+  return TM_OK;
+}
+}  // namespace
+
 int tm_set_spheres(tm_ctx* c, const double* radii, double n_re, double n_im) {
   CHECK_CTX(c);
   if (!c->have_geom) return tmh::set_err(c, TM_ERR_STATE, "set geometry first");
@@ -442,28 +541,80 @@ int tm_set_spheres(tm_ctx* c, const double* radii, double n_re, double n_im) {
     if (g.k * r[i] * std::max(1.0, nabs) > 12.0)
       return tmh::set_err(c, TM_ERR_INVALID_ARG, "k r |n| > 12 is outside the supported range");
   }
-  // non-intersecting spheres (App. I.C): every pair closer than twice the
-  // largest radius is checked, diagonal and farther neighbours included
-  double rmax = 0.0;
-  for (int i = 0; i < g.n; ++i) rmax = std::max(rmax, r[i]);
-  const int reach = (int)std::floor(2.0 * rmax / g.pitch);
-  for (int dy = 0; dy <= reach; ++dy)
-    for (int dx = (dy == 0 ? 1 : -reach); dx <= reach; ++dx) {
-      const double dist = g.pitch * std::hypot((double)dx, (double)dy);
-      if (dist > 2.0 * rmax) continue;
-      for (int iy = 0; iy + dy < g.ny; ++iy)
-        for (int ix = std::max(0, -dx); ix < g.nx && ix + dx < g.nx; ++ix) {
-          const int i = iy * g.nx + ix, j = (iy + dy) * g.nx + ix + dx;
-          if (r[i] + r[j] >= dist)
-            return tmh::set_err(c, TM_ERR_OVERLAP, "spheres " + std::to_string(i) + " and " +
-                                                      std::to_string(j) + " overlap");
-        }
-    }
-  int rc = tmh::launch_mie(c, radii, n_re, n_im);
+  // non-intersecting spheres (App. I.C), diagonal and farther neighbours included
+  int rc = check_enclosing(c, r, "spheres");
+  if (rc != TM_OK) return rc;
+  rc = tmh::launch_mie(c, radii, n_re, n_im);
   if (rc != TM_OK) return rc;
   c->have_t = c->have_dt = true;
   c->t_dense = false;
   return TM_OK;
+}
+
+int tm_set_cylinders(tm_ctx* c, const double* radii, double height, double n_re, double n_im,
+                     int n_quad) {
+  CHECK_CTX(c);
+  if (!c->have_geom) return tmh::set_err(c, TM_ERR_STATE, "set geometry first");
+  if (!radii) return tmh::set_err(c, TM_ERR_INVALID_ARG, "null radii");
+  if (!std::isfinite(n_re) || !std::isfinite(n_im) || n_im < 0.0 || !(height > 0.0) ||
+      !std::isfinite(height) || n_quad < 0 || n_quad > 1024 || (n_quad > 0 && n_quad < 4))
+    return tmh::set_err(c, TM_ERR_INVALID_ARG, "invalid cylinder parameters");
+  const tmh::Geometry& g = c->g;
+  std::vector<double> r(g.n), re(g.n);
+  TM_HIP(c, hipMemcpyAsync(r.data(), radii, g.n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  TM_HIP(c, hipStreamSynchronize(c->stream));
+  const double nabs = std::hypot(n_re, n_im);
+  for (int i = 0; i < g.n; ++i) {
+    if (!std::isfinite(r[i])) return tmh::set_err(c, TM_ERR_NAN, "non-finite radius");
+    if (!(r[i] > 0.0)) return tmh::set_err(c, TM_ERR_INVALID_ARG, "radius must be > 0");
+    re[i] = std::hypot(r[i], 0.5 * height);
+    if (g.k * re[i] * std::max(1.0, nabs) > 12.0)
+      return tmh::set_err(c, TM_ERR_INVALID_ARG, "k r_enclosing |n| > 12 is outside the supported range");
+  }
+  int rc;
+  if ((rc = check_enclosing(c, re, "the enclosing spheres of cylinders")) != TM_OK) return rc;
+  const size_t bytes = (size_t)g.n * g.L * g.L * sizeof(tm_c128);
+  if ((rc = tmh::ensure(c, c->tden, bytes)) != TM_OK) return rc;
+  if ((rc = tmh::launch_ebcm_cylinders(c, c->stream, g.n, radii, height, g.k, n_re, n_im, g.lmax,
+                                       n_quad > 0 ? n_quad : 96, (tm_c128*)c->tden.p)) != TM_OK)
+    return rc;
+  c->have_t = true;
+  c->have_dt = false;
+  c->t_dense = true;
+  return TM_OK;
+}
+
+int tm_ebcm_cylinder(int lmax, double k, double radius, double height, double n_re, double n_im,
+                     int n_quad, tm_c128* T_out) {
+  if (lmax < 1 || lmax > tmh::LMAX_SUPPORTED || !T_out || n_quad < 0 || n_quad > 1024 ||
+      (n_quad > 0 && n_quad < 4))
+    return TM_ERR_INVALID_ARG;
+  if (!std::isfinite(k) || !std::isfinite(radius) || !std::isfinite(height) || !std::isfinite(n_re) ||
+      !std::isfinite(n_im))
+    return TM_ERR_NAN;
+  if (!(k > 0.0) || !(radius > 0.0) || !(height > 0.0) || n_im < 0.0 ||
+      k * std::hypot(radius, 0.5 * height) * std::max(1.0, std::hypot(n_re, n_im)) > 12.0)
+    return TM_ERR_INVALID_ARG;
+  const int L = 2 * lmax * (lmax + 2);
+  double* dr = nullptr;
+  tm_c128* dT = nullptr;
+  if (hipMalloc((void**)&dr, sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&dT, (size_t)L * L * sizeof(tm_c128)) != hipSuccess) {
+    (void)hipGetLastError();
+    if (dr) hipFree(dr);
+    return TM_ERR_OOM;
+  }
+  int rc = TM_OK;
+  if (hipMemcpy(dr, &radius, sizeof(double), hipMemcpyHostToDevice) != hipSuccess) rc = TM_ERR_HIP;
+  if (rc == TM_OK)
+    rc = tmh::launch_ebcm_cylinders(nullptr, nullptr, 1, dr, height, k, n_re, n_im, lmax,
+                                    n_quad > 0 ? n_quad : 96, dT);
+  if (rc == TM_OK &&
+      hipMemcpy(T_out, dT, (size_t)L * L * sizeof(tm_c128), hipMemcpyDeviceToHost) != hipSuccess)
+    rc = TM_ERR_HIP;
+  hipFree(dr);
+  hipFree(dT);
+  return rc;
 }
 
 int tm_set_tmatrix_diag(tm_ctx* c, const tm_c128* t) {
@@ -620,7 +771,18 @@ int tm_jinc_rhs(tm_ctx* c, int R, const tm_jinc* src, int n_beta, tm_c128* a0) {
   int rc;
   if ((rc = check_jinc(c, R, src)) != TM_OK) return rc;
   const tmh::Geometry& g = c->g;
-  const int nb = n_beta > 0 ? n_beta : jinc_nodes(g, R, src, 0, 0, g.nx, g.ny);
+  int nb = n_beta;
+  if (nb == 0 && g.lattice) {
+    nb = jinc_nodes(g, R, src, 0, 0, g.nx, g.ny);
+  } else if (nb == 0) {
+    double rmax = 0.0;
+    for (int j = 0; j < R; ++j)
+      for (int i = 0; i < g.n; ++i)
+        rmax = std::max(rmax, std::sqrt(std::pow(c->host_xy[2 * i] - src[j].x0, 2) +
+                                        std::pow(c->host_xy[2 * i + 1] - src[j].y0, 2) +
+                                        src[j].z0 * src[j].z0));
+    nb = tmh::jinc_beta_count(g.k, rmax);
+  }
   return tmh::launch_jinc_rhs(c, R, src, nb, a0);
 }
 
@@ -628,6 +790,7 @@ int tm_jinc_rhs_batched(tm_ctx* c, int n_sub, const tm_subregion* subs, int R, i
                         const tm_jinc* src, const int* groups, int n_beta, tm_c128* a0) {
   CHECK_CTX(c);
   if (!c->have_geom) return tmh::set_err(c, TM_ERR_STATE, "set geometry first");
+  if (!c->g.lattice) return tmh::set_err(c, TM_ERR_NOT_LATTICE, "subregions need a lattice geometry");
   if (n_sub < 1 || R < 1 || n_src < 0 || !subs || !groups || !a0 || (n_src > 0 && !src) || n_beta < 0 ||
       n_beta > 100000)
     return tmh::set_err(c, TM_ERR_INVALID_ARG, "bad arguments");
@@ -662,6 +825,8 @@ int tm_grad_position(tm_ctx* c, int R, const tm_c128* mu, const tm_c128* s, cons
                      const double* khat, const double* xd, const tm_c128* w, double* grad) {
   CHECK_CTX(c);
   if (!c->have_geom || !c->have_t) return tmh::set_err(c, TM_ERR_STATE, "geometry and T must be set");
+  if (!c->g.lattice)
+    return tmh::set_err(c, TM_ERR_NOT_LATTICE, "position gradients use the lattice's derivative tables");
   if (R < 1 || !mu || !s || !grad || (khat && !a0) || (!xd) != (!w))
     return tmh::set_err(c, TM_ERR_INVALID_ARG, "bad arguments");
   if (khat)
@@ -807,6 +972,7 @@ int tm_autotune(tm_ctx* c, int n_rhs, int precision, double* best_ms) {
   if (!c->have_geom) return tmh::set_err(c, TM_ERR_STATE, "set geometry first");
   if (n_rhs < 1 || (precision != TM_PREC_FP64 && precision != TM_PREC_MIXED))
     return tmh::set_err(c, TM_ERR_INVALID_ARG, "bad arguments");
+  if (!c->g.lattice) return tmh::set_err(c, TM_ERR_NOT_LATTICE, "the tuned kernels are the lattice's");
   return tmh::autotune(c, n_rhs, precision, best_ms);
 }
 

@@ -268,8 +268,8 @@ struct PwArgs {
   double pol[6 * 8];  // re, im interleaved per component
 };
 
-__global__ void plane_wave_kernel(PwArgs pw, int R, int N, int L, int lmax, int nx, double x0,
-                                  double y0, double pitch, double k, tm_c128* __restrict__ a0) {
+__global__ void plane_wave_kernel(PwArgs pw, int R, int N, int L, int lmax, SitePos sp, double k,
+                                  tm_c128* __restrict__ a0) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (long long)R * N * L) return;
   const int n = (int)(e % L);
@@ -303,10 +303,11 @@ __global__ void plane_wave_kernel(PwArgs pw, int R, int N, int L, int lmax, int 
     v = pre * ipow<double>(l) * (mul_i(pi * bA) + tau * aA);
   else
     v = pre * ipow<double>(l + 1) * (tau * bA - mul_i(pi * aA));
-  const double xi = x0 + pitch * (double)(i % nx), yi = y0 + pitch * (double)(i / nx);
-  double sp, cp;
-  sincos(k * (kh[0] * xi + kh[1] * yi), &sp, &cp);
-  v = cx<double>(cp, sp) * v;
+  double xi, yi;
+  sp.at(i, xi, yi);
+  double sph, cph;
+  sincos(k * (kh[0] * xi + kh[1] * yi), &sph, &cph);
+  v = cx<double>(cph, sph) * v;
   a0[e] = tm_c128{v.re, v.im};
 }
 
@@ -338,7 +339,7 @@ constexpr int NF_MAXR = 4;
 // (k r reduced modulo 2 pi before the FP32 sine/cosine).
 template <typename T, int LMAX, int R>
 __global__ __launch_bounds__(256) void near_field_v2(
-    const tm_c128* __restrict__ s, int N, int nx, double x0, double y0, double pitch, double k,
+    const tm_c128* __restrict__ s, int N, SitePos sp, double k,
     const double* __restrict__ pts, int P, tm_c128* __restrict__ E) {
   constexpr int L = 2 * LMAX * (LMAX + 2), H = LMAX * (LMAX + 2);
   // spheres staged per LDS chunk: at most 48 KB of coefficients
@@ -371,8 +372,10 @@ __global__ __launch_bounds__(256) void near_field_v2(
     __syncthreads();
     for (int ii = 0; ii < nch; ++ii) {
       const int i = i0 + ii;
-      const double dx = px - (x0 + pitch * (double)(i % nx));
-      const double dy = py - (y0 + pitch * (double)(i / nx));
+      double sx_, sy_;
+      sp.at(i, sx_, sy_);
+      const double dx = px - sx_;
+      const double dy = py - sy_;
       const double dz = pz;
       const double rho2 = dx * dx + dy * dy;
       const double r2 = rho2 + dz * dz;
@@ -488,27 +491,26 @@ __global__ __launch_bounds__(256) void near_field_v2(
 }
 
 template <typename T, int LMAX>
-static void nf_dispatch_r(int R, dim3 g, hipStream_t st, const tm_c128* s, int N, int nx, double x0,
-                          double y0, double pitch, double k, const double* pts, int P, tm_c128* E) {
+static void nf_dispatch_r(int R, dim3 g, hipStream_t st, const tm_c128* s, int N, SitePos sp, double k,
+                          const double* pts, int P, tm_c128* E) {
   switch (R) {
-    case 1: hipLaunchKernelGGL((near_field_v2<T, LMAX, 1>), g, dim3(256), 0, st, s, N, nx, x0, y0, pitch, k, pts, P, E); break;
-    case 2: hipLaunchKernelGGL((near_field_v2<T, LMAX, 2>), g, dim3(256), 0, st, s, N, nx, x0, y0, pitch, k, pts, P, E); break;
-    case 3: hipLaunchKernelGGL((near_field_v2<T, LMAX, 3>), g, dim3(256), 0, st, s, N, nx, x0, y0, pitch, k, pts, P, E); break;
-    default: hipLaunchKernelGGL((near_field_v2<T, LMAX, 4>), g, dim3(256), 0, st, s, N, nx, x0, y0, pitch, k, pts, P, E); break;
+    case 1: hipLaunchKernelGGL((near_field_v2<T, LMAX, 1>), g, dim3(256), 0, st, s, N, sp, k, pts, P, E); break;
+    case 2: hipLaunchKernelGGL((near_field_v2<T, LMAX, 2>), g, dim3(256), 0, st, s, N, sp, k, pts, P, E); break;
+    case 3: hipLaunchKernelGGL((near_field_v2<T, LMAX, 3>), g, dim3(256), 0, st, s, N, sp, k, pts, P, E); break;
+    default: hipLaunchKernelGGL((near_field_v2<T, LMAX, 4>), g, dim3(256), 0, st, s, N, sp, k, pts, P, E); break;
   }
 }
 
 template <typename T>
-static void nf_dispatch(int lmax, int R, dim3 g, hipStream_t st, const tm_c128* s, int N, int nx,
-                        double x0, double y0, double pitch, double k, const double* pts, int P,
-                        tm_c128* E) {
+static void nf_dispatch(int lmax, int R, dim3 g, hipStream_t st, const tm_c128* s, int N, SitePos sp,
+                        double k, const double* pts, int P, tm_c128* E) {
   switch (lmax) {
-    case 1: nf_dispatch_r<T, 1>(R, g, st, s, N, nx, x0, y0, pitch, k, pts, P, E); break;
-    case 2: nf_dispatch_r<T, 2>(R, g, st, s, N, nx, x0, y0, pitch, k, pts, P, E); break;
-    case 3: nf_dispatch_r<T, 3>(R, g, st, s, N, nx, x0, y0, pitch, k, pts, P, E); break;
-    case 4: nf_dispatch_r<T, 4>(R, g, st, s, N, nx, x0, y0, pitch, k, pts, P, E); break;
-    case 5: nf_dispatch_r<T, 5>(R, g, st, s, N, nx, x0, y0, pitch, k, pts, P, E); break;
-    default: nf_dispatch_r<T, 6>(R, g, st, s, N, nx, x0, y0, pitch, k, pts, P, E); break;
+    case 1: nf_dispatch_r<T, 1>(R, g, st, s, N, sp, k, pts, P, E); break;
+    case 2: nf_dispatch_r<T, 2>(R, g, st, s, N, sp, k, pts, P, E); break;
+    case 3: nf_dispatch_r<T, 3>(R, g, st, s, N, sp, k, pts, P, E); break;
+    case 4: nf_dispatch_r<T, 4>(R, g, st, s, N, sp, k, pts, P, E); break;
+    case 5: nf_dispatch_r<T, 5>(R, g, st, s, N, sp, k, pts, P, E); break;
+    default: nf_dispatch_r<T, 6>(R, g, st, s, N, sp, k, pts, P, E); break;
   }
 }
 
@@ -520,8 +522,8 @@ static void nf_dispatch(int lmax, int R, dim3 g, hipStream_t st, const tm_c128* 
 constexpr int FF_THREADS = 256;
 template <int LMAXT>
 __global__ __launch_bounds__(FF_THREADS) void far_field_kernel(
-    const tm_c128* __restrict__ s, int R, int N, int L, int lmax, int nx, double x0, double y0,
-    double pitch, double k, const double* __restrict__ dirs, int D, tm_c128* __restrict__ F) {
+    const tm_c128* __restrict__ s, int R, int N, int L, int lmax, SitePos sp, double k,
+    const double* __restrict__ dirs, int D, tm_c128* __restrict__ F) {
   constexpr int LM = 2 * LMAXT * (LMAXT + 2);
   __shared__ double red[FF_THREADS / 64][2 * LM];
   const int e = blockIdx.x;
@@ -531,16 +533,17 @@ __global__ __launch_bounds__(FF_THREADS) void far_field_kernel(
 #pragma unroll
   for (int n = 0; n < LM; ++n) cr[n] = ci[n] = 0.0;
   for (int i = threadIdx.x; i < N; i += FF_THREADS) {
-    const double xi = x0 + pitch * (double)(i % nx), yi = y0 + pitch * (double)(i / nx);
-    double sp, cp;
-    sincos(-k * (ux * xi + uy * yi), &sp, &cp);
+    double xi, yi;
+    sp.at(i, xi, yi);
+    double sph, cph;
+    sincos(-k * (ux * xi + uy * yi), &sph, &cph);
     const tm_c128* si = s + ((size_t)r * N + i) * L;
 #pragma unroll
     for (int n = 0; n < LM; ++n) {
       if (n < L) {
         const tm_c128 v = si[n];
-        cr[n] += cp * v.re - sp * v.im;
-        ci[n] += cp * v.im + sp * v.re;
+        cr[n] += cph * v.re - sph * v.im;
+        ci[n] += cph * v.im + sph * v.re;
       }
     }
   }
@@ -651,15 +654,16 @@ __device__ void outgoing_xyz(int n, int lmax, double dx, double dy, double dz, d
 
 __global__ void detector_kernel(double xdx, double xdy, double xdz, double wxr, double wxi,
                                 double wyr, double wyi, double wzr, double wzi, int N, int L,
-                                int lmax, int nx, double x0, double y0, double pitch, double k,
+                                int lmax, SitePos sp, double k,
                                 tm_c128* __restrict__ v) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (long long)N * L) return;
   const int n = (int)(e % L);
   const long long i = e / L;
   cx<double> Ex, Ey, Ez;
-  outgoing_xyz(n, lmax, xdx - (x0 + pitch * (double)(i % nx)), xdy - (y0 + pitch * (double)(i / nx)),
-               xdz, k, Ex, Ey, Ez);
+  double sx_, sy_;
+  sp.at(i, sx_, sy_);
+  outgoing_xyz(n, lmax, xdx - sx_, xdy - sy_, xdz, k, Ex, Ey, Ez);
   const cx<double> o = cx<double>(wxr, wxi) * Ex + cx<double>(wyr, wyi) * Ey + cx<double>(wzr, wzi) * Ez;
   v[e] = tm_c128{o.re, o.im};
 }
@@ -670,15 +674,16 @@ __global__ void detector_kernel(double xdx, double xdy, double xdz, double wxr, 
 constexpr int NFT_TILE = 256;
 __global__ __launch_bounds__(256) void near_field_t_kernel(
     const double* __restrict__ pts, const tm_c128* __restrict__ w, int P, int N, int L, int lmax,
-    int nx, double x0, double y0, double pitch, double k, tm_c128* __restrict__ v) {
-  __shared__ double sp[NFT_TILE][3];
+    SitePos sp, double k, tm_c128* __restrict__ v) {
+  __shared__ double spt[NFT_TILE][3];
   __shared__ cplx<double> sw[NFT_TILE][3];
   const int r = blockIdx.y;
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const bool active = e < (long long)N * L;
   const int n = active ? (int)(e % L) : 0;
   const long long i = active ? e / L : 0;
-  const double xi = x0 + pitch * (double)(i % nx), yi = y0 + pitch * (double)(i / nx);
+  double xi, yi;
+  sp.at(i, xi, yi);
   cx<double> acc(0.0, 0.0);
   const tm_c128* wr = w + (size_t)r * P * 3;
   for (int p0 = 0; p0 < P; p0 += NFT_TILE) {
@@ -686,7 +691,7 @@ __global__ __launch_bounds__(256) void near_field_t_kernel(
     __syncthreads();
     for (int t = threadIdx.x; t < np; t += blockDim.x) {
       for (int c3 = 0; c3 < 3; ++c3) {
-        sp[t][c3] = pts[(size_t)(p0 + t) * 3 + c3];
+        spt[t][c3] = pts[(size_t)(p0 + t) * 3 + c3];
         const tm_c128 q = wr[(size_t)(p0 + t) * 3 + c3];
         sw[t][c3] = cplx<double>{q.re, q.im};
       }
@@ -695,7 +700,7 @@ __global__ __launch_bounds__(256) void near_field_t_kernel(
     if (active) {
       for (int t = 0; t < np; ++t) {
         cx<double> Ex, Ey, Ez;
-        outgoing_xyz(n, lmax, sp[t][0] - xi, sp[t][1] - yi, sp[t][2], k, Ex, Ey, Ez);
+        outgoing_xyz(n, lmax, spt[t][0] - xi, spt[t][1] - yi, spt[t][2], k, Ex, Ey, Ez);
         acc = acc + cx<double>(sw[t][0].re, sw[t][0].im) * Ex + cx<double>(sw[t][1].re, sw[t][1].im) * Ey +
               cx<double>(sw[t][2].re, sw[t][2].im) * Ez;
       }
@@ -777,15 +782,17 @@ struct DgradArgs {
 };
 __global__ void gpos_detector_kernel(const tm_c128* __restrict__ s, const c128* __restrict__ coef,
                                      const int* __restrict__ dm, int R, int N, int L, int lmax,
-                                     int nx, double x0, double y0, double pitch, double k,
+                                     SitePos sp, double k,
                                      double xdx, double xdy, double xdz, DgradArgs wa,
                                      double* __restrict__ grad) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (long long)R * N) return;
   const int r = (int)(e / N);
   const long long i = e % N;
-  const double dx = xdx - (x0 + pitch * (double)(i % nx));
-  const double dy = xdy - (y0 + pitch * (double)(i / nx));
+  double sx_, sy_;
+  sp.at(i, sx_, sy_);
+  const double dx = xdx - sx_;
+  const double dy = xdy - sy_;
   const double dz = xdz;
   const double rho2 = dx * dx + dy * dy;
   const double rr = sqrt(rho2 + dz * dz);
@@ -879,8 +886,8 @@ int launch_gpos_detector(tm_ctx* c, int R, const tm_c128* s, const c128* coef, c
       wa.W[(r * 3 + 2) * 2 + 1] = a * (wr[0].im + wr[1].re);
     }
     hipLaunchKernelGGL(gpos_detector_kernel, dim3(nblk((long long)nr * g.n)), dim3(256), 0,
-                       c->stream, s + (size_t)r0 * g.n * g.L, coef, dm, nr, g.n, g.L, g.lmax, g.nx,
-                       g.x0, g.y0, g.pitch, g.k, xd[0], xd[1], xd[2], wa,
+                       c->stream, s + (size_t)r0 * g.n * g.L, coef, dm, nr, g.n, g.L, g.lmax,
+                       site_pos(c), g.k, xd[0], xd[1], xd[2], wa,
                        grad + (size_t)r0 * g.n * 2);
   }
   TM_HIP(c, hipGetLastError());
@@ -888,6 +895,273 @@ int launch_gpos_detector(tm_ctx* c, int R, const tm_c128* s, const c128* coef, c
 }
 
 
+
+// ---------------------------------------------------------------- null-field T-matrix
+// T-matrix of a body of revolution about z by the null-field method (App.
+// I.B): for each m the matrices of surface integrals
+//   O_ab = 2 pi sum_nodes w [ R Phi_{l'mp'}(k_s x) x Phi_{l,-m,1-p}(k_b x)
+//                             + (k_s/k_b) R Phi_{l'm,1-p'}(k_s x) x Phi_{l,-m,p}(k_b x) ] . n
+// (outgoing test waves) and R_ab (the same with regular test waves), a = (l, p),
+// b = (l', p'), and T_m = -R O^{-1}.  The two terms add and the regular-test
+// matrix multiplies the inverse, the forms that reproduce the Lorenz-Mie T on
+// a sphere in this basis.  One workgroup per (scatterer, m); the surface is a
+// cylinder of radius a_i and height h centred on the scatterer (bottom cap,
+// side, top cap, nq Gauss-Legendre nodes each).
+constexpr int EB_NB = 2 * LMAX_SUPPORTED;       // largest m block (l = 1..lmax, two types)
+constexpr int EB_CHUNK = 32;                    // surface nodes staged per pass
+
+// j_l(z), l = 0..lmax+1 at complex z by the power series (|z| <= 12)
+__device__ inline void sph_j_all(int lmax, cx<double> z, cx<double>* j) {
+  for (int l = 0; l <= lmax; ++l) j[l] = sph_j_series(l, z);
+}
+
+// Spherical components (r, theta, phi) of Phi_lmp without e^{imphi}, from the
+// radial pair (z_l, (x z_l)'/x at x) and the Legendre data (Pbar, m Pbar/sin, tau).
+__device__ inline void vswf_rtp(int l, int p, cx<double> zl, cx<double> dz, cx<double> x, double P,
+                                double pim, double tau, cx<double>* v) {
+  const double nrm = 1.0 / sqrt(2.0 * l * (l + 1));
+  if (p == 0) {
+    v[0] = cx<double>(0.0, 0.0);
+    v[1] = nrm * mul_i(pim * zl);
+    v[2] = (-nrm * tau) * zl;
+  } else {
+    v[0] = (nrm * l * (l + 1) * P) * (zl / x);
+    v[1] = (nrm * tau) * dz;
+    v[2] = mul_i((nrm * pim) * dz);
+  }
+}
+
+__device__ inline cx<double> cross_dot_n(const cx<double>* a, const cx<double>* b, double nr, double nt) {
+  // (a x b) . n with n = (nr, nt, 0) in (r, theta, phi)
+  const cx<double> cr = a[1] * b[2] - a[2] * b[1];
+  const cx<double> ct = a[2] * b[0] - a[0] * b[2];
+  return nr * cr + nt * ct;
+}
+
+struct EbNode {
+  double r, th, nr, nt, w;
+};
+
+__global__ __launch_bounds__(256) void ebcm_cylinder_kernel(const double* __restrict__ radii, double height,
+                                                            double k, double nre, double nim, int lmax,
+                                                            int nq, const double* __restrict__ gl,
+                                                            tm_c128* __restrict__ T) {
+  const int i = blockIdx.x;
+  const int m = (int)blockIdx.y - lmax;
+  const int am = m < 0 ? -m : m;
+  const int l0 = am > 1 ? am : 1;
+  const int nl = lmax - l0 + 1, nb = 2 * nl;
+  const int L = 2 * lmax * (lmax + 2);
+  const double a = radii[i];
+  const cx<double> nrel(nre, nim);
+  const cx<double> ks = k * nrel;
+  __shared__ EbNode nodes[EB_CHUNK];
+  // per node: test waves (outgoing and regular at k_b) and internal waves (regular at k_s),
+  // each for l = l0..lmax and both types, in (r, theta, phi) components
+  __shared__ cplx<double> wout[EB_CHUNK][EB_NB][3], wreg[EB_CHUNK][EB_NB][3], wint[EB_CHUNK][EB_NB][3];
+  __shared__ cplx<double> Pm[EB_NB][EB_NB], Qm[EB_NB][EB_NB];
+  const int tid = threadIdx.x;
+  const int ea = tid / EB_NB, eb = tid % EB_NB;  // entry (a, b) of this thread
+  const bool own = tid < EB_NB * EB_NB && ea < nb && eb < nb;
+  cx<double> accO, accR;
+  const int total = 3 * nq;
+  for (int n0 = 0; n0 < total; n0 += EB_CHUNK) {
+    const int cnt = min(EB_CHUNK, total - n0);
+    __syncthreads();
+    if (tid < cnt) {
+      // node n0 + tid on the generating curve: segment, Gauss-Legendre point
+      const int q = n0 + tid, seg = q / nq, g = q % nq;
+      const double u = 0.5 * (gl[2 * g] + 1.0), wg = gl[2 * g + 1];
+      double rho, z, ncr, ncz, wl;
+      if (seg == 0) {        // bottom cap, normal -z
+        rho = a * u; z = -0.5 * height; ncr = 0.0; ncz = -1.0; wl = 0.5 * a * wg;
+      } else if (seg == 1) { // side, normal rho_hat
+        rho = a; z = height * (u - 0.5); ncr = 1.0; ncz = 0.0; wl = 0.5 * height * wg;
+      } else {               // top cap, normal +z
+        rho = a * u; z = 0.5 * height; ncr = 0.0; ncz = 1.0; wl = 0.5 * a * wg;
+      }
+      const double r = sqrt(rho * rho + z * z), th = atan2(rho, z);
+      const double st = sin(th), ct = cos(th);
+      EbNode nd;
+      nd.r = r;
+      nd.th = th;
+      nd.nr = ncr * st + ncz * ct;
+      nd.nt = ncr * ct - ncz * st;
+      nd.w = wl * rho;
+      nodes[tid] = nd;
+      // radial functions
+      const double xb = k * r;
+      double sn, cs;
+      sincos(xb, &sn, &cs);
+      cx<double> hb[LMAX_SUPPORTED + 2], jb[LMAX_SUPPORTED + 2], js[LMAX_SUPPORTED + 2];
+      hankel_set<double>(xb, cs, sn, lmax, hb);
+      sph_j_all(lmax, cx<double>(xb, 0.0), jb);
+      const cx<double> xs = r * ks;
+      sph_j_all(lmax, xs, js);
+      for (int li = 0; li < nl; ++li) {
+        const int l = l0 + li;
+        double P, U, tau;
+        legendre_one<double>(l, am, ct, st, P, U, tau);
+        const double pim = (double)m * U;  // the internal waves carry +m
+        const cx<double> X(xb, 0.0);
+        const cx<double> dhb = hb[l - 1] - ((double)l / xb) * hb[l];
+        const cx<double> djb = jb[l - 1] - ((double)l / xb) * jb[l];
+        const cx<double> djs = js[l - 1] - ((double)l) * (js[l] / xs);
+        for (int p = 0; p < 2; ++p) {
+          cx<double> v[3];
+          // test waves carry -m: pi changes sign, Pbar and tau do not
+          vswf_rtp(l, p, hb[l], dhb, X, P, -pim, tau, v);
+          for (int c = 0; c < 3; ++c) wout[tid][2 * li + p][c] = cplx<double>{v[c].re, v[c].im};
+          vswf_rtp(l, p, jb[l], djb, X, P, -pim, tau, v);
+          for (int c = 0; c < 3; ++c) wreg[tid][2 * li + p][c] = cplx<double>{v[c].re, v[c].im};
+          vswf_rtp(l, p, js[l], djs, xs, P, pim, tau, v);
+          for (int c = 0; c < 3; ++c) wint[tid][2 * li + p][c] = cplx<double>{v[c].re, v[c].im};
+        }
+      }
+    }
+    __syncthreads();
+    if (own) {
+      // row a = (l, p) -> test index 2 li + p; column b = (l', p') -> internal
+      const int la = ea >> 1, pa = ea & 1, lb = eb >> 1, pb = eb & 1;
+      const cx<double> ratio = ks / cx<double>(k, 0.0);
+      for (int q = 0; q < cnt; ++q) {
+        const EbNode nd = nodes[q];
+        cx<double> ip[3], iq[3], o1[3], o0[3], r1[3], r0[3];
+        for (int c = 0; c < 3; ++c) {
+          ip[c] = cx<double>(wint[q][2 * lb + pb][c].re, wint[q][2 * lb + pb][c].im);
+          iq[c] = cx<double>(wint[q][2 * lb + 1 - pb][c].re, wint[q][2 * lb + 1 - pb][c].im);
+          o1[c] = cx<double>(wout[q][2 * la + 1 - pa][c].re, wout[q][2 * la + 1 - pa][c].im);
+          o0[c] = cx<double>(wout[q][2 * la + pa][c].re, wout[q][2 * la + pa][c].im);
+          r1[c] = cx<double>(wreg[q][2 * la + 1 - pa][c].re, wreg[q][2 * la + 1 - pa][c].im);
+          r0[c] = cx<double>(wreg[q][2 * la + pa][c].re, wreg[q][2 * la + pa][c].im);
+        }
+        const cx<double> fo = cross_dot_n(ip, o1, nd.nr, nd.nt) + ratio * cross_dot_n(iq, o0, nd.nr, nd.nt);
+        const cx<double> fr = cross_dot_n(ip, r1, nd.nr, nd.nt) + ratio * cross_dot_n(iq, r0, nd.nr, nd.nt);
+        accO = accO + nd.w * fo;
+        accR = accR + nd.w * fr;
+      }
+    }
+  }
+  if (own) {
+    const double tp = 6.283185307179586476925286766559;
+    Pm[ea][eb] = cplx<double>{tp * accO.re, tp * accO.im};
+    Qm[ea][eb] = cplx<double>{tp * accR.re, tp * accR.im};
+  }
+  __syncthreads();
+  if (tid == 0) {
+    // T_m O = -R  <=>  O^T T_m^T = -R^T: Gaussian elimination with partial
+    // pivoting on O^T (columns of the unknown: the rows of T_m)
+    cx<double> A[EB_NB][EB_NB], B[EB_NB][EB_NB];
+    for (int r_ = 0; r_ < nb; ++r_)
+      for (int c_ = 0; c_ < nb; ++c_) {
+        A[r_][c_] = cx<double>(Pm[c_][r_].re, Pm[c_][r_].im);   // O^T
+        B[r_][c_] = cx<double>(-Qm[c_][r_].re, -Qm[c_][r_].im); // -R^T
+      }
+    for (int c_ = 0; c_ < nb; ++c_) {
+      int piv = c_;
+      double best = -1.0;
+      for (int r_ = c_; r_ < nb; ++r_) {
+        const double v = A[r_][c_].re * A[r_][c_].re + A[r_][c_].im * A[r_][c_].im;
+        if (v > best) {
+          best = v;
+          piv = r_;
+        }
+      }
+      if (piv != c_)
+        for (int q = 0; q < nb; ++q) {
+          const cx<double> t1 = A[c_][q];
+          A[c_][q] = A[piv][q];
+          A[piv][q] = t1;
+          const cx<double> t2 = B[c_][q];
+          B[c_][q] = B[piv][q];
+          B[piv][q] = t2;
+        }
+      const cx<double> inv = cx<double>(1.0, 0.0) / A[c_][c_];
+      for (int r_ = c_ + 1; r_ < nb; ++r_) {
+        const cx<double> f = A[r_][c_] * inv;
+        for (int q = c_; q < nb; ++q) A[r_][q] = A[r_][q] - f * A[c_][q];
+        for (int q = 0; q < nb; ++q) B[r_][q] = B[r_][q] - f * B[c_][q];
+      }
+    }
+    for (int r_ = nb - 1; r_ >= 0; --r_) {
+      const cx<double> inv = cx<double>(1.0, 0.0) / A[r_][r_];
+      for (int q = 0; q < nb; ++q) {
+        cx<double> acc = B[r_][q];
+        for (int c_ = r_ + 1; c_ < nb; ++c_) acc = acc - A[r_][c_] * B[c_][q];
+        B[r_][q] = acc * inv;
+      }
+    }
+    // B = T_m^T: T_m[a][b] = B[b][a]; scatter into the boundary order
+    tm_c128* Ti = T + (size_t)i * L * L;
+    const int half = lmax * (lmax + 2);
+    for (int a_ = 0; a_ < nb; ++a_)
+      for (int b_ = 0; b_ < nb; ++b_) {
+        const int la = l0 + (a_ >> 1), pa = a_ & 1, lb = l0 + (b_ >> 1), pb = b_ & 1;
+        const int na = pa * half + la * (la + 1) - 1 + m, nbi = pb * half + lb * (lb + 1) - 1 + m;
+        Ti[(size_t)na * L + nbi] = tm_c128{B[b_][a_].re, B[b_][a_].im};
+      }
+  }
+}
+
+__global__ void fill_c128_kernel(tm_c128* __restrict__ p, long long n) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) p[e] = tm_c128{0.0, 0.0};
+}
+
+// Gauss-Legendre nodes and weights on [-1, 1] as (x, w) pairs.
+static void gauss_legendre(int n, std::vector<double>& out) {
+  out.assign((size_t)2 * n, 0.0);
+  const double pi = 3.14159265358979323846;
+  for (int i = 0; i < n; ++i) {
+    double z = cos(pi * (i + 0.75) / (n + 0.5)), pp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int j = 2; j <= n; ++j) {
+        const double p2 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p0) / j;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (n == 1) {
+        p1 = z;
+        p0 = 1.0;
+      }
+      pp = n * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / pp;
+      z -= dz;
+      if (fabs(dz) < 1e-16) break;
+    }
+    out[2 * i] = z;
+    out[2 * i + 1] = 2.0 / ((1.0 - z * z) * pp * pp);
+  }
+}
+
+// Dense T of N cylinders (radii device [N]) into T device [N][L][L].
+int launch_ebcm_cylinders(tm_ctx* c, hipStream_t st, int N, const double* radii, double height, double k,
+                          double nre, double nim, int lmax, int nq, tm_c128* T) {
+  std::vector<double> gl;
+  gauss_legendre(nq, gl);
+  double* dgl = nullptr;
+  if (hipMalloc((void**)&dgl, gl.size() * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    return c ? set_err(c, TM_ERR_OOM, "device allocation failed") : TM_ERR_OOM;
+  }
+  const int L = 2 * lmax * (lmax + 2);
+  int rc = TM_OK;
+  if (hipMemcpyAsync(dgl, gl.data(), gl.size() * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess)
+    rc = TM_ERR_HIP;
+  if (rc == TM_OK) {
+    const long long tot = (long long)N * L * L;
+    hipLaunchKernelGGL(fill_c128_kernel, dim3(nblk(tot)), dim3(256), 0, st, T, tot);
+    hipLaunchKernelGGL(ebcm_cylinder_kernel, dim3(N, 2 * lmax + 1), dim3(256), 0, st, radii, height, k,
+                       nre, nim, lmax, nq, dgl, T);
+    if (hipGetLastError() != hipSuccess) rc = TM_ERR_HIP;
+  }
+  // the host nodes are read by the asynchronous copy; the buffer goes after the launch
+  if (hipStreamSynchronize(st) != hipSuccess) rc = TM_ERR_HIP;
+  hipFree(dgl);
+  if (rc != TM_OK && c) set_err(c, rc, "null-field T-matrix launch failed");
+  return rc;
+}
 
 // ---------------------------------------------------------------- jinc sources
 // Expansion coefficients of a jinc source (App. II, "Implementing jinc source
@@ -990,7 +1264,7 @@ struct JincSrc {
 
 // a0[r][i][n] = coefficients of source r about scatterer i (one lattice)
 __global__ void jinc_rhs_kernel(const JincSrc* __restrict__ src, int R, int N, int L, int lmax,
-                                int nx, double x0, double y0, double pitch, double k,
+                                SitePos sp, double k,
                                 const double* __restrict__ nodes, int nb, tm_c128* __restrict__ a0) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (long long)R * N * L) return;
@@ -998,7 +1272,8 @@ __global__ void jinc_rhs_kernel(const JincSrc* __restrict__ src, int R, int N, i
   const long long i = (e / L) % N;
   const int r = (int)(e / ((long long)L * N));
   const JincSrc s = src[r];
-  const double xi = x0 + pitch * (double)(i % nx), yi = y0 + pitch * (double)(i / nx);
+  double xi, yi;
+  sp.at(i, xi, yi);
   const cx<double> v = jinc_coeff(n, lmax, xi - s.x0, yi - s.y0, -s.z0, k, cx<double>(s.axr, s.axi),
                                   cx<double>(s.ayr, s.ayi), nodes, nb);
   a0[e] = tm_c128{v.re, v.im};
@@ -1106,7 +1381,7 @@ int launch_jinc_rhs(tm_ctx* c, int R, const tm_jinc* src, int nb, tm_c128* a0) {
   if ((rc = upload_jinc(c, R, src, nb, c->jinc_buf, &dsrc, &dnodes, 0, nullptr)) != TM_OK) return rc;
   const long long total = (long long)R * g.n * g.L;
   hipLaunchKernelGGL(jinc_rhs_kernel, dim3(nblk(total)), dim3(256), 0, c->stream, dsrc, R, g.n, g.L,
-                     g.lmax, g.nx, g.x0, g.y0, g.pitch, g.k, dnodes, nb, a0);
+                     g.lmax, site_pos(c), g.k, dnodes, nb, a0);
   TM_HIP(c, hipGetLastError());
   return TM_OK;
 }
@@ -1199,7 +1474,7 @@ int launch_plane_wave(tm_ctx* c, int R, const double* khat, const tm_c128* pol, 
     }
     const long long total = (long long)nr * g.n * g.L;
     hipLaunchKernelGGL(plane_wave_kernel, dim3(nblk(total)), dim3(256), 0, c->stream, pw, nr, g.n,
-                       g.L, g.lmax, g.nx, g.x0, g.y0, g.pitch, g.k,
+                       g.L, g.lmax, site_pos(c), g.k,
                        a0 + (size_t)r0 * g.n * g.L);
   }
   TM_HIP(c, hipGetLastError());
@@ -1214,11 +1489,11 @@ int launch_near_field(tm_ctx* c, int R, const tm_c128* s, int P, const double* p
     const tm_c128* sr = s + (size_t)r0 * g.n * g.L;
     tm_c128* Er = E + (size_t)r0 * P * 3;
     if (precision == TM_PREC_MIXED)
-      nf_dispatch<float>(g.lmax, nr, dim3(nblk(P)), c->stream, sr, g.n, g.nx, g.x0, g.y0, g.pitch,
+      nf_dispatch<float>(g.lmax, nr, dim3(nblk(P)), c->stream, sr, g.n, site_pos(c),
                          g.k, pts, P, Er);
     else
-      nf_dispatch<double>(g.lmax, nr, dim3(nblk(P)), c->stream, sr, g.n, g.nx, g.x0, g.y0,
-                          g.pitch, g.k, pts, P, Er);
+      nf_dispatch<double>(g.lmax, nr, dim3(nblk(P)), c->stream, sr, g.n, site_pos(c), g.k, pts,
+                          P, Er);
   }
   TM_HIP(c, hipGetLastError());
   return TM_OK;
@@ -1228,7 +1503,7 @@ int launch_far_field(tm_ctx* c, int R, const tm_c128* s, int D, const double* di
   const Geometry& g = c->g;
 #define FF_LAUNCH(LM)                                                                              \
   hipLaunchKernelGGL(far_field_kernel<LM>, dim3((unsigned)((long long)R * D)), dim3(FF_THREADS), 0, \
-                     c->stream, s, R, g.n, g.L, g.lmax, g.nx, g.x0, g.y0, g.pitch, g.k, dirs, D, F)
+                     c->stream, s, R, g.n, g.L, g.lmax, site_pos(c), g.k, dirs, D, F)
   // per-thread coefficient sums sized for the geometry's lmax
   switch (g.lmax) {
     case 1: FF_LAUNCH(1); break;
@@ -1247,7 +1522,7 @@ int launch_detector(tm_ctx* c, const double* xd, const tm_c128* w, tm_c128* v) {
   const Geometry& g = c->g;
   hipLaunchKernelGGL(detector_kernel, dim3(nblk((long long)g.n * g.L)), dim3(256), 0, c->stream,
                      xd[0], xd[1], xd[2], w[0].re, w[0].im, w[1].re, w[1].im, w[2].re, w[2].im,
-                     g.n, g.L, g.lmax, g.nx, g.x0, g.y0, g.pitch, g.k, v);
+                     g.n, g.L, g.lmax, site_pos(c), g.k, v);
   TM_HIP(c, hipGetLastError());
   return TM_OK;
 }
@@ -1255,7 +1530,7 @@ int launch_detector(tm_ctx* c, const double* xd, const tm_c128* w, tm_c128* v) {
 int launch_near_field_t(tm_ctx* c, int R, int P, const double* pts, const tm_c128* w, tm_c128* v) {
   const Geometry& g = c->g;
   hipLaunchKernelGGL(near_field_t_kernel, dim3(nblk((long long)g.n * g.L), R), dim3(256), 0,
-                     c->stream, pts, w, P, g.n, g.L, g.lmax, g.nx, g.x0, g.y0, g.pitch, g.k, v);
+                     c->stream, pts, w, P, g.n, g.L, g.lmax, site_pos(c), g.k, v);
   TM_HIP(c, hipGetLastError());
   return TM_OK;
 }

@@ -1030,6 +1030,7 @@ static int batched_entry(tm_ctx* c, int n_sub, const tm_subregion* subs, int n_r
   if (!c->have_geom || !c->have_t) return tmh::set_err(c, TM_ERR_STATE, "geometry and T must be set");
   if (c->t_dense)
     return tmh::set_err(c, TM_ERR_STATE, "the batched solver takes diagonal T (spheres or tm_set_tmatrix_diag)");
+  if (!c->g.lattice) return tmh::set_err(c, TM_ERR_NOT_LATTICE, "subregions need a lattice geometry");
   if (n_sub < 1 || n_rhs < 1 || n_rhs > 8 || !subs || (!a0_packed && (!khat || !pol)) || !s_out || !o ||
       !info)
     return tmh::set_err(c, TM_ERR_INVALID_ARG, "bad arguments");

@@ -39,6 +39,7 @@ using c128 = cplx<double>;
 
 struct Geometry {
   int n = 0, nx = 0, ny = 0, lmax = 0, L = 0;
+  bool lattice = true;  // false: arbitrary positions in z = 0 (no displacement tables)
   int S = SLOTS, NG = 1;                      // slots per class, groups of 16 per class
   double pitch = 0.0, k = 0.0, x0 = 0.0, y0 = 0.0;
   // slot map: for boundary index n -> class, slot; and per class the list
@@ -55,6 +56,23 @@ struct SlotMaps {
   int slot_of[LM_MAX];
   int n_of[NCLASS][SMAX];
   int L, lmax, S;
+};
+
+// Scatterer centres in the z = 0 plane as kernels see them: on a lattice
+// they follow from the site index, otherwise from a device array [N][2].
+struct SitePos {
+  const double* xy;  // device [N][2] (x, y), or null on a lattice
+  int nx;
+  double x0, y0, pitch;
+  __device__ inline void at(long long i, double& x, double& y) const {
+    if (xy) {
+      x = xy[2 * i];
+      y = xy[2 * i + 1];
+    } else {
+      x = x0 + pitch * (double)(i % nx);
+      y = y0 + pitch * (double)(i / nx);
+    }
+  }
 };
 
 // One subregion of a batched solve: its lattice, the offset of its
@@ -109,6 +127,9 @@ struct tm_ctx {
   bool have_dtab = false;
   tmh::DevBuf gpos;  // position-gradient workspace (slot-layout vectors)
   tmh::DevBuf jinc_buf;  // jinc sources, polar nodes and subregion tables
+  tmh::DevBuf xy;        // scatterer centres [N][2] (off-lattice geometries)
+  tmh::DevBuf olc;       // off-lattice translation constants (coef, dm)
+  std::vector<double> host_xy;  // the same on the host (off-lattice)
   // T and dT/dr in slot layout [2][N][S]
   tmh::DevBuf t64, t32, dt64;
   tmh::DevBuf tden, ttmp;  // dense T [N][L][L] (boundary order); its scratch vector
@@ -143,6 +164,10 @@ struct tm_ctx {
 
 namespace tmh {
 
+inline SitePos site_pos(const tm_ctx* c) {
+  return SitePos{c->g.lattice ? nullptr : (const double*)c->xy.p, c->g.nx, c->g.x0, c->g.y0, c->g.pitch};
+}
+
 // ---- error helpers -------------------------------------------------------
 int set_err(tm_ctx* c, int code, const std::string& msg);
 #define TM_HIP(ctx, call)                                                       \
@@ -163,6 +188,11 @@ void release(DevBuf& b);
 int build_tables(tm_ctx* c);            // forward tables, FP64 + c64
 int build_transposed_tables(tm_ctx* c); // A^T tables
 int build_derivative_tables(tm_ctx* c); // position-gradient tables (FP64)
+int build_offlattice_constants(tm_ctx* c);  // per-entry constants of the on-the-fly matvec
+// on-the-fly block matvec for off-lattice geometries (tm_offlattice.hip)
+enum class Op;
+template <typename T>
+int offlattice_apply(tm_ctx* c, Op op, int R, const void* xin, const c128* x, c128* y);
 void detector_grad_constants(int lmax, std::vector<c128>& coef, std::vector<int>& dm);
 void host_slot_maps(int lmax, Geometry& g, SlotMaps& m);
 
@@ -189,6 +219,10 @@ int launch_gpos_contract(tm_ctx* c, int R, const c128* lam, const c128* s, const
 int launch_gpos_detector(tm_ctx* c, int R, const tm_c128* s, const c128* coef, const int* dm,
                          const double* xd, const tm_c128* w, double* grad);
 
+// null-field T-matrices of cylinders (tm_basis.hip): T device [N][L][L];
+// c may be null (then no error message is recorded)
+int launch_ebcm_cylinders(tm_ctx* c, hipStream_t st, int N, const double* radii, double height, double k,
+                          double nre, double nim, int lmax, int nq, tm_c128* T);
 // jinc sources (tm_basis.hip): one lattice [R][N][L], or packed subregions
 // with one source group per (subregion, rhs)
 int jinc_beta_count(double k, double rmax);

@@ -431,6 +431,16 @@ static int apply_impl(tm_ctx* c, Op op, int R, const c128* x, c128* y) {
   const long long total = vec * R;
   const bool transposed = (op == Op::Adjoint || op == Op::CouplingT);
   int rc;
+  if (!g.lattice) {  // off-lattice: blocks formed on the fly, no tables
+    const void* xin = x;
+    if (!std::is_same<T, double>::value || op == Op::Adjoint) {
+      if ((rc = ensure(c, c->xlow, (size_t)total * sizeof(cplx<T>))) != TM_OK) return rc;
+      launch_prep<T>(c->stream, x, op == Op::Adjoint ? (const c128*)c->t64.p : nullptr, c->xlow.p, vec,
+                     total);
+      xin = c->xlow.p;
+    }
+    return offlattice_apply<T>(c, op, R, xin, x, y);
+  }
   if (transposed && !c->have_tabT) {
     if ((rc = build_transposed_tables(c)) != TM_OK) return rc;
   }

@@ -114,6 +114,7 @@ extern "C" int tm_apply_operator_noalloc(tm_ctx* c, int R, const tm_c128* x, tm_
                                          int precision, int op) {
   if (!c) return TM_ERR_INVALID_ARG;
   if (!c->have_geom) return tmh::set_err(c, TM_ERR_STATE, "set geometry first");
+  if (!c->g.lattice) return tmh::set_err(c, TM_ERR_NOT_LATTICE, "the allocation-free operator needs a lattice");
   if (R < 1 || !x || !y || x == y || op < 0 || op > 3 ||
       (precision != TM_PREC_FP64 && precision != TM_PREC_MIXED))
     return tmh::set_err(c, TM_ERR_INVALID_ARG, "bad arguments");

@@ -1,0 +1,193 @@
+// Block matvec for scatterers at arbitrary positions in the z = 0 plane: the
+// translation blocks are formed on the fly per (target, source) pair instead
+// of being read from a per-displacement table (the paper's own GPU matvec
+// computes matrix elements on the fly, App. I.D).  For a pair with
+// d = x_t - x_s (r = |d|, azimuth phi) and every entry (i, j) of a z-mirror
+// class block,
+//   M_ij(d) = e^{i dm_ij phi} sum_q C_ijq h_q(k r)
+// (App. I.C, eq. "tran_coeff", the Legendre factor at theta = pi/2 folded into
+// C), and z_t = sum_{s != t} M(x_t - x_s) x_s.  The transposed operator uses
+// (A^T)_ts = M(x_s - x_t)^T.
+//
+// One thread per target; the workgroups of a launch split the sources into
+// chunks (blockIdx.z) whose partial sums a combine kernel adds in chunk order
+// (deterministic).  Sources of a chunk are staged through LDS in groups; the
+// coefficient loop is uniform across the wave, so its constants are scalar
+// loads.  Arithmetic in T (FP64, or FP32 for the mixed path with k r reduced
+// modulo 2 pi in FP64 before the FP32 sine and cosine).
+#include <algorithm>
+#include <cmath>
+
+#include "tm_internal.h"
+
+namespace tmh {
+
+constexpr int OL_THREADS = 256;
+constexpr int OL_GROUP = 64;  // sources staged per LDS pass
+
+template <typename T>
+__device__ inline void ol_hankel(double kr, int qmax, T* hr, T* hi) {
+  const double twopi = 6.283185307179586476925286766559;
+  const double red = kr - twopi * rint(kr / twopi);
+  T s, c;
+  if (sizeof(T) == 4) {
+    float sf, cf;
+    sincosf((float)red, &sf, &cf);
+    s = (T)sf;
+    c = (T)cf;
+  } else {
+    double sd, cd;
+    sincos(red, &sd, &cd);
+    s = (T)sd;
+    c = (T)cd;
+  }
+  const T x = (T)kr, ix = (T)1 / x;
+  hr[0] = s * ix;
+  hi[0] = -c * ix;
+  hr[1] = -(c * x - s) * ix * ix;
+  hi[1] = -(s * x + c) * ix * ix;
+  for (int q = 1; q < qmax; ++q) {
+    const T f = (T)(2 * q + 1) * ix;
+    hr[q + 1] = f * hr[q] - hr[q - 1];
+    hi[q + 1] = f * hi[q] - hi[q - 1];
+  }
+}
+
+// partial[chunk][r][c][t][S] = sum over the chunk's sources of M x_s (or M^T)
+template <typename T>
+__global__ __launch_bounds__(OL_THREADS) void offlattice_kernel(
+    const double* __restrict__ xy, const cplx<T>* __restrict__ x, const double* __restrict__ coef,
+    const int* __restrict__ dm, int N, int S, int nh, int lmax, double k, int chunk, int transpose,
+    cplx<T>* __restrict__ partial) {
+  extern __shared__ double ol_lds[];
+  double* sxy = ol_lds;                                        // [OL_GROUP][2]
+  cplx<T>* sx = reinterpret_cast<cplx<T>*>(ol_lds + 2 * OL_GROUP);  // [OL_GROUP][S]
+  const int t = blockIdx.x * OL_THREADS + threadIdx.x;
+  const int rc = blockIdx.y;  // r * 2 + c
+  const int c = rc & 1;
+  const int s0 = blockIdx.z * chunk, s1 = min(N, s0 + chunk);
+  const bool live = t < N;
+  const double xt = live ? xy[2 * t] : 0.0, yt = live ? xy[2 * t + 1] : 0.0;
+  const int Q = 2 * lmax + 1;
+  const cplx<T>* xin = x + (size_t)rc * N * S;
+  const double* cf = coef + (size_t)c * S * S * Q * 2;
+  const int* dmc = dm + (size_t)c * S * S;
+  T yr[SMAX], yi[SMAX];
+  for (int i = 0; i < S; ++i) yr[i] = yi[i] = (T)0;
+  for (int g0 = s0; g0 < s1; g0 += OL_GROUP) {
+    const int ng = min(OL_GROUP, s1 - g0);
+    __syncthreads();
+    for (int q = threadIdx.x; q < ng * S; q += OL_THREADS) {
+      const int ss = q / S, j = q % S;
+      sx[q] = xin[(size_t)(g0 + ss) * S + j];
+    }
+    for (int q = threadIdx.x; q < 2 * ng; q += OL_THREADS) sxy[q] = xy[2 * g0 + q];
+    __syncthreads();
+    if (!live) continue;
+    for (int ss = 0; ss < ng; ++ss) {
+      const int s = g0 + ss;
+      if (s == t) continue;
+      // displacement of the block: target - source (source - target for A^T)
+      const double dx = transpose ? sxy[2 * ss] - xt : xt - sxy[2 * ss];
+      const double dy = transpose ? sxy[2 * ss + 1] - yt : yt - sxy[2 * ss + 1];
+      const double r = sqrt(dx * dx + dy * dy);
+      T hr[2 * LMAX_SUPPORTED + 1], hi[2 * LMAX_SUPPORTED + 1];
+      ol_hankel<T>(k * r, Q - 1, hr, hi);
+      // e^{i mu phi}, mu = 0..2 lmax, from (dx + i dy)/r
+      const T cph = (T)(dx / r), sph = (T)(dy / r);
+      T er[2 * LMAX_SUPPORTED + 1], ei[2 * LMAX_SUPPORTED + 1];
+      er[0] = (T)1;
+      ei[0] = (T)0;
+      for (int mu = 1; mu < Q; ++mu) {
+        er[mu] = er[mu - 1] * cph - ei[mu - 1] * sph;
+        ei[mu] = er[mu - 1] * sph + ei[mu - 1] * cph;
+      }
+      const cplx<T>* xs = sx + (size_t)ss * S;
+      for (int i = 0; i < nh; ++i) {
+        T ar = (T)0, ai = (T)0;
+        for (int j = 0; j < nh; ++j) {
+          // entry (i, j) of M, or (j, i) for the transposed operator
+          const int e = transpose ? j * S + i : i * S + j;
+          const double* ce = cf + (size_t)e * Q * 2;
+          T sr = (T)0, si = (T)0;
+          for (int q = 0; q < Q; ++q) {
+            const T cr = (T)ce[2 * q], ci = (T)ce[2 * q + 1];
+            sr += cr * hr[q] - ci * hi[q];
+            si += cr * hi[q] + ci * hr[q];
+          }
+          const int mu = dmc[e];
+          const T pr = er[mu < 0 ? -mu : mu], pi = mu < 0 ? -ei[-mu] : ei[mu];
+          const T mr = sr * pr - si * pi, mi = sr * pi + si * pr;
+          const cplx<T> v = xs[j];
+          ar += mr * v.re - mi * v.im;
+          ai += mr * v.im + mi * v.re;
+        }
+        yr[i] += ar;
+        yi[i] += ai;
+      }
+    }
+  }
+  if (!live) return;
+  cplx<T>* out = partial + (((size_t)blockIdx.z * gridDim.y + rc) * N + t) * S;
+  for (int i = 0; i < S; ++i) out[i] = cplx<T>{yr[i], yi[i]};
+}
+
+// y = x - t * z (Forward), x - z (Adjoint, z from t x), or z, z = sum of the
+// chunks' partials in chunk order.
+template <typename T>
+__global__ void offlattice_combine_kernel(const cplx<T>* __restrict__ partial, int nchunk,
+                                          long long total, const c128* __restrict__ x,
+                                          const c128* __restrict__ t, long long vec,
+                                          c128* __restrict__ y, int mode) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  double sr = 0.0, si = 0.0;
+  for (int q = 0; q < nchunk; ++q) {
+    const cplx<T> v = partial[(size_t)q * total + e];
+    sr += (double)v.re;
+    si += (double)v.im;
+  }
+  c128 o;
+  if (mode == (int)Op::Forward) {
+    const c128 tv = t[e % vec], xv = x[e];
+    o = c128{xv.re - (tv.re * sr - tv.im * si), xv.im - (tv.re * si + tv.im * sr)};
+  } else if (mode == (int)Op::Adjoint) {
+    const c128 xv = x[e];
+    o = c128{xv.re - sr, xv.im - si};
+  } else {
+    o = c128{sr, si};
+  }
+  y[e] = o;
+}
+
+template <typename T>
+int offlattice_apply(tm_ctx* c, Op op, int R, const void* xin, const c128* x, c128* y) {
+  const Geometry& g = c->g;
+  const int N = g.n, S = g.S;
+  const int nh = g.L / 2;
+  const long long total = g.vec_len() * R;
+  // enough workgroups to fill the chip: target blocks x (rhs, class) x chunks
+  const int tb = (N + OL_THREADS - 1) / OL_THREADS;
+  int nchunk = std::max(1, std::min((N + OL_GROUP - 1) / OL_GROUP, 2048 / std::max(1, tb * 2 * R)));
+  const int chunk = (N + nchunk - 1) / nchunk;
+  nchunk = (N + chunk - 1) / chunk;
+  int rc;
+  if ((rc = ensure(c, c->partial, (size_t)nchunk * total * sizeof(cplx<T>))) != TM_OK) return rc;
+  const size_t cb = (size_t)NCLASS * S * S * (2 * g.lmax + 1) * 2 * sizeof(double);
+  const double* coef = (const double*)c->olc.p;
+  const int* dm = (const int*)((const char*)c->olc.p + cb);
+  const size_t lds = 2 * OL_GROUP * sizeof(double) + (size_t)OL_GROUP * S * sizeof(cplx<T>);
+  const bool tr = (op == Op::Adjoint || op == Op::CouplingT);
+  hipLaunchKernelGGL(offlattice_kernel<T>, dim3(tb, 2 * R, nchunk), dim3(OL_THREADS), lds, c->stream,
+                     (const double*)c->xy.p, (const cplx<T>*)xin, coef, dm, N, S, nh, g.lmax, g.k, chunk,
+                     tr ? 1 : 0, (cplx<T>*)c->partial.p);
+  hipLaunchKernelGGL(offlattice_combine_kernel<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
+                     c->stream, (const cplx<T>*)c->partial.p, nchunk, total, x, (const c128*)c->t64.p,
+                     g.vec_len(), y, (int)op);
+  TM_HIP(c, hipGetLastError());
+  return TM_OK;
+}
+template int offlattice_apply<float>(tm_ctx*, Op, int, const void*, const c128*, c128*);
+template int offlattice_apply<double>(tm_ctx*, Op, int, const void*, const c128*, c128*);
+
+}  // namespace tmh

@@ -491,6 +491,23 @@ static int build_impl(tm_ctx* c, DevBuf& t64, DevBuf& t32, int transpose) {
 
 int build_tables(tm_ctx* c) { return build_impl(c, c->tab64, c->tab32, 0); }
 
+// Off-lattice geometries: no displacement tables; the on-the-fly matvec reads
+// the per-entry constants coef [2][S][S][Q] (complex, Pbar_q(0) folded in: every
+// scatterer lies in z = 0) and dm [2][S][S] from one device buffer.
+int build_offlattice_constants(tm_ctx* c) {
+  const Geometry& g = c->g;
+  std::vector<double> coef;
+  std::vector<int> dm, sig;
+  const int Q = 2 * g.lmax + 1;
+  host_table_constants(g, Q, coef, dm, sig);
+  const size_t cb = coef.size() * sizeof(double), db = dm.size() * sizeof(int);
+  int rc;
+  if ((rc = ensure(c, c->olc, cb + db)) != TM_OK) return rc;
+  TM_HIP(c, hipMemcpy(c->olc.p, coef.data(), cb, hipMemcpyHostToDevice));
+  TM_HIP(c, hipMemcpy((char*)c->olc.p + cb, dm.data(), db, hipMemcpyHostToDevice));
+  return TM_OK;
+}
+
 int build_transposed_tables(tm_ctx* c) {
   int rc = build_impl(c, c->tabT64, c->tabT32, 1);
   if (rc == TM_OK) c->have_tabT = true;

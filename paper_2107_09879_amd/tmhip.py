@@ -114,6 +114,8 @@ def load():
         "tm_apply_operator_noalloc": (I, [P, I, P, P, I, I]),
         "tm_grad_position": (I, [P, I, P, P, P, P, P, P, P]),
         "tm_jinc_rhs": (I, [P, I, P, I, P]),
+        "tm_set_cylinders": (I, [P, P, D, D, D, I]),
+        "tm_ebcm_cylinder": (I, [I, D, D, D, D, D, I, P]),
         "tm_jinc_rhs_batched": (I, [P, I, P, I, I, P, P, I, P]),
         "tm_solve_batched_a0": (I, [P, I, P, I, P, P, P, P, I]),
         "tm_near_field": (I, [P, I, P, I, P, P, I]),
@@ -141,6 +143,19 @@ def load():
         fn.argtypes = args
     _lib = lib
     return lib
+
+
+def ebcm_cylinder(lmax, k, radius, height, n_rel, n_quad=0):
+    """T [L, L] (host) of one cylinder from tm_ebcm_cylinder."""
+    lib = load()
+    L = 2 * lmax * (lmax + 2)
+    T = np.zeros((L, L), dtype=np.complex128)
+    n = complex(n_rel)
+    rc = lib.tm_ebcm_cylinder(int(lmax), float(k), float(radius), float(height), n.real, n.imag,
+                              int(n_quad), T.ctypes.data_as(ctypes.c_void_p))
+    if rc != TM_OK:
+        raise TmError(rc, "tm_ebcm_cylinder failed")
+    return T
 
 
 def mie(lmax, k, radius, n_rel):
@@ -289,6 +304,13 @@ class Context:
         r = _dev(radii, torch.float64, "radii", self.device, (self.n,))
         n_rel = complex(n_rel)
         self._check(self.lib.tm_set_spheres(self.h, _ptr(r), n_rel.real, n_rel.imag))
+
+    def set_cylinders(self, radii, height, n_rel, n_quad=0):
+        """tm_set_cylinders: null-field T-matrices of cylinders (radii device [N])."""
+        (radii,) = _devs(self.device, (radii, torch.float64, "radii", (self.n,), None))
+        n = complex(n_rel)
+        self._check(self.lib.tm_set_cylinders(self.h, _ptr(radii), float(height), n.real, n.imag,
+                                              int(n_quad)))
 
     def set_tmatrix_diag(self, t):
         t = _dev(t, torch.complex128, "t", self.device, (self.n, self.L))

@@ -350,9 +350,10 @@ def test_gradient_vs_oracle_adjoint():
 def test_error_paths():
     ctx = tmhip.Context(0)
     pos = wl.lattice_positions(4, 4)
+    # a centre off the z = 0 plane is outside the method's planar layout
     with pytest.raises(tmhip.TmError) as e:
         bad = pos.copy()
-        bad[5, 0] += 0.01
+        bad[5, 2] += 0.01
         ctx.set_geometry(bad, K, 3)
     assert e.value.code == -3
     ctx.set_geometry(pos, K, 3)
