@@ -88,6 +88,33 @@ def measured_traffic(kernels, workload):
     return sum(rows[k] for k in kernels)
 
 
+NF_SOURCE = "paper_2107_09879_amd/csrc/tm_basis.hip"
+# FP32 VALU issue peak: 0.5 wave64 instructions per SIMD per cycle on 1024
+# SIMDs at 2.4 GHz, in lane-instructions per second (FMA = one instruction)
+PEAK_VALU_LANE_INSTR = 1024 * 0.5 * 64 * 2.4e9
+
+
+def nf_valu_per_pair(kernel):
+    """VALU lane-instructions per (point, sphere) pair of the near-field kernel
+    from the committed counter summary, or None if the source changed since."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "near_field_c5_300x300_plane1000x1000.md")
+    if not os.path.exists(path):
+        return None
+    with open(os.path.join(ROOT, NF_SOURCE), "rb") as fh:
+        digest = hashlib.sha256(fh.read()).hexdigest()[:16]
+    with open(path) as f:
+        for line in f:
+            cells = [c.strip() for c in line.strip().strip("|").split("|")]
+            if len(cells) == 3 and cells[0] == kernel and cells[1] == digest:
+                try:
+                    return float(cells[2])
+                except ValueError:
+                    return None
+    return None
+
+
 def copy_calibration(torch, mib=512):
     """A plain copy of known size for the HBM counters: y = x * 1 over
     `mib` MiB of float32 reads `mib` MiB and writes `mib` MiB."""
@@ -419,10 +446,20 @@ def near_field_plane(ctx, s, cfg):
     ev1.record()
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1)
-    pairs = pts.shape[0] * ctx.n * s.shape[0]
-    log(f"[bench] near field {n_side}x{n_side}: {ms:.1f} ms, {pairs / ms / 1e6:.3g} G pair-rhs/s")
+    R = s.shape[0]
+    pairs = pts.shape[0] * ctx.n * R
+    kernel = f"near_field_v2<float, {ctx.lmax}, {R}>"
+    ipp = nf_valu_per_pair(kernel)
+    roof = None
+    if ipp is not None:
+        achieved = pts.shape[0] * ctx.n * ipp / (ms * 1e-3)
+        roof = {"bound": "alu", "kernel": kernel, "valu_lane_instr_per_pair": ipp,
+                "achieved": achieved / 1e12, "peak": PEAK_VALU_LANE_INSTR / 1e12,
+                "unit": "T VALU lane-instructions/s", "frac": achieved / PEAK_VALU_LANE_INSTR}
+    log(f"[bench] near field {n_side}x{n_side}: {ms:.1f} ms, {pairs / ms / 1e6:.3g} G pair-rhs/s, "
+        f"VALU issue {roof['frac'] if roof else None}")
     return {"points": pts.shape[0], "ms": ms, "pair_rhs_per_s": pairs / ms * 1e3,
-            "max_abs": float(E.abs().max())}
+            "max_abs": float(E.abs().max()), "roofline": roof}
 
 
 def bench_batched(args):

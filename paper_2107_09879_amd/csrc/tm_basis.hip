@@ -326,75 +326,135 @@ __device__ inline void hankel_set(T x, T c, T s, int lmax, cx<T>* h) {
 
 constexpr int NF_MAXR = 4;
 
+// Phase and distance of one (point, sphere) pair for the near field: kr in
+// FP64 (|kr| reaches 1e3..1e4 across a metasurface), its reduction modulo 2 pi,
+// and 1/r in the basis precision.  The FP32 basis takes 1/sqrt(r^2) from the
+// hardware reciprocal square root, refines r = r^2 / sqrt(r^2) by one FP64
+// Newton step (relative error ~1e-14), and evaluates the sine and cosine of
+// the reduced phase on the hardware units, whose argument is in revolutions.
+template <typename T>
+struct NfPhase;
+
+template <>
+struct NfPhase<float> {
+  static __device__ inline void eval(double r2, double k, float& sn, float& cs, float& x, float& irr) {
+    const float y = __builtin_amdgcn_rsqf((float)r2);
+    const double r0 = r2 * (double)y;
+    const double rr = fma(0.5 * (double)y, fma(-r0, r0, r2), r0);
+    const double t = (k * rr) * 0.15915494309189533576888376337251;  // revolutions
+    const float fr = (float)(t - rint(t));
+    sn = __builtin_amdgcn_sinf(fr);
+    cs = __builtin_amdgcn_cosf(fr);
+    x = (float)(k * rr);
+    irr = y;
+  }
+  static __device__ inline float rsqrt_pos(float v) { return __builtin_amdgcn_rsqf(v); }
+  static __device__ inline float rcp(float v) { return __builtin_amdgcn_rcpf(v); }
+};
+
+template <>
+struct NfPhase<double> {
+  static __device__ inline void eval(double r2, double k, double& sn, double& cs, double& x, double& irr) {
+    const double rr = sqrt(r2);
+    const double kr = k * rr;
+    const double twopi = 6.283185307179586476925286766559;
+    const double red = kr - twopi * rint(kr * 0.15915494309189533576888376337251);
+    sincos(red, &sn, &cs);
+    x = kr;
+    irr = 1.0 / rr;
+  }
+  static __device__ inline double rsqrt_pos(double v) { return 1.0 / sqrt(v); }
+  static __device__ inline double rcp(double v) { return 1.0 / v; }
+};
+
 // Near field with compile-time lmax and RHS count (all basis values in
 // registers).  Each workgroup stages the coefficients of CH spheres at a time
 // in LDS (every thread reads the same entries: broadcast) and each thread
-// accumulates the field of one point.  The +-m terms of one (l, |m|) share
-// P, U, tau and conj(e^{i|m|phi}), so they are folded:
-//   sMe = s_M(+m) e + s_M(-m) e*,  dMe = s_M(+m) e - s_M(-m) e*  (same for N),
-//   E_r += c_l P sNe,  E_th += i|m| U a_l dMe + tau b_l sNe,
-//   E_ph += -tau a_l sMe + i|m| U b_l dNe,
-// with a_l = h_l/sqrt(2l(l+1)), b_l = (x h_{l-1} - l h_l)/x /sqrt(2l(l+1)),
-// c_l = l(l+1) h_l/x /sqrt(2l(l+1)).  Distances and k r are formed in FP64
-// (k r reduced modulo 2 pi before the FP32 sine/cosine).
+// accumulates the field of one point.
+//
+// The +-m terms of one (l, |m|) share P, U, tau and conj(e^{i|m|phi}), so
+// they are folded.  With s(+m) = a + ib, s(-m) = a' + ib' and
+// e = e^{i|m|phi} = c + id,
+//   sMe = s(+m) e + s(-m) e* = (c A+ - d B-) + i (c B+ + d A-),
+//   dMe = s(+m) e - s(-m) e* = (c A- - d B+) + i (c B- + d A+),
+// A+- = a +- a', B+- = b +- b'; the four sums are formed once per sphere when
+// the coefficients are staged (likewise sNe, dNe from the N-type pair).
+// Staging also multiplies in the real constants sqrt((2l+1)/2 (l-m)!/(l+m)!)
+// and 1/sqrt(2l(l+1)).  The l-dependent radial factors come out of the sum
+// over |m|:
+//   E_r  += c_l sum_m P sNe,
+//   E_th += i a_l sum_m U dMe + b_l sum_m tau sNe,
+//   E_ph += -a_l sum_m tau sMe + i b_l sum_m U dNe,
+// with a_l = h_l, b_l = (x h_{l-1} - l h_l)/x, c_l = l(l+1) h_l/x,
+// P = sin u_l^m, U = |m| u_l^m, tau = l cos u_l^m - (l+|m|) u_{l-1}^m for
+// |m| >= 1 (u = P_l^m / sin), P = P_l^0 and tau = -sin u_l^1 for m = 0.
+// Staged layout per (sphere, RHS), in reals: for l = 1..LMAX at offset
+// 4 (l^2 - 1): m = 0 as [M.re, M.im, N.re, N.im], then for |m| = 1..l
+// [M: A+, A-, B+, B-][N: A+, A-, B+, B-].
 template <typename T, int LMAX, int R>
 __global__ __launch_bounds__(256) void near_field_v2(
     const tm_c128* __restrict__ s, int N, SitePos sp, double k,
     const double* __restrict__ pts, int P, tm_c128* __restrict__ E) {
   constexpr int L = 2 * LMAX * (LMAX + 2), H = LMAX * (LMAX + 2);
+  constexpr int NF = 2 * L;                     // staged reals per (sphere, RHS)
+  constexpr int NU = LMAX * (LMAX + 3) / 2;     // (l, |m|) units per (sphere, RHS)
   // spheres staged per LDS chunk: at most 48 KB of coefficients
   constexpr int CHN = (LMAX <= 3) ? 32 : 8;
-  __shared__ cplx<T> sh[CHN][R][L];
+  __shared__ __align__(16) T sh[CHN][R][NF];
+  __shared__ __align__(16) double shp[CHN][2];  // centres of the staged spheres
   const int ip = blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = ip < P;
   const double px = live ? pts[3 * ip] : 0.0, py = live ? pts[3 * ip + 1] : 0.0,
                pz = live ? pts[3 * ip + 2] : 1.0;
+  const T invk = (T)(1.0 / k);
   cx<T> acc[R][3];
-  const double twopi = 6.283185307179586476925286766559;
-  // normalisation constants sqrt((2l+1)/2 (l-m)!/(l+m)!)
-  T nlm[LMAX + 1][LMAX + 1];
-#pragma unroll
-  for (int l = 0; l <= LMAX; ++l)
-#pragma unroll
-    for (int am = 0; am <= LMAX; ++am) {
-      double v = (2.0 * l + 1.0) / 2.0;
-      for (int q = l - am + 1; q <= l + am; ++q) v /= (double)q;
-      nlm[l][am] = (T)sqrt(v);
-    }
   for (int i0 = 0; i0 < N; i0 += CHN) {
     const int nch = min(CHN, N - i0);
     __syncthreads();
-    for (int q = threadIdx.x; q < nch * R * L; q += blockDim.x) {
-      const int n = q % L, rr = (q / L) % R, ii = q / (L * R);
-      const tm_c128 v = s[((size_t)rr * N + (i0 + ii)) * L + n];
-      sh[ii][rr][n] = cplx<T>{(T)v.re, (T)v.im};
+    if (threadIdx.x < nch) sp.at(i0 + threadIdx.x, shp[threadIdx.x][0], shp[threadIdx.x][1]);
+    for (int q = threadIdx.x; q < nch * R * NU; q += blockDim.x) {
+      const int u = q % NU, rr = (q / NU) % R, ii = q / (NU * R);
+      int l = 1;
+      while ((l + 1) * (l + 2) / 2 - 1 <= u) ++l;  // units before l: (l-1)(l+2)/2
+      const int am = u - (l - 1) * (l + 2) / 2;
+      double v = (2.0 * l + 1.0) / 2.0;
+      for (int f = l - am + 1; f <= l + am; ++f) v /= (double)f;
+      const double w = sqrt(v / (2.0 * l * (l + 1)));
+      const tm_c128* si = s + ((size_t)rr * N + (i0 + ii)) * L;
+      T* dst = &sh[ii][rr][4 * (l * l - 1) + (am == 0 ? 0 : 8 * am - 4)];
+      const int np = l * (l + 1) - 1 + am, nm = l * (l + 1) - 1 - am;
+      if (am == 0) {
+        dst[0] = (T)(w * si[np].re);
+        dst[1] = (T)(w * si[np].im);
+        dst[2] = (T)(w * si[H + np].re);
+        dst[3] = (T)(w * si[H + np].im);
+      } else {
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          const tm_c128 a = si[t * H + np], b = si[t * H + nm];
+          dst[4 * t + 0] = (T)(w * (a.re + b.re));
+          dst[4 * t + 1] = (T)(w * (a.re - b.re));
+          dst[4 * t + 2] = (T)(w * (a.im + b.im));
+          dst[4 * t + 3] = (T)(w * (a.im - b.im));
+        }
+      }
     }
     __syncthreads();
     for (int ii = 0; ii < nch; ++ii) {
-      const int i = i0 + ii;
-      double sx_, sy_;
-      sp.at(i, sx_, sy_);
-      const double dx = px - sx_;
-      const double dy = py - sy_;
+      const double dx = px - shp[ii][0];
+      const double dy = py - shp[ii][1];
       const double dz = pz;
       const double rho2 = dx * dx + dy * dy;
-      const double r2 = rho2 + dz * dz;
-      const double rr = sqrt(r2);
-      const double kr = k * rr;
-      const double red = kr - twopi * rint(kr / twopi);
-      T sn, cs;
-      sincos_t((T)red, &sn, &cs);
-      const T x = (T)kr;
-      const T ix = (T)1 / x;
-      const T irr = (T)(1.0 / rr);
+      T sn, cs, x, irr;
+      NfPhase<T>::eval(rho2 + dz * dz, k, sn, cs, x, irr);
+      const T ix = irr * invk;
       const T ct = (T)dz * irr;
-      const T rho = (T)sqrt(rho2);
-      const T st = rho * irr;
-      T cf = 1, sf = 0;
+      T cf = 1, sf = 0, st = 0;
       if (rho2 > 0.0) {
-        const T ir = (T)1 / rho;
+        const T ir = NfPhase<T>::rsqrt_pos((T)rho2);
         cf = (T)dx * ir;
         sf = (T)dy * ir;
+        st = ((T)rho2 * ir) * irr;
       }
       // Hankel h_0..h_LMAX
       cx<T> h[LMAX + 1];
@@ -418,15 +478,15 @@ __global__ __launch_bounds__(256) void near_field_v2(
         u[am][am] = um;
 #pragma unroll
         for (int l = am + 1; l <= LMAX; ++l)
-          u[l][am] = ((T)(2 * l - 1) * ct * u[l - 1][am] - (T)(l + am - 1) * (l - 2 >= am ? u[l - 2][am] : (T)0)) /
-                     (T)(l - am);
+          u[l][am] = ((T)(2 * l - 1) * ct * u[l - 1][am] - (T)(l + am - 1) * (l - 2 >= am ? u[l - 2][am] : (T)0)) *
+                     (T)(1.0 / (l - am));
       }
       T p0[LMAX + 1];
       p0[0] = 1;
       if (LMAX >= 1) p0[1] = ct;
 #pragma unroll
       for (int l = 2; l <= LMAX; ++l)
-        p0[l] = ((T)(2 * l - 1) * ct * p0[l - 1] - (T)(l - 1) * p0[l - 2]) / (T)l;
+        p0[l] = ((T)(2 * l - 1) * ct * p0[l - 1] - (T)(l - 1) * p0[l - 2]) * (T)(1.0 / l);
       cx<T> e[LMAX + 1];
       e[0] = cx<T>(1, 0);
 #pragma unroll
@@ -434,44 +494,47 @@ __global__ __launch_bounds__(256) void near_field_v2(
       cx<T> Er[R], Et[R], Ep[R];
 #pragma unroll
       for (int l = 1; l <= LMAX; ++l) {
-        const T nrm = (T)1 / sqrt((T)(2 * l * (l + 1)));
-        const cx<T> al = nrm * h[l];
-        const cx<T> bl = nrm * cx<T>((x * h[l - 1].re - (T)l * h[l].re) * ix, (x * h[l - 1].im - (T)l * h[l].im) * ix);
-        const cx<T> cl = (nrm * (T)(l * (l + 1)) * ix) * h[l];
+        const cx<T> al = h[l];
+        const cx<T> bl = cx<T>((x * h[l - 1].re - (T)l * h[l].re) * ix, (x * h[l - 1].im - (T)l * h[l].im) * ix);
+        const cx<T> cl = ((T)(l * (l + 1)) * ix) * h[l];
+        cx<T> X[R], Y1[R], Y2[R], Z1[R], Z2[R];
 #pragma unroll
         for (int am = 0; am <= l; ++am) {
-          T Pb, Ub, tau;
+          const int off = 4 * (l * l - 1) + (am == 0 ? 0 : 8 * am - 4);
           if (am == 0) {
-            Pb = nlm[l][0] * p0[l];
-            Ub = 0;
-            tau = -nlm[l][0] * st * u[l][1];
-          } else {
-            Pb = nlm[l][am] * st * u[l][am];
-            Ub = nlm[l][am] * (T)am * u[l][am];
-            tau = nlm[l][am] * ((T)l * ct * u[l][am] - (T)(l + am) * u[l - 1][am]);
-          }
-          const int np = l * (l + 1) - 1 + am, nm = l * (l + 1) - 1 - am;
+            const T Pb = p0[l], tau = -st * u[l][1];
 #pragma unroll
-          for (int r = 0; r < R; ++r) {
-            cx<T> sMe, dMe, sNe, dNe;
-            if (am == 0) {
-              sMe = cx<T>(sh[ii][r][np].re, sh[ii][r][np].im);
-              sNe = cx<T>(sh[ii][r][H + np].re, sh[ii][r][H + np].im);
-            } else {
-              const cx<T> ep = e[am], em = cx<T>(e[am].re, -e[am].im);
-              const cx<T> a1 = cx<T>(sh[ii][r][np].re, sh[ii][r][np].im) * ep;
-              const cx<T> a2 = cx<T>(sh[ii][r][nm].re, sh[ii][r][nm].im) * em;
-              const cx<T> b1 = cx<T>(sh[ii][r][H + np].re, sh[ii][r][H + np].im) * ep;
-              const cx<T> b2 = cx<T>(sh[ii][r][H + nm].re, sh[ii][r][H + nm].im) * em;
-              sMe = a1 + a2;
-              dMe = a1 - a2;
-              sNe = b1 + b2;
-              dNe = b1 - b2;
+            for (int r = 0; r < R; ++r) {
+              const T* c = &sh[ii][r][off];
+              const cx<T> sM(c[0], c[1]), sN(c[2], c[3]);
+              X[r] = X[r] + Pb * sN;
+              Y2[r] = Y2[r] + tau * sN;
+              Z1[r] = Z1[r] + tau * sM;
             }
-            Er[r] = Er[r] + Pb * (cl * sNe);
-            Et[r] = Et[r] + mul_i(Ub * (al * dMe)) + tau * (bl * sNe);
-            Ep[r] = Ep[r] - tau * (al * sMe) + mul_i(Ub * (bl * dNe));
+          } else {
+            const T Pb = st * u[l][am], Ub = (T)am * u[l][am];
+            const T tau = (T)l * ct * u[l][am] - (T)(l + am) * u[l - 1][am];
+            const T c = e[am].re, d = e[am].im;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+              const T* g = &sh[ii][r][off];
+              const cx<T> sMe(c * g[0] - d * g[3], c * g[2] + d * g[1]);
+              const cx<T> dMe(c * g[1] - d * g[2], c * g[3] + d * g[0]);
+              const cx<T> sNe(c * g[4] - d * g[7], c * g[6] + d * g[5]);
+              const cx<T> dNe(c * g[5] - d * g[6], c * g[7] + d * g[4]);
+              X[r] = X[r] + Pb * sNe;
+              Y1[r] = Y1[r] + Ub * dMe;
+              Y2[r] = Y2[r] + tau * sNe;
+              Z1[r] = Z1[r] + tau * sMe;
+              Z2[r] = Z2[r] + Ub * dNe;
+            }
           }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          Er[r] = Er[r] + cl * X[r];
+          Et[r] = Et[r] + mul_i(al * Y1[r]) + bl * Y2[r];
+          Ep[r] = Ep[r] - al * Z1[r] + mul_i(bl * Z2[r]);
         }
       }
 #pragma unroll
