@@ -532,7 +532,7 @@ static int autotune_impl(tm_ctx* c, int R, double* best_ms) {
   TM_HIP(c, hipMemsetAsync(c->xlow.p, 0, (size_t)total * sizeof(cplx<T>), c->stream));
   // workgroup counts (items x 2R); smaller equal-work items keep every CU
   // busy to the end of the launch, at the price of more partial sums
-  const int wg_targets[] = {2048, 4096, 8192, 16384, 32768};
+  const int wg_targets[] = {4096, 8192, 16384, 32768, 65536};
   hipEvent_t e0, e1;
   TM_HIP(c, hipEventCreate(&e0));
   TM_HIP(c, hipEventCreate(&e1));

@@ -133,7 +133,18 @@ struct LdsCfg {
   static constexpr int THT = WIDE ? 4 : 16;        // tile height in sites
   static constexpr int WX = TWT - 1 + BX, WY = THT - 1 + BY;
   static constexpr int CH = LdsT<T>::CH;
-  static constexpr int CHUNKS = WX * WY * CH;
+  // FP32 regular tiles use a padded layout instead of the XOR swizzle, so
+  // that the address of a lane's B operand is affine in the displacement (one
+  // add per step): a site takes SS = 9 chunks (8 of data) and a window row RP
+  // chunks with RP = 4 (mod 16).  The reads of a 4x4 patch then cost some
+  // LDS bank conflicts (about 4 cycles per read on gfx950); a conflict-free
+  // padding (10 chunks per site) needs 8x6 displacement blocks to fit two
+  // workgroups per CU and measured slower, the extra windows costing more
+  // than the conflicts.
+  static constexpr bool PAD = std::is_same<T, float>::value && !WIDE;
+  static constexpr int SS = PAD ? CH + 1 : CH;
+  static constexpr int RP = PAD ? ((WX * SS + 11) / 16) * 16 + 4 : WX * CH;
+  static constexpr int CHUNKS = WY * RP;
   static constexpr size_t BYTES = (size_t)CHUNKS * 16;
 };
 
@@ -192,6 +203,9 @@ __global__ __launch_bounds__(256, 2) void block_matvec_lds_kernel(LdsArgs a) {
   const int wdylo = gy0 - (ny - 1), wdyhi = min(gy0 + 3, ny - 1);
   const int wdxlo = gxw - (nx - 1), wdxhi = min(gxw + TW - 1, nx - 1);
   const bool wave_live = gy0 < ny && gxw < nx;
+  // padded layout: chunk of this lane's B operand (group 0, K-chunk kq) at the
+  // block's first displacement (bx0, by0)
+  const int lane_b0 = ((ty - Y0) + BY - 1) * Cfg::RP + (wxo + lx + BX - 1) * Cfg::SS + kq;
 
   acc_t t1[GX], t2[GX], t3[GX];
 #pragma unroll
@@ -210,15 +224,40 @@ __global__ __launch_bounds__(256, 2) void block_matvec_lds_kernel(LdsArgs a) {
     // window origin: source site of target (X0, Y0) at displacement (bx0+BX-1, by0+BY-1)
     const int wx0 = X0 - (bx0 + BX - 1), wy0 = Y0 - (by0 + BY - 1);
     __syncthreads();  // every wave is done with the previous window
-    for (int q = threadIdx.x; q < Cfg::CHUNKS; q += 256) {
-      const int h = q % CH;
-      const int site = q / CH;
-      const int wx = site % WX, wy = site / WX;
-      const int gx = wx0 + wx, gy = wy0 + wy;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (gx >= 0 && gx < nx && gy >= 0 && gy < ny)
-        v = *reinterpret_cast<const float4*>(xin + ((size_t)gy * nx + gx) * S + h * (SLOTS / CH));
-      win[site * CH + L::swz(h, wx, wy)] = v;
+    // window fill in batches of FB chunks per thread: all loads of a batch
+    // are in flight together, then all its LDS stores.  Thread t fills chunk
+    // h = t % CH of sites t / CH, t / CH + 256 / CH, ... (256 % CH == 0).
+    {
+      constexpr int SST = 256 / CH, DWX = SST % WX, DWY = SST / WX;
+      constexpr int PER = (WX * WY * CH + 255) / 256, FB = PER < 8 ? PER : 8;
+      const int h = threadIdx.x % CH;
+      int wx = (threadIdx.x / CH) % WX, wy = (threadIdx.x / CH) / WX;
+#pragma unroll 1
+      for (int q0 = 0; q0 < PER; q0 += FB) {
+        float4 v[FB];
+        int dst[FB];
+#pragma unroll
+        for (int j = 0; j < FB; ++j) {
+          const int gx = wx0 + wx, gy = wy0 + wy;
+          const int chunk = Cfg::PAD ? wy * Cfg::RP + wx * Cfg::SS + h : (wy * WX + wx) * CH + L::swz(h, wx, wy);
+          dst[j] = (q0 + j < PER && wy < WY) ? chunk : -1;
+          // sources outside the lattice read the (valid) first chunk and are
+          // replaced by zeros: no branch around the load
+          const bool in = dst[j] >= 0 && (unsigned)gx < (unsigned)nx && (unsigned)gy < (unsigned)ny;
+          const size_t site_off = in ? (size_t)gy * nx + gx : 0;
+          const float4 t = *reinterpret_cast<const float4*>(xin + site_off * S + h * (SLOTS / CH));
+          v[j] = in ? t : make_float4(0.f, 0.f, 0.f, 0.f);
+          wx += DWX;
+          wy += DWY;
+          if (wx >= WX) {
+            wx -= WX;
+            ++wy;
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < FB; ++j)
+          if (dst[j] >= 0) win[dst[j]] = v[j];
+      }
     }
     __syncthreads();
     if (!wave_live) continue;
@@ -248,11 +287,23 @@ __global__ __launch_bounds__(256, 2) void block_matvec_lds_kernel(LdsArgs a) {
              boff;
     };
     auto read_all_b = [&](int x, int y, T (*r_)[4], T (*i_)[4]) {
-      const int wy = (ty - Y0) - (y - by0) + BY - 1;
+      if constexpr (Cfg::PAD) {
+        // chunk of (group 0, K-chunk kq): lane part minus a wave-uniform part
+        const int off = lane_b0 - ((x - bx0) * Cfg::SS + (y - by0) * Cfg::RP);
 #pragma unroll
-      for (int g = 0; g < GX; ++g) {
-        const int wx = wxo + 4 * g + lx - (x - bx0) + BX - 1;
-        read_b(win, (wy * WX + wx) * CH, wx, wy, kq, r_[g], i_[g]);
+        for (int g = 0; g < GX; ++g) {
+          const float4 p = win[off + 4 * Cfg::SS * g];
+          const float4 q = win[off + 4 * Cfg::SS * g + 4];
+          r_[g][0] = p.x; i_[g][0] = p.y; r_[g][1] = p.z; i_[g][1] = p.w;
+          r_[g][2] = q.x; i_[g][2] = q.y; r_[g][3] = q.z; i_[g][3] = q.w;
+        }
+      } else {
+        const int wy = (ty - Y0) - (y - by0) + BY - 1;
+#pragma unroll
+        for (int g = 0; g < GX; ++g) {
+          const int wx = wxo + 4 * g + lx - (x - bx0) + BX - 1;
+          read_b(win, (wy * WX + wx) * CH, wx, wy, kq, r_[g], i_[g]);
+        }
       }
     };
     // The fetch positions stop at the block's last displacement, so fetches
@@ -279,10 +330,7 @@ __global__ __launch_bounds__(256, 2) void block_matvec_lds_kernel(LdsArgs a) {
       T ms[4];
 #pragma unroll
       for (int s = 0; s < 4; ++s) ms[s] = ar[K][s] + ai[K][s];
-#pragma unroll
-      for (int g = 0; g < GX; ++g) {
-        const int gx0 = gxw + 4 * g;
-        if (gx0 >= nx || gx0 + 3 - cdx < 0 || gx0 - cdx >= nx) continue;  // wave-uniform
+      auto group = [&](int g) {
         T xs[4];
 #pragma unroll
         for (int s = 0; s < 4; ++s) xs[s] = br[K][g][s] + bi[K][g][s];
@@ -292,7 +340,20 @@ __global__ __launch_bounds__(256, 2) void block_matvec_lds_kernel(LdsArgs a) {
           t2[g] = L::mma(ai[K][s], bi[K][g][s], t2[g]);
           t3[g] = L::mma(ms[s], xs[s], t3[g]);
         }
+      };
+      // group g of the wave has sources at this displacement iff its columns
+      // are in the lattice and gx0 - nx < cdx <= gx0 + 3: a wave-uniform bit
+      // mask, kept in a scalar register
+      // (sign bits of the three differences, integer ops only)
+      int gmask = 0;
+#pragma unroll
+      for (int g = 0; g < GX; ++g) {
+        const int gx0 = gxw + 4 * g;
+        gmask |= (((cdx - gx0 - 4) & (gx0 - cdx - nx) & (gx0 - nx)) >> 31) & (1 << g);
       }
+#pragma unroll
+      for (int g = 0; g < GX; ++g)
+        if (gmask & (1 << g)) group(g);
       advance(cdx, cdy);
     };
     using I0 = std::integral_constant<int, 0>;
@@ -433,8 +494,8 @@ void lds_split(const std::vector<std::vector<double>>& wb, double per, int sub,
 
 // Items of one lattice: regular tiles first, then wide tiles (tile indices
 // continue), so the two launches take contiguous item ranges.
-static void lds_plan(const Geometry& g, const LdsTiling& tl, int BX, int BY, int win_cost, int target,
-                     std::vector<LdsItem>& items, std::vector<int>& ibeg) {
+static void lds_plan(const Geometry& g, const LdsTiling& tl, int BX, int BY, int WBX, int WBY,
+                     int win_cost, int target, std::vector<LdsItem>& items, std::vector<int>& ibeg) {
   std::vector<std::vector<double>> wb((size_t)tl.n_reg + tl.n_wide);
   double total = 0.0;
   for (int t = 0; t < tl.n_reg; ++t)
@@ -442,7 +503,7 @@ static void lds_plan(const Geometry& g, const LdsTiling& tl, int BX, int BY, int
                              BX, BY, win_cost, wb[t]);
   for (int t = 0; t < tl.n_wide; ++t)
     total += tile_block_work(g.nx, g.ny, (t % tl.tiles_xw) * 4 * tl.TW, tl.y_wide + (t / tl.tiles_xw) * 4,
-                             true, tl.TW, BX, BY, win_cost, wb[(size_t)tl.n_reg + t]);
+                             true, tl.TW, WBX, WBY, win_cost, wb[(size_t)tl.n_reg + t]);
   items.clear();
   ibeg.clear();
   lds_split(wb, total / std::max(1, target), 0, items, ibeg);
@@ -518,23 +579,30 @@ __global__ void lds_combine_kernel(const cplx<T>* __restrict__ partial, const in
   y[idx] = o;
 }
 
-// Configurations: FP32 16x16 tile with 16x4 displacement blocks (75 KB of
-// LDS, two workgroups per CU); FP64 8x16 tile with 8x4 blocks (73 KB).
+// Configurations (two workgroups per CU): FP32 16x16 tile with 8x8
+// displacement blocks in the padded layout (78 KB of LDS), its 64x4 wide
+// tiles with 16x4 blocks (71 KB); FP64 8x16 tile with 8x4 blocks (73 KB),
+// wide tiles alike.
 template <typename T>
 struct LdsChoice;
 template <>
 struct LdsChoice<float> {
-  static constexpr int GX = 4, BX = 16, BY = 4;
+  static constexpr int GX = 4, BX = 8, BY = 8, WBX = 16, WBY = 4;
 };
 template <>
 struct LdsChoice<double> {
-  static constexpr int GX = 2, BX = 8, BY = 4;
+  static constexpr int GX = 2, BX = 8, BY = 4, WBX = 8, WBY = 4;
 };
+static_assert(LdsCfg<float, 4, 8, 8, false>::BYTES <= 80 * 1024, "two FP32 workgroups per CU");
+static_assert(LdsCfg<float, 4, 16, 4, true>::BYTES <= 80 * 1024, "two FP32 workgroups per CU");
+static_assert(LdsCfg<double, 2, 8, 4, false>::BYTES <= 80 * 1024, "two FP64 workgroups per CU");
+static_assert(LdsCfg<double, 2, 8, 4, true>::BYTES <= 80 * 1024, "two FP64 workgroups per CU");
 
 template <typename T, int PF, bool WIDE>
 static void lds_launch_pf(hipStream_t st, int nitems, int R, const LdsArgs& a) {
   using Ch = LdsChoice<T>;
-  hipLaunchKernelGGL((block_matvec_lds_kernel<T, Ch::GX, Ch::BX, Ch::BY, PF, WIDE>),
+  constexpr int BX = WIDE ? Ch::WBX : Ch::BX, BY = WIDE ? Ch::WBY : Ch::BY;
+  hipLaunchKernelGGL((block_matvec_lds_kernel<T, Ch::GX, BX, BY, PF, WIDE>),
                      dim3(nitems, 2 * R * a.NG), dim3(256), 0, st, a);
 }
 // FP64 stages are twice as wide: depth 3 does not fit two waves' registers,
@@ -565,7 +633,7 @@ int lds_apply(tm_ctx* c, int which, int R, const void* table, const void* xin, c
   if (c->plan_kind[which] != 2 || c->plan_R[which] != R || c->plan_target[which] != items_target) {
     std::vector<LdsItem> items;
     std::vector<int> ibeg;
-    lds_plan(g, tl, Ch::BX, Ch::BY, 64, items_target, items, ibeg);
+    lds_plan(g, tl, Ch::BX, Ch::BY, Ch::WBX, Ch::WBY, 64, items_target, items, ibeg);
     c->plan_nreg[which] = ibeg[tl.n_reg];
     if ((rc = ensure(c, c->plan_items[which], items.size() * sizeof(LdsItem))) != TM_OK) return rc;
     if ((rc = ensure(c, c->plan_ibeg[which], ibeg.size() * sizeof(int))) != TM_OK) return rc;
@@ -665,22 +733,26 @@ __global__ void lds_uniform_plan_kernel(LdsItem* __restrict__ items, int* __rest
   }
   if (idx >= ntile * ipt) return;
   const int t = idx / ipt, k = idx % ipt;
-  int X0, Y0, TWT, THT;
+  int X0, Y0, TWT, THT, BX, BY;
   if (t < tl.n_reg) {
     X0 = (t % tl.tiles_x) * tl.TW;
     Y0 = (t / tl.tiles_x) * 16;
     TWT = tl.TW;
     THT = 16;
+    BX = Ch::BX;
+    BY = Ch::BY;
   } else {
     const int w = t - tl.n_reg;
     X0 = (w % tl.tiles_xw) * 4 * tl.TW;
     Y0 = tl.y_wide + (w / tl.tiles_xw) * 4;
     TWT = 4 * tl.TW;
     THT = 4;
+    BX = Ch::WBX;
+    BY = Ch::WBY;
   }
   const int dxlo = X0 - (nx - 1), dxhi = min(X0 + TWT - 1, nx - 1);
   const int dylo = Y0 - (ny - 1), dyhi = min(Y0 + THT - 1, ny - 1);
-  const int nb = ((dxhi - dxlo + Ch::BX) / Ch::BX) * ((dyhi - dylo + Ch::BY) / Ch::BY);
+  const int nb = ((dxhi - dxlo + BX) / BX) * ((dyhi - dylo + BY) / BY);
   const int chunk = (nb + ipt - 1) / ipt;
   const int b0 = min(nb, k * chunk), b1 = min(nb, b0 + chunk);
   items[idx] = LdsItem{t, b0, b1, 0};
