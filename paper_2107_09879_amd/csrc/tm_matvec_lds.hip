@@ -223,47 +223,9 @@ __global__ __launch_bounds__(256, 2) void block_matvec_lds_kernel(LdsArgs a) {
     const int by0 = dylo + (b / nbx) * BY;
     // window origin: source site of target (X0, Y0) at displacement (bx0+BX-1, by0+BY-1)
     const int wx0 = X0 - (bx0 + BX - 1), wy0 = Y0 - (by0 + BY - 1);
-    __syncthreads();  // every wave is done with the previous window
-    // window fill in batches of FB chunks per thread: all loads of a batch
-    // are in flight together, then all its LDS stores.  Thread t fills chunk
-    // h = t % CH of sites t / CH, t / CH + 256 / CH, ... (256 % CH == 0).
-    {
-      constexpr int SST = 256 / CH, DWX = SST % WX, DWY = SST / WX;
-      constexpr int PER = (WX * WY * CH + 255) / 256, FB = PER < 8 ? PER : 8;
-      const int h = threadIdx.x % CH;
-      int wx = (threadIdx.x / CH) % WX, wy = (threadIdx.x / CH) / WX;
-#pragma unroll 1
-      for (int q0 = 0; q0 < PER; q0 += FB) {
-        float4 v[FB];
-        int dst[FB];
-#pragma unroll
-        for (int j = 0; j < FB; ++j) {
-          const int gx = wx0 + wx, gy = wy0 + wy;
-          const int chunk = Cfg::PAD ? wy * Cfg::RP + wx * Cfg::SS + h : (wy * WX + wx) * CH + L::swz(h, wx, wy);
-          dst[j] = (q0 + j < PER && wy < WY) ? chunk : -1;
-          // sources outside the lattice read the (valid) first chunk and are
-          // replaced by zeros: no branch around the load
-          const bool in = dst[j] >= 0 && (unsigned)gx < (unsigned)nx && (unsigned)gy < (unsigned)ny;
-          const size_t site_off = in ? (size_t)gy * nx + gx : 0;
-          const float4 t = *reinterpret_cast<const float4*>(xin + site_off * S + h * (SLOTS / CH));
-          v[j] = in ? t : make_float4(0.f, 0.f, 0.f, 0.f);
-          wx += DWX;
-          wy += DWY;
-          if (wx >= WX) {
-            wx -= WX;
-            ++wy;
-          }
-        }
-#pragma unroll
-        for (int j = 0; j < FB; ++j)
-          if (dst[j] >= 0) win[dst[j]] = v[j];
-      }
-    }
-    __syncthreads();
-    if (!wave_live) continue;
     const int dyb = max(by0, max(dylo, wdylo)), dye = min(by0 + BY - 1, min(dyhi, wdyhi));
     const int dxb = max(bx0, max(dxlo, wdxlo)), dxe = min(bx0 + BX - 1, min(dxhi, wdxhi));
-    if (dyb > dye || dxb > dxe) continue;
+    const bool has_work = wave_live && dyb <= dye && dxb <= dxe;  // wave-uniform
     const int ndx = dxe - dxb + 1;
     const int nq = (dye - dyb + 1) * ndx;
     // Operand pipeline, unrolled by U = PF + 1 so that every stage owns its
@@ -313,11 +275,53 @@ __global__ __launch_bounds__(256, 2) void block_matvec_lds_kernel(LdsArgs a) {
       if (x != dxe || y != dye) advance(x, y);
     };
     int adx = dxb, ady = dyb, bdx = dxb, bdy = dyb, cdx = dxb, cdy = dyb;
+    // the first translation blocks are fetched before the window fill, so
+    // that their latency overlaps the fill's
+    if (has_work) {
 #pragma unroll
-    for (int p = 0; p < PF; ++p) {
-      load_a(table_block(adx, ady), S, jt, kq, ar[p], ai[p]);
-      advance_fetch(adx, ady);
+      for (int p = 0; p < PF; ++p) {
+        load_a(table_block(adx, ady), S, jt, kq, ar[p], ai[p]);
+        advance_fetch(adx, ady);
+      }
     }
+    __syncthreads();  // every wave is done with the previous window
+    // window fill in batches of FB chunks per thread: all loads of a batch
+    // are in flight together, then all its LDS stores.  Thread t fills chunk
+    // h = t % CH of sites t / CH, t / CH + 256 / CH, ... (256 % CH == 0).
+    {
+      constexpr int SST = 256 / CH, DWX = SST % WX, DWY = SST / WX;
+      constexpr int PER = (WX * WY * CH + 255) / 256, FB = (PER + 1) / 2;
+      const int h = threadIdx.x % CH;
+      int wx = (threadIdx.x / CH) % WX, wy = (threadIdx.x / CH) / WX;
+#pragma unroll 1
+      for (int q0 = 0; q0 < PER; q0 += FB) {
+        float4 v[FB];
+        int dst[FB];
+#pragma unroll
+        for (int j = 0; j < FB; ++j) {
+          const int gx = wx0 + wx, gy = wy0 + wy;
+          const int chunk = Cfg::PAD ? wy * Cfg::RP + wx * Cfg::SS + h : (wy * WX + wx) * CH + L::swz(h, wx, wy);
+          dst[j] = (q0 + j < PER && wy < WY) ? chunk : -1;
+          // sources outside the lattice read the (valid) first chunk and are
+          // replaced by zeros: no branch around the load
+          const bool in = dst[j] >= 0 && (unsigned)gx < (unsigned)nx && (unsigned)gy < (unsigned)ny;
+          const size_t site_off = in ? (size_t)gy * nx + gx : 0;
+          const float4 t = *reinterpret_cast<const float4*>(xin + site_off * S + h * (SLOTS / CH));
+          v[j] = in ? t : make_float4(0.f, 0.f, 0.f, 0.f);
+          wx += DWX;
+          wy += DWY;
+          if (wx >= WX) {
+            wx -= WX;
+            ++wy;
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < FB; ++j)
+          if (dst[j] >= 0) win[dst[j]] = v[j];
+      }
+    }
+    __syncthreads();
+    if (!has_work) continue;
     read_all_b(bdx, bdy, br[0], bi[0]);
     advance_fetch(bdx, bdy);
     // step q of the block, with q % U == K known at compile time
