@@ -131,7 +131,10 @@ struct LdsCfg {
   static constexpr int TW = 4 * GX;                // columns per wave
   static constexpr int TWT = WIDE ? 4 * TW : TW;   // tile width in sites
   static constexpr int THT = WIDE ? 4 : 16;        // tile height in sites
-  static constexpr int WX = TWT - 1 + BX, WY = THT - 1 + BY;
+  // every wave reads the same 4 source rows per displacement row (wave w of
+  // a regular tile takes its displacements shifted by 4w rows), so a window
+  // is 4 - 1 + BY rows high for both tile shapes
+  static constexpr int WX = TWT - 1 + BX, WY = 4 - 1 + BY;
   static constexpr int CH = LdsT<T>::CH;
   // FP32 regular tiles use a padded layout instead of the XOR swizzle, so
   // that the address of a lane's B operand is affine in the displacement (one
@@ -188,24 +191,30 @@ __global__ __launch_bounds__(256, 2) void block_matvec_lds_kernel(LdsArgs a) {
   const int X0 = (tl % tiles_x) * TWT;
   const int Y0 = a.y_base + (tl / tiles_x) * THT;
   const int wxo = WIDE ? TW * wave : 0;  // this wave's column and row offsets in the tile
-  const int gy0 = Y0 + (WIDE ? 0 : 4 * wave);
+  const int wyo = WIDE ? 0 : 4 * wave;
+  const int gy0 = Y0 + wyo;
   const int gxw = X0 + wxo;
   const int ty = gy0 + ly;
   const C* __restrict__ xin0 =
       reinterpret_cast<const C*>(a.x) + voff + ((size_t)r * NCLASS + c) * N * S;
   const C* __restrict__ tab = reinterpret_cast<const C*>(a.table);
   const int wxt = 2 * a.tnx - 1;
-  // the tile's displacement range and its block grid
+  // The tile's displacement range and its block grid.  Rows are counted
+  // relative to each wave: at relative row y, the wave with rows gy0..gy0+3
+  // applies the displacement row y + (gy0 - Y0), so that all waves read
+  // source rows Y0 - y .. Y0 + 3 - y of one shared window and have the same
+  // number of steps (waves of a tile cut by the lattice edge excepted).
   const int dxlo = X0 - (nx - 1), dxhi = min(X0 + TWT - 1, nx - 1);
-  const int dylo = Y0 - (ny - 1), dyhi = min(Y0 + THT - 1, ny - 1);
+  const int dylo = Y0 - (ny - 1), dyhi = min(Y0 + 3, ny - 1);
   const int nbx = (dxhi - dxlo + BX) / BX;
-  // this wave's valid displacements (its rows and columns must reach a source)
-  const int wdylo = gy0 - (ny - 1), wdyhi = min(gy0 + 3, ny - 1);
+  // this wave's valid displacements (its rows and columns must reach a
+  // source), rows relative
+  const int wdylo = dylo, wdyhi = min(Y0 + 3, ny - 1 - wyo);
   const int wdxlo = gxw - (nx - 1), wdxhi = min(gxw + TW - 1, nx - 1);
   const bool wave_live = gy0 < ny && gxw < nx;
   // padded layout: chunk of this lane's B operand (group 0, K-chunk kq) at the
   // block's first displacement (bx0, by0)
-  const int lane_b0 = ((ty - Y0) + BY - 1) * Cfg::RP + (wxo + lx + BX - 1) * Cfg::SS + kq;
+  const int lane_b0 = (ly + BY - 1) * Cfg::RP + (wxo + lx + BX - 1) * Cfg::SS + kq;
 
   acc_t t1[GX], t2[GX], t3[GX];
 #pragma unroll
@@ -238,14 +247,14 @@ __global__ __launch_bounds__(256, 2) void block_matvec_lds_kernel(LdsArgs a) {
     constexpr int U = PF + 1;
     T ar[U][4], ai[U][4];
     T br[U][GX][4], bi[U][GX][4];
+    // (selects, not branches: positions are wave-uniform scalars)
     auto advance = [&](int& x, int& y) {
-      if (++x > dxe) {
-        x = dxb;
-        ++y;
-      }
+      const int wrap = x == dxe;
+      x = wrap ? dxb : x + 1;
+      y += wrap;
     };
     auto table_block = [&](int x, int y) {
-      return tab + (((size_t)(y + a.tny - 1) * wxt + (x + a.tnx - 1)) * NCLASS + c) * (size_t)(S * S) +
+      return tab + (((size_t)(y + wyo + a.tny - 1) * wxt + (x + a.tnx - 1)) * NCLASS + c) * (size_t)(S * S) +
              boff;
     };
     auto read_all_b = [&](int x, int y, T (*r_)[4], T (*i_)[4]) {
@@ -260,7 +269,7 @@ __global__ __launch_bounds__(256, 2) void block_matvec_lds_kernel(LdsArgs a) {
           r_[g][2] = q.x; i_[g][2] = q.y; r_[g][3] = q.z; i_[g][3] = q.w;
         }
       } else {
-        const int wy = (ty - Y0) - (y - by0) + BY - 1;
+        const int wy = ly - (y - by0) + BY - 1;
 #pragma unroll
         for (int g = 0; g < GX; ++g) {
           const int wx = wxo + 4 * g + lx - (x - bx0) + BX - 1;
@@ -272,7 +281,9 @@ __global__ __launch_bounds__(256, 2) void block_matvec_lds_kernel(LdsArgs a) {
     // past the end re-read valid data: every fetch is unconditional and the
     // compiler waits for exactly the operands a step consumes.
     auto advance_fetch = [&](int& x, int& y) {
-      if (x != dxe || y != dye) advance(x, y);
+      const int wrap = x == dxe, stop = wrap & (y == dye);
+      x = stop ? x : (wrap ? dxb : x + 1);
+      y += wrap & !stop;
     };
     int adx = dxb, ady = dyb, bdx = dxb, bdy = dyb, cdx = dxb, cdy = dyb;
     // the first translation blocks are fetched before the window fill, so
@@ -405,9 +416,10 @@ __global__ __launch_bounds__(256, 2) void block_matvec_lds_kernel(LdsArgs a) {
 static double tile_block_work(int nx, int ny, int X0, int Y0, bool wide, int TW, int BX, int BY,
                               int win_cost, std::vector<double>& wb) {
   const int GX = TW / 4;
-  const int TWT = wide ? 4 * TW : TW, THT = wide ? 4 : 16;
+  const int TWT = wide ? 4 * TW : TW;
+  // displacement rows relative to each wave's first row (as in the kernel)
   const int dxlo = X0 - (nx - 1), dxhi = std::min(X0 + TWT - 1, nx - 1);
-  const int dylo = Y0 - (ny - 1), dyhi = std::min(Y0 + THT - 1, ny - 1);
+  const int dylo = Y0 - (ny - 1), dyhi = std::min(Y0 + 3, ny - 1);
   const int nbx = (dxhi - dxlo + BX) / BX, nby = (dyhi - dylo + BY) / BY;
   wb.assign((size_t)nbx * nby, 0.0);
   int gyw[4], gxw[4];
@@ -422,8 +434,8 @@ static double tile_block_work(int nx, int ny, int X0, int Y0, bool wide, int TW,
     for (int wv = 0; wv < 4; ++wv) {
       const int gy0 = gyw[wv], gx = gxw[wv];
       if (gy0 >= ny || gx >= nx) continue;
-      const int yb = std::max(by0, std::max(dylo, gy0 - (ny - 1)));
-      const int ye = std::min(by0 + BY - 1, std::min(dyhi, std::min(gy0 + 3, ny - 1)));
+      const int yb = std::max(by0, dylo);
+      const int ye = std::min(by0 + BY - 1, std::min(Y0 + 3, ny - 1 - (gy0 - Y0)));
       const int xb = std::max(bx0, std::max(dxlo, gx - (nx - 1)));
       const int xe = std::min(bx0 + BX - 1, std::min(dxhi, std::min(gx + TW - 1, nx - 1)));
       if (yb > ye || xb > xe) continue;
@@ -583,23 +595,28 @@ __global__ void lds_combine_kernel(const cplx<T>* __restrict__ partial, const in
   y[idx] = o;
 }
 
-// Configurations (two workgroups per CU): FP32 16x16 tile with 8x8
-// displacement blocks in the padded layout (78 KB of LDS), its 64x4 wide
-// tiles with 16x4 blocks (71 KB); FP64 8x16 tile with 8x4 blocks (73 KB),
-// wide tiles alike.
+// Configurations (two workgroups per CU): FP32 16x16 tile with 16x8
+// displacement blocks in the padded layout (51 KB of LDS), its 64x4 wide
+// tiles with 16x4 blocks (71 KB); FP64 8x16 tile with 8x16 blocks (73 KB),
+// its 32x4 wide tiles with 8x4 blocks (70 KB).
+#ifndef TM_LDS_F32_BX
+#define TM_LDS_F32_BX 16
+#define TM_LDS_F32_BY 8
+#endif
 template <typename T>
 struct LdsChoice;
 template <>
 struct LdsChoice<float> {
-  static constexpr int GX = 4, BX = 8, BY = 8, WBX = 16, WBY = 4;
+  static constexpr int GX = 4, BX = TM_LDS_F32_BX, BY = TM_LDS_F32_BY, WBX = 16, WBY = 4;
 };
 template <>
 struct LdsChoice<double> {
-  static constexpr int GX = 2, BX = 8, BY = 4, WBX = 8, WBY = 4;
+  static constexpr int GX = 2, BX = 8, BY = 16, WBX = 8, WBY = 4;
 };
-static_assert(LdsCfg<float, 4, 8, 8, false>::BYTES <= 80 * 1024, "two FP32 workgroups per CU");
+static_assert(LdsCfg<float, 4, LdsChoice<float>::BX, LdsChoice<float>::BY, false>::BYTES <= 80 * 1024,
+              "two FP32 workgroups per CU");
 static_assert(LdsCfg<float, 4, 16, 4, true>::BYTES <= 80 * 1024, "two FP32 workgroups per CU");
-static_assert(LdsCfg<double, 2, 8, 4, false>::BYTES <= 80 * 1024, "two FP64 workgroups per CU");
+static_assert(LdsCfg<double, 2, 8, 16, false>::BYTES <= 80 * 1024, "two FP64 workgroups per CU");
 static_assert(LdsCfg<double, 2, 8, 4, true>::BYTES <= 80 * 1024, "two FP64 workgroups per CU");
 
 template <typename T, int PF, bool WIDE>
@@ -737,12 +754,11 @@ __global__ void lds_uniform_plan_kernel(LdsItem* __restrict__ items, int* __rest
   }
   if (idx >= ntile * ipt) return;
   const int t = idx / ipt, k = idx % ipt;
-  int X0, Y0, TWT, THT, BX, BY;
+  int X0, Y0, TWT, BX, BY;
   if (t < tl.n_reg) {
     X0 = (t % tl.tiles_x) * tl.TW;
     Y0 = (t / tl.tiles_x) * 16;
     TWT = tl.TW;
-    THT = 16;
     BX = Ch::BX;
     BY = Ch::BY;
   } else {
@@ -750,12 +766,11 @@ __global__ void lds_uniform_plan_kernel(LdsItem* __restrict__ items, int* __rest
     X0 = (w % tl.tiles_xw) * 4 * tl.TW;
     Y0 = tl.y_wide + (w / tl.tiles_xw) * 4;
     TWT = 4 * tl.TW;
-    THT = 4;
     BX = Ch::WBX;
     BY = Ch::WBY;
   }
   const int dxlo = X0 - (nx - 1), dxhi = min(X0 + TWT - 1, nx - 1);
-  const int dylo = Y0 - (ny - 1), dyhi = min(Y0 + THT - 1, ny - 1);
+  const int dylo = Y0 - (ny - 1), dyhi = min(Y0 + 3, ny - 1);  // rows relative per wave
   const int nb = ((dxhi - dxlo + BX) / BX) * ((dyhi - dylo + BY) / BY);
   const int chunk = (nb + ipt - 1) / ipt;
   const int b0 = min(nb, k * chunk), b1 = min(nb, b0 + chunk);
