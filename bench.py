@@ -39,11 +39,14 @@ def kernel_names(variant, ctype):
     """Names of the kernels one block matvec of a variant launches (as the
     profiler prints them, template arguments included)."""
     if variant >= 8:
-        gx, bx, by = (4, 16, 4) if ctype == "float" else (2, 8, 4)
+        # (columns groups per wave, displacement block) of the regular and the
+        # wide tiles
+        gx, reg, wide = (4, (16, 8), (16, 4)) if ctype == "float" else (2, (8, 16), (8, 4))
         pf = variant - 7 if ctype == "float" else min(variant - 7, 2)
         # regular tiles, then the wide-tile instance for the rows past the
         # last multiple of 16 (absent when the height is a multiple of 16)
-        return [f"block_matvec_lds_kernel<{ctype}, {gx}, {bx}, {by}, {pf}, {w}>" for w in ("false", "true")]
+        return [f"block_matvec_lds_kernel<{ctype}, {gx}, {b[0]}, {b[1]}, {pf}, {w}>"
+                for b, w in ((reg, "false"), (wide, "true"))]
     gauss, pref, occ = variant & 1, (variant >> 1) & 1, 4 if variant & 4 else 2
     return [f"block_matvec_kernel<{ctype}, {str(bool(gauss)).lower()}, {str(bool(pref)).lower()}, {occ}>"]
 

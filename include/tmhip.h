@@ -408,10 +408,10 @@ int tm_set_matvec_config(tm_ctx* ctx, int precision, int variant, int items);
 int tm_get_matvec_config(tm_ctx* ctx, int precision, int* variant, int* items);
 
 /* Time the LDS-staged variants (8..10; FP64: 8, 9) with a few work-item
- * counts (2k..32k workgroups) on the current geometry for n_rhs right-hand
+ * counts (4k..64k workgroups) on the current geometry for n_rhs right-hand
  * sides and keep the fastest for `precision`.  Synchronises; best_ms (host,
  * nullable) receives the best block-matvec time.  Without a call, FP64 uses
- * variant 9 and complex64 variant 10 with the default work split. */
+ * variant 9 and complex64 variant 8 with the default work split. */
 int tm_autotune(tm_ctx* ctx, int n_rhs, int precision, double* best_ms);
 
 /* ---- progress ------------------------------------------------------------- */

@@ -146,7 +146,7 @@ struct tm_ctx {
   // matvec launch configuration per precision slot (0 = FP64, 1 = complex64):
   // kernel variant, target work items per (rhs, class), and the cached plan
   // default: the LDS-staged kernels (FP64 prefetch depth 2, complex64 depth 3)
-  int mv_variant[2] = {9, 10};
+  int mv_variant[2] = {9, 8};
   int mv_items[2] = {0, 0};
   tmh::DevBuf plan_items[2], plan_ibeg[2];
   // the cached plan of a precision slot is reused only for the same kernel

@@ -603,19 +603,24 @@ __global__ void lds_combine_kernel(const cplx<T>* __restrict__ partial, const in
 #define TM_LDS_F32_BX 16
 #define TM_LDS_F32_BY 8
 #endif
+#ifndef TM_LDS_F32_GX
+#define TM_LDS_F32_GX 4
+#endif
 template <typename T>
 struct LdsChoice;
 template <>
 struct LdsChoice<float> {
-  static constexpr int GX = 4, BX = TM_LDS_F32_BX, BY = TM_LDS_F32_BY, WBX = 16, WBY = 4;
+  static constexpr int GX = TM_LDS_F32_GX, BX = TM_LDS_F32_BX, BY = TM_LDS_F32_BY, WBX = 16, WBY = 4;
 };
 template <>
 struct LdsChoice<double> {
   static constexpr int GX = 2, BX = 8, BY = 16, WBX = 8, WBY = 4;
 };
-static_assert(LdsCfg<float, 4, LdsChoice<float>::BX, LdsChoice<float>::BY, false>::BYTES <= 80 * 1024,
+static_assert(LdsCfg<float, LdsChoice<float>::GX, LdsChoice<float>::BX, LdsChoice<float>::BY,
+                     false>::BYTES <= 80 * 1024,
               "two FP32 workgroups per CU");
-static_assert(LdsCfg<float, 4, 16, 4, true>::BYTES <= 80 * 1024, "two FP32 workgroups per CU");
+static_assert(LdsCfg<float, LdsChoice<float>::GX, 16, 4, true>::BYTES <= 80 * 1024,
+              "two FP32 workgroups per CU");
 static_assert(LdsCfg<double, 2, 8, 16, false>::BYTES <= 80 * 1024, "two FP64 workgroups per CU");
 static_assert(LdsCfg<double, 2, 8, 4, true>::BYTES <= 80 * 1024, "two FP64 workgroups per CU");
 

@@ -100,7 +100,7 @@ static int apply_noalloc(tm_ctx* c, int R, const tm_c128* x, tm_c128* y, int op,
                           ? (transposed ? c->tabT64.p : c->tab64.p)
                           : (transposed ? c->tabT32.p : c->tab32.p);
   // the context's LDS prefetch depth (variants 8..10), else the default
-  int pf = c->mv_variant[which] >= 8 ? c->mv_variant[which] - 7 : (which == 0 ? 2 : 3);
+  int pf = c->mv_variant[which] >= 8 ? c->mv_variant[which] - 7 : (which == 0 ? 2 : 1);
   int rc = lds_apply_fixed<T>(c, R, table, xin, xa, yb, op, pf, ipt, rest);
   if (rc != TM_OK) return rc;
   unpack_slots(c->stream, g, c->maps, R, yb, y);

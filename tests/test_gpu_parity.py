@@ -471,8 +471,8 @@ def test_batched_subregions_match_single_solves(precision, use_graph, autotune):
         assert 1 <= pf <= (3 if precision == "mixed" else 2)
         assert items in [wg // (2 * R) for wg in (16384, 32768, 65536)]
     else:
-        # the context's default kernels: FP64 table prefetch depth 2, complex64 depth 3
-        assert (pf, items) == (3 if precision == "mixed" else 2, 32768 // (2 * R))
+        # the context's default kernels: FP64 table prefetch depth 2, complex64 depth 1
+        assert (pf, items) == (1 if precision == "mixed" else 2, 32768 // (2 * R))
     for k, (ox, oy, sx, sy) in enumerate(SUBS):
         ix, iy = np.meshgrid(np.arange(ox, ox + sx), np.arange(oy, oy + sy))
         idx = (iy * nx + ix).ravel()
