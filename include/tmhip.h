@@ -261,7 +261,11 @@ typedef struct {
  * Geometry (the full lattice) and T must be set.  subs: host [S];
  * s_out: device, the subregions' [R][N_k][L] coefficient blocks concatenated
  * in subregion order (site index within a subregion ly*side_x + lx);
- * info: host [S][R].  opts->use_x0 must be 0.  1 <= n_rhs <= 8. */
+ * info: host [S][R].  opts->use_x0 must be 0.  1 <= n_rhs <= 8.
+ * A system whose right-hand side or residual is not finite leaves the batch
+ * with info status TM_ERR_NAN (its coefficients unspecified) while the
+ * others go on; the call then returns TM_NOT_CONVERGED, as when any system
+ * stops at max_iter. */
 int tm_solve_batched(tm_ctx* ctx, int n_sub, const tm_subregion* subs, int n_rhs,
                      const double* khat, const tm_c128* pol, tm_c128* s_out,
                      const tm_solve_opts* opts, tm_solve_info* info, int use_graph);

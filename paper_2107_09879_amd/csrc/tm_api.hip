@@ -1,8 +1,10 @@
 // C ABI of libtmhip: context, set-up, restarted GMRES drivers, readout and
-// sensitivities.  The GMRES loop runs on the host; every vector operation,
-// reduction and matvec is a HIP kernel on the context stream.  Per Arnoldi
-// step the host reads back one Hessenberg column (j+2 complex values) to
-// apply the Givens rotations and test convergence.
+// sensitivities.  The host enqueues whole GMRES cycles; every vector
+// operation, reduction, matvec, Givens rotation and the least-squares solve
+// is a HIP kernel on the context stream.  Per cycle the host reads back one
+// record (the true residual norm, the number of Arnoldi steps taken, a
+// non-finite flag): the steps of a cycle after its convergence test fired
+// on the device return at once.
 //
 // Solver (App. I.D: matrix-free matvecs inside GMRES; the preconditioned
 // system of App. I.C):
@@ -154,91 +156,95 @@ static int gmres(tm_ctx* c, Op op, const c128* b, c128* x, const tm_solve_opts& 
     TM_HIP(c, hipMemsetAsync(x, 0, len * sizeof(c128), st));
     k_copy(st, G.r, b, len);
   }
-  std::vector<std::complex<double>> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), y(m);
-  auto Hij = [&](int i, int j) -> std::complex<double>& { return H[(size_t)i * m + j]; };
+  if ((rc = ensure(c, c->gm_dev, gm_state_bytes(m))) != TM_OK) return rc;
+  void* gs = c->gm_dev.p;
+  const int* stop = &static_cast<const GmFlags*>(gs)->stop;
+  // the matvecs of apply_op skip their work once the cycle has stopped;
+  // cleared on every way out of this function
+  struct StopGuard {
+    tm_ctx* c;
+    ~StopGuard() { c->mv_stop = nullptr; }
+  } guard{c};
+  const int which_prof = (o.precision == TM_PREC_MIXED) ? 1 : 0;
   int it = 0;
   double relres = 0.0;
   const int prec = o.precision;
+  double beta = dev_norm(G, G.r);
   for (;;) {
-    const double beta = dev_norm(G, G.r);
     relres = beta / bnorm;
     if (!std::isfinite(beta)) return set_err(c, TM_ERR_NAN, "residual became non-finite");
     if (relres <= o.tol || it >= o.max_iter) break;
     if (c->progress) c->progress(c->progress_user, info.cycles, it, 1, relres);
     info.cycles++;
     k_scale(st, G.V, G.r, 1.0 / beta, len);
-    std::fill(gv.begin(), gv.end(), 0.0);
-    gv[0] = beta;
+    k_gm_cycle_init(st, gs, m, G.nout);  // G.nout holds beta
     const double target =
         (prec == TM_PREC_MIXED) ? std::max(o.tol * bnorm, o.inner_tol * beta) : o.tol * bnorm;
-    int jend = 0;
-    for (int j = 0; j < m; ++j) {
+    const int jmax = std::min(m, o.max_iter - it);
+    c->mv_stop = stop;
+    int launched = 0;
+    for (int j = 0; j < jmax; ++j) {
+      ++launched;
       c128* vj = G.V + (size_t)j * len;
       if ((rc = apply_op(c, op, prec, 1, vj, G.w)) != TM_OK) return rc;
-      if (prec == TM_PREC_MIXED) info.matvecs_lowp++;
-      else info.matvecs_fp64++;
       // CGS2: h1 = V^H w, w -= V h1, h2 = V^H w, w -= V h2, H(:,j) = h1 + h2
-      k_multidot(st, G.V, len, j + 1, G.w, len, G.dp, nblk);
-      k_reduce_dots(st, G.dp, nblk, j + 1, G.dots, nullptr);
-      k_update(st, G.w, G.V, len, j + 1, G.dots, len, -1.0);
-      k_multidot(st, G.V, len, j + 1, G.w, len, G.dp, nblk);
-      k_reduce_dots(st, G.dp, nblk, j + 1, G.dots2, nullptr);
-      k_update(st, G.w, G.V, len, j + 1, G.dots2, len, -1.0);
-      k_norm2_partial(st, G.w, len, G.np, nblk);
-      k_reduce_norm(st, G.np, nblk, G.nout);
-      const size_t hb = (size_t)(j + 1) * sizeof(c128);
-      TM_HIP(c, hipMemcpyAsync(c->host_pinned, G.dots, hb, hipMemcpyDeviceToHost, st));
-      TM_HIP(c, hipMemcpyAsync((char*)c->host_pinned + hb, G.dots2, hb, hipMemcpyDeviceToHost, st));
-      TM_HIP(c, hipMemcpyAsync((char*)c->host_pinned + 2 * hb, G.nout, sizeof(double),
-                               hipMemcpyDeviceToHost, st));
-      TM_HIP(c, hipStreamSynchronize(st));
-      const c128* hh = (const c128*)c->host_pinned;
-      const c128* hh2 = hh + (j + 1);
-      double hn;
-      std::memcpy(&hn, (const char*)c->host_pinned + 2 * hb, sizeof(double));
-      for (int i = 0; i <= j; ++i)
-        Hij(i, j) = std::complex<double>(hh[i].re + hh2[i].re, hh[i].im + hh2[i].im);
-      Hij(j + 1, j) = hn;
-      if (!std::isfinite(hn)) return set_err(c, TM_ERR_NAN, "Arnoldi produced a non-finite value");
-      if (hn > 0.0) k_scale(st, G.V + (size_t)(j + 1) * len, G.w, 1.0 / hn, len);
-      for (int i = 0; i < j; ++i) {
-        const std::complex<double> t = std::conj(cs[i]) * Hij(i, j) + std::conj(sn[i]) * Hij(i + 1, j);
-        Hij(i + 1, j) = -sn[i] * Hij(i, j) + cs[i] * Hij(i + 1, j);
-        Hij(i, j) = t;
+      k_multidot(st, G.V, len, j + 1, G.w, len, G.dp, nblk, stop);
+      k_reduce_dots(st, G.dp, nblk, j + 1, G.dots, nullptr, stop);
+      k_update(st, G.w, G.V, len, j + 1, G.dots, len, -1.0, stop);
+      k_multidot(st, G.V, len, j + 1, G.w, len, G.dp, nblk, stop);
+      k_reduce_dots(st, G.dp, nblk, j + 1, G.dots2, nullptr, stop);
+      k_update(st, G.w, G.V, len, j + 1, G.dots2, len, -1.0, stop);
+      k_norm2_partial(st, G.w, len, G.np, nblk, stop);
+      k_reduce_norm(st, G.np, nblk, G.nout, stop);
+      k_gm_givens(st, gs, m, j, G.dots, G.dots2, G.nout, target);
+      k_gm_scale_next(st, G.V + (size_t)(j + 1) * len, G.w, gs, len);
+      // with a progress callback, a long cycle also reports every 50 steps
+      // (one readback of the flags there; a cycle already stopped ends here)
+      if (c->progress && (j + 1) % 50 == 0 && j + 1 < jmax) {
+        TM_HIP(c, hipMemcpyAsync(c->host_pinned, gs, sizeof(GmFlags), hipMemcpyDeviceToHost, st));
+        TM_HIP(c, hipStreamSynchronize(st));
+        GmFlags fl;
+        std::memcpy(&fl, c->host_pinned, sizeof(GmFlags));
+        if (fl.stop) break;
+        c->progress(c->progress_user, info.cycles - 1, it + fl.jend, 1, fl.est / bnorm);
       }
-      const double den = std::hypot(std::abs(Hij(j, j)), std::abs(Hij(j + 1, j)));
-      if (den == 0.0) {
-        cs[j] = 1.0;
-        sn[j] = 0.0;
-      } else {
-        cs[j] = Hij(j, j) / den;
-        sn[j] = Hij(j + 1, j) / den;
-      }
-      Hij(j, j) = den;
-      Hij(j + 1, j) = 0.0;
-      gv[j + 1] = -sn[j] * gv[j];
-      gv[j] = std::conj(cs[j]) * gv[j];
-      ++it;
-      jend = j + 1;
-      if (std::abs(gv[j + 1]) <= target || it >= o.max_iter || hn == 0.0) break;
-      // long cycles also report every 50 steps, with the Givens estimate
-      if (c->progress && (j + 1) % 50 == 0 && j + 1 < m)
-        c->progress(c->progress_user, info.cycles - 1, it, 1, std::abs(gv[j + 1]) / bnorm);
     }
-    // back substitution H y = g
-    for (int i = jend - 1; i >= 0; --i) {
-      std::complex<double> s = gv[i];
-      for (int q = i + 1; q < jend; ++q) s -= Hij(i, q) * y[q];
-      y[i] = (Hij(i, i) != 0.0) ? s / Hij(i, i) : 0.0;
-    }
-    std::memcpy(c->host_pinned, y.data(), (size_t)jend * sizeof(c128));
-    TM_HIP(c, hipMemcpyAsync(G.dots, c->host_pinned, (size_t)jend * sizeof(c128),
-                             hipMemcpyHostToDevice, st));
-    k_update(st, x, G.V, len, jend, G.dots, len, +1.0);
+    c->mv_stop = nullptr;
+    const size_t prof_mark = c->prof ? c->prof_pending[which_prof].size() : 0;
+    // y = H^-1 g on the device, x += V y (y is zero past the steps taken)
+    k_gm_backsub(st, gs, m);
+    k_gm_update_x(st, x, G.V, len, gs, m);
     // true residual in FP64
     if ((rc = apply_op(c, op, TM_PREC_FP64, 1, x, G.r)) != TM_OK) return rc;
     info.matvecs_fp64++;
     k_sub(st, G.r, b, G.r, len);
+    // the cycle's one readback: residual norm and the flags
+    k_norm2_partial(st, G.r, len, G.np, nblk);
+    k_reduce_norm(st, G.np, nblk, G.nout);
+    TM_HIP(c, hipMemcpyAsync(c->host_pinned, G.nout, sizeof(double), hipMemcpyDeviceToHost, st));
+    TM_HIP(c, hipMemcpyAsync((char*)c->host_pinned + 16, gs, sizeof(GmFlags), hipMemcpyDeviceToHost, st));
+    TM_HIP(c, hipStreamSynchronize(st));
+    GmFlags fl;
+    std::memcpy(&beta, c->host_pinned, sizeof(double));
+    std::memcpy(&fl, (const char*)c->host_pinned + 16, sizeof(GmFlags));
+    if (fl.nonfinite) return set_err(c, TM_ERR_NAN, "Arnoldi produced a non-finite value");
+    it += fl.jend;
+    if (prec == TM_PREC_MIXED) info.matvecs_lowp += fl.jend;
+    else info.matvecs_fp64 += fl.jend;
+    // matvecs launched after the convergence test fired did no work: their
+    // profile records (the last ones of the Arnoldi loop) are dropped
+    if (c->prof && fl.jend < launched) {
+      auto& pend = c->prof_pending[which_prof];
+      const size_t drop = (size_t)(launched - fl.jend);
+      const size_t mark = prof_mark;
+      if (mark >= drop && mark <= pend.size()) {
+        for (size_t k = mark - drop; k < mark; ++k) {
+          hipEventDestroy(pend[k].first);
+          hipEventDestroy(pend[k].second);
+        }
+        pend.erase(pend.begin() + (mark - drop), pend.begin() + mark);
+      }
+    }
   }
   info.iters = it;
   info.rel_residual = relres;
@@ -312,7 +318,8 @@ void tm_destroy(tm_ctx* c) {
   if (!c) return;
   hipSetDevice(c->device);
   hipStreamSynchronize(c->stream);
-  for (tmh::DevBuf* b : {&c->dtab[0], &c->dtab[1], &c->dtab[2], &c->dtab[3], &c->gpos, &c->jinc_buf})
+  for (tmh::DevBuf* b : {&c->dtab[0], &c->dtab[1], &c->dtab[2], &c->dtab[3], &c->gpos, &c->jinc_buf,
+                        &c->gm_dev})
     tmh::release(*b);
   for (tmh::DevBuf* b : {&c->tab64, &c->tab32, &c->tabT64, &c->tabT32, &c->t64, &c->t32, &c->dt64,
                         &c->tden, &c->ttmp, &c->partial, &c->xlow, &c->work_a, &c->work_b, &c->work_c, &c->basis,

@@ -900,12 +900,14 @@ static int batched_impl(tm_ctx* c, int S, const tm_subregion* subs, int R, const
     c->batch_pf[w] = (w == 0) ? std::min(B.pf[w], 2) : std::min(B.pf[w], 3);
     c->batch_items[w] = B.items_tgt[w];
   }
-  std::vector<int> live(ns, 1), iters(ns, 0), cycles(ns, 0), mv64(ns, 0), mvlo(ns, 0);
+  // a system whose right-hand side or residual turns non-finite leaves the
+  // batch with status TM_ERR_NAN; the others go on
+  std::vector<int> live(ns, 1), iters(ns, 0), cycles(ns, 0), mv64(ns, 0), mvlo(ns, 0), bad(ns, 0);
   std::vector<double> relres(ns, 0.0);
   for (int s = 0; s < ns; ++s) {
-    if (!std::isfinite(bn[s])) return set_err(c, TM_ERR_NAN, "right-hand side is not finite");
-    live[s] = bn[s] > 0.0;
-    relres[s] = live[s] ? 1.0 : 0.0;
+    bad[s] = !std::isfinite(bn[s]);
+    live[s] = !bad[s] && bn[s] > 0.0;
+    relres[s] = live[s] ? 1.0 : (bad[s] ? NAN : 0.0);
   }
   const int prec = o.precision;
   bool any_graph = false;
@@ -920,8 +922,8 @@ static int batched_impl(tm_ctx* c, int S, const tm_subregion* subs, int R, const
     for (int s = 0; s < ns; ++s) {
       if (!live[s]) continue;
       relres[s] = beta[s] / bn[s];
-      if (!std::isfinite(relres[s])) return set_err(c, TM_ERR_NAN, "residual became non-finite");
-      if (relres[s] <= o.tol || iters[s] >= o.max_iter) live[s] = 0;
+      if (!std::isfinite(relres[s])) bad[s] = 1;
+      if (bad[s] || relres[s] <= o.tol || iters[s] >= o.max_iter) live[s] = 0;
       nlive += live[s];
     }
     if (!nlive) break;
@@ -993,7 +995,7 @@ static int batched_impl(tm_ctx* c, int S, const tm_subregion* subs, int R, const
   TM_HIP(c, hipStreamSynchronize(c->stream));
   bool all_ok = true;
   for (int s = 0; s < ns; ++s) {
-    info[s].status = relres[s] <= o.tol ? TM_OK : TM_NOT_CONVERGED;
+    info[s].status = bad[s] ? TM_ERR_NAN : (relres[s] <= o.tol ? TM_OK : TM_NOT_CONVERGED);
     info[s].iters = iters[s];
     info[s].cycles = cycles[s];
     info[s].matvecs_fp64 = mv64[s];

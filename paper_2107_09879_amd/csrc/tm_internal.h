@@ -135,6 +135,11 @@ struct tm_ctx {
   tmh::DevBuf tden, ttmp;  // dense T [N][L][L] (boundary order); its scratch vector
   // workspaces
   tmh::DevBuf partial, xlow, work_a, work_b, work_c, basis, dots, dotpart, scal;
+  // single-system GMRES state on the device (flags, Hessenberg, rotations)
+  tmh::DevBuf gm_dev;
+  // while set, the block-matvec kernels of apply_op return at once when the
+  // pointed-to flag is nonzero (the GMRES cycle has stopped)
+  const int* mv_stop = nullptr;
   // host staging (pinned)
   void* host_pinned = nullptr;
   size_t host_pinned_bytes = 0;
@@ -264,15 +269,36 @@ int lds_apply_fixed(tm_ctx* c, int R, const void* table, const void* xin, const 
 // looked up once per device by tm_create (tm_noalloc.hip)
 int noalloc_init(tm_ctx* c);
 
-// Krylov kernels (tm_krylov.hip)
+// Krylov kernels (tm_krylov.hip).  `stop` (nullable, device): the kernel
+// returns at once when *stop is nonzero.
 void k_multidot(hipStream_t st, const c128* V, long long stride, int nvec, const c128* w,
-                long long len, c128* partial, int nblk);
+                long long len, c128* partial, int nblk, const int* stop = nullptr);
 void k_reduce_dots(hipStream_t st, const c128* partial, int nblk, int nvec, c128* out,
-                   const c128* add);
+                   const c128* add, const int* stop = nullptr);
 void k_update(hipStream_t st, c128* w, const c128* V, long long stride, int nvec,
-              const c128* h, long long len, double sign);
-void k_norm2_partial(hipStream_t st, const c128* w, long long len, double* partial, int nblk);
-void k_reduce_norm(hipStream_t st, const double* partial, int nblk, double* out);
+              const c128* h, long long len, double sign, const int* stop = nullptr);
+void k_norm2_partial(hipStream_t st, const c128* w, long long len, double* partial, int nblk,
+                     const int* stop = nullptr);
+void k_reduce_norm(hipStream_t st, const double* partial, int nblk, double* out,
+                   const int* stop = nullptr);
+// Device-side Givens of one restarted GMRES cycle.  Layout of the state
+// buffer: GmFlags, then H [(m+1) x m], cs [m], sn [m], g [m+1], y [m]
+// (complex).  One Arnoldi step: column j of H from the two CGS passes' dots
+// and the new vector's norm, the previous rotations applied, a new rotation,
+// the residual estimate |g[j+1]|; `stop` is raised when the estimate reaches
+// `target`, on a zero (lucky breakdown) or non-finite norm.
+struct GmFlags {
+  int stop, jend, nonfinite, pad;
+  double inv_hn, est;
+};
+size_t gm_state_bytes(int m);
+void k_gm_cycle_init(hipStream_t st, void* state, int m, const double* beta);
+void k_gm_givens(hipStream_t st, void* state, int m, int j, const c128* h1, const c128* h2,
+                 const double* hn, double target);
+void k_gm_scale_next(hipStream_t st, c128* v, const c128* w, const void* state, long long len);
+void k_gm_backsub(hipStream_t st, void* state, int m);
+void k_gm_update_x(hipStream_t st, c128* x, const c128* V, long long len, const void* state, int m);
+const c128* gm_y(const void* state, int m);
 void k_scale(hipStream_t st, c128* y, const c128* x, double a, long long len);
 void k_axpy_dev(hipStream_t st, c128* y, const c128* x, const c128* V, long long stride,
                 int nvec, const c128* coef, long long len);

@@ -534,7 +534,8 @@ __global__ void lds_combine_kernel(const cplx<T>* __restrict__ partial, const in
                                    int R, int nx, LdsTiling tl, long long N,
                                    const c128* __restrict__ x, const c128* __restrict__ t,
                                    c128* __restrict__ y, long long vec, long long total, int mode,
-                                   int S, int NG) {
+                                   int S, int NG, const int* __restrict__ stop) {
+  if (stop && *stop) return;
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= total) return;
   const int sl = (int)(idx % S);
@@ -694,7 +695,7 @@ int lds_apply(tm_ctx* c, int which, int R, const void* table, const void* xin, c
   a.n_sites = g.n;
   a.subs = nullptr;
   a.active = nullptr;
-  a.done = nullptr;
+  a.done = c->mv_stop;  // a stopped GMRES cycle skips its remaining matvecs
   a.y_base = 0;
   a.tile_base = 0;
   a.item_base = 0;
@@ -739,7 +740,8 @@ int lds_apply(tm_ctx* c, int which, int R, const void* table, const void* xin, c
     const int nb = (int)((total + 255) / 256);
     hipLaunchKernelGGL(lds_combine_kernel<T>, dim3(nb), dim3(256), 0, c->stream,
                        (const cplx<T>*)c->partial.p, (const int*)c->plan_ibeg[which].p, R, g.nx, tl,
-                       (long long)g.n, x, (const c128*)c->t64.p, y, vec, total, op, g.S, g.NG);
+                       (long long)g.n, x, (const c128*)c->t64.p, y, vec, total, op, g.S, g.NG,
+                       c->mv_stop);
   }
   TM_HIP(c, hipGetLastError());
   return TM_OK;
@@ -858,7 +860,7 @@ int lds_apply_fixed(tm_ctx* c, int R, const void* table, const void* xin, const 
   const long long vec = g.vec_len(), total = vec * R;
   hipLaunchKernelGGL(lds_combine_kernel<T>, dim3((int)((total + 255) / 256)), dim3(256), 0, c->stream,
                      (const cplx<T>*)partial, (const int*)ibeg, R, g.nx, tl, (long long)g.n, x,
-                     (const c128*)c->t64.p, y, vec, total, op, g.S, g.NG);
+                     (const c128*)c->t64.p, y, vec, total, op, g.S, g.NG, (const int*)nullptr);
   TM_HIP(c, hipGetLastError());
   return TM_OK;
 }

@@ -58,7 +58,8 @@ template <typename T>
 __global__ __launch_bounds__(OL_THREADS) void offlattice_kernel(
     const double* __restrict__ xy, const cplx<T>* __restrict__ x, const double* __restrict__ coef,
     const int* __restrict__ dm, int N, int S, int nh, int lmax, double k, int chunk, int transpose,
-    cplx<T>* __restrict__ partial) {
+    cplx<T>* __restrict__ partial, const int* __restrict__ stop) {
+  if (stop && *stop) return;  // a stopped GMRES cycle
   extern __shared__ double ol_lds[];
   double* sxy = ol_lds;                                        // [OL_GROUP][2]
   cplx<T>* sx = reinterpret_cast<cplx<T>*>(ol_lds + 2 * OL_GROUP);  // [OL_GROUP][S]
@@ -138,7 +139,8 @@ template <typename T>
 __global__ void offlattice_combine_kernel(const cplx<T>* __restrict__ partial, int nchunk,
                                           long long total, const c128* __restrict__ x,
                                           const c128* __restrict__ t, long long vec,
-                                          c128* __restrict__ y, int mode) {
+                                          c128* __restrict__ y, int mode, const int* __restrict__ stop) {
+  if (stop && *stop) return;
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= total) return;
   double sr = 0.0, si = 0.0;
@@ -180,10 +182,10 @@ int offlattice_apply(tm_ctx* c, Op op, int R, const void* xin, const c128* x, c1
   const bool tr = (op == Op::Adjoint || op == Op::CouplingT);
   hipLaunchKernelGGL(offlattice_kernel<T>, dim3(tb, 2 * R, nchunk), dim3(OL_THREADS), lds, c->stream,
                      (const double*)c->xy.p, (const cplx<T>*)xin, coef, dm, N, S, nh, g.lmax, g.k, chunk,
-                     tr ? 1 : 0, (cplx<T>*)c->partial.p);
+                     tr ? 1 : 0, (cplx<T>*)c->partial.p, c->mv_stop);
   hipLaunchKernelGGL(offlattice_combine_kernel<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
                      c->stream, (const cplx<T>*)c->partial.p, nchunk, total, x, (const c128*)c->t64.p,
-                     g.vec_len(), y, (int)op);
+                     g.vec_len(), y, (int)op, c->mv_stop);
   TM_HIP(c, hipGetLastError());
   return TM_OK;
 }
