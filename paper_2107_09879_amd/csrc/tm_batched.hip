@@ -26,11 +26,8 @@
 
 namespace tmh {
 
-// from tm_matvec_lds.hip
-double lds_block_work(int nx, int ny, int TW, int BX, int BY, int win_cost,
-                      std::vector<std::vector<double>>& wb);
-void lds_split(const std::vector<std::vector<double>>& wb, double per, int sub,
-               std::vector<LdsItem>& items, std::vector<int>& ibeg);
+// from tm_matvec_lds.hip (the planner, lds_block_work and lds_split, is in
+// tm_host.h)
 template <typename T>
 int lds_launch(tm_ctx* c, const void* table, const void* xin, void* partial, const LdsItem* items,
                int nitems, int R, const SubParams* subs, const int* active, const int* done, int pf);

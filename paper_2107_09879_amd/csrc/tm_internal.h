@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "../../include/tmhip.h"
+#include "tm_host.h"
 
 namespace tmh {
 
@@ -84,11 +85,6 @@ struct SubParams {
   long long vec_off;
 };
 
-// Work item of the LDS-staged block matvec: a target tile of a (sub)lattice
-// and a range [b0, b1) of its displacement blocks.
-struct LdsItem {
-  int tile, b0, b1, sub;
-};
 
 // Workspace buffer that grows on demand.
 struct DevBuf {

@@ -409,124 +409,6 @@ __global__ __launch_bounds__(256, 2) void block_matvec_lds_kernel(LdsArgs a) {
   }
 }
 
-// ---------------------------------------------------------------- host side
-// Work of every displacement block of one tile (MFMA units plus the window
-// copy), mirroring the kernel's per-wave clipping: the planner cuts each
-// tile's block list into equal-work items.  TW = columns per wave.
-static double tile_block_work(int nx, int ny, int X0, int Y0, bool wide, int TW, int BX, int BY,
-                              int win_cost, std::vector<double>& wb) {
-  const int GX = TW / 4;
-  const int TWT = wide ? 4 * TW : TW;
-  // displacement rows relative to each wave's first row (as in the kernel)
-  const int dxlo = X0 - (nx - 1), dxhi = std::min(X0 + TWT - 1, nx - 1);
-  const int dylo = Y0 - (ny - 1), dyhi = std::min(Y0 + 3, ny - 1);
-  const int nbx = (dxhi - dxlo + BX) / BX, nby = (dyhi - dylo + BY) / BY;
-  wb.assign((size_t)nbx * nby, 0.0);
-  int gyw[4], gxw[4];
-  for (int wv = 0; wv < 4; ++wv) {
-    gyw[wv] = Y0 + (wide ? 0 : 4 * wv);
-    gxw[wv] = X0 + (wide ? TW * wv : 0);
-  }
-  double total = 0.0;
-  for (int b = 0; b < nbx * nby; ++b) {
-    const int bx0 = dxlo + (b % nbx) * BX, by0 = dylo + (b / nbx) * BY;
-    double w = win_cost;
-    for (int wv = 0; wv < 4; ++wv) {
-      const int gy0 = gyw[wv], gx = gxw[wv];
-      if (gy0 >= ny || gx >= nx) continue;
-      const int yb = std::max(by0, dylo);
-      const int ye = std::min(by0 + BY - 1, std::min(Y0 + 3, ny - 1 - (gy0 - Y0)));
-      const int xb = std::max(bx0, std::max(dxlo, gx - (nx - 1)));
-      const int xe = std::min(bx0 + BX - 1, std::min(dxhi, std::min(gx + TW - 1, nx - 1)));
-      if (yb > ye || xb > xe) continue;
-      double row = 0.0;
-      for (int dx = xb; dx <= xe; ++dx) {
-        int groups = 0;
-        for (int q = 0; q < GX; ++q) {
-          const int gx0 = gx + 4 * q;
-          if (gx0 < nx && gx0 + 3 - dx >= 0 && gx0 - dx < nx) ++groups;
-        }
-        row += 12.0 * groups + 4.0;
-      }
-      w += row * (ye - yb + 1);
-    }
-    wb[b] = w;
-    total += w;
-  }
-  return total;
-}
-
-// Regular tiles only (the batched solver's subregions).
-double lds_block_work(int nx, int ny, int TW, int BX, int BY, int win_cost,
-                      std::vector<std::vector<double>>& wb) {
-  const int tiles_x = (nx + TW - 1) / TW, tiles_y = (ny + 15) / 16;
-  wb.assign((size_t)tiles_x * tiles_y, {});
-  double total = 0.0;
-  for (int t = 0; t < tiles_x * tiles_y; ++t)
-    total += tile_block_work(nx, ny, (t % tiles_x) * TW, (t / tiles_x) * 16, false, TW, BX, BY,
-                             win_cost, wb[t]);
-  return total;
-}
-
-// Tiling of one lattice: regular tiles over rows [0, y_wide), wide tiles (4
-// rows) over the remaining ny - y_wide < 16 rows.
-struct LdsTiling {
-  int TW, tiles_x, n_reg, y_wide, tiles_xw, n_wide;
-};
-static LdsTiling lds_tiling(const Geometry& g, int TW) {
-  LdsTiling tl;
-  tl.TW = TW;
-  tl.tiles_x = (g.nx + TW - 1) / TW;
-  tl.y_wide = 16 * (g.ny / 16);
-  tl.n_reg = tl.tiles_x * (tl.y_wide / 16);
-  tl.tiles_xw = (g.nx + 4 * TW - 1) / (4 * TW);
-  tl.n_wide = g.ny > tl.y_wide ? tl.tiles_xw * ((g.ny - tl.y_wide + 3) / 4) : 0;
-  return tl;
-}
-
-// Cut every tile's blocks into items of about `per` work; appends to items
-// and ibeg (ibeg gets one entry per tile, the caller closes the list).
-void lds_split(const std::vector<std::vector<double>>& wb, double per, int sub,
-               std::vector<LdsItem>& items, std::vector<int>& ibeg) {
-  for (int t = 0; t < (int)wb.size(); ++t) {
-    ibeg.push_back((int)items.size());
-    const int nb = (int)wb[t].size();
-    double wt = 0.0;
-    for (double v : wb[t]) wt += v;
-    int nch = std::max(1, std::min(nb, (int)std::llround(wt / per)));
-    double acc = 0.0;
-    int start = 0, k = 1;
-    for (int b = 0; b < nb; ++b) {
-      acc += wb[t][b];
-      if (k < nch && acc >= k * wt / nch && b < nb - 1) {
-        items.push_back(LdsItem{t, start, b + 1, sub});
-        start = b + 1;
-        ++k;
-      }
-    }
-    items.push_back(LdsItem{t, start, nb, sub});
-  }
-}
-
-// Items of one lattice: regular tiles first, then wide tiles (tile indices
-// continue), so the two launches take contiguous item ranges.
-static void lds_plan(const Geometry& g, const LdsTiling& tl, int BX, int BY, int WBX, int WBY,
-                     int win_cost, int target, std::vector<LdsItem>& items, std::vector<int>& ibeg) {
-  std::vector<std::vector<double>> wb((size_t)tl.n_reg + tl.n_wide);
-  double total = 0.0;
-  for (int t = 0; t < tl.n_reg; ++t)
-    total += tile_block_work(g.nx, g.ny, (t % tl.tiles_x) * tl.TW, (t / tl.tiles_x) * 16, false, tl.TW,
-                             BX, BY, win_cost, wb[t]);
-  for (int t = 0; t < tl.n_wide; ++t)
-    total += tile_block_work(g.nx, g.ny, (t % tl.tiles_xw) * 4 * tl.TW, tl.y_wide + (t / tl.tiles_xw) * 4,
-                             true, tl.TW, WBX, WBY, win_cost, wb[(size_t)tl.n_reg + t]);
-  items.clear();
-  ibeg.clear();
-  lds_split(wb, total / std::max(1, target), 0, items, ibeg);
-  ibeg.push_back((int)items.size());
-}
-
-
 // y = x - t * z (Forward) etc., z = sum of the partials of the items covering
 // the site's tile, added in item order.
 template <typename T>
@@ -654,13 +536,13 @@ int lds_apply(tm_ctx* c, int which, int R, const void* table, const void* xin, c
   using Cfg = LdsCfg<T, Ch::GX, Ch::BX, Ch::BY>;
   const Geometry& g = c->g;
   const int TW = Cfg::TW;
-  const LdsTiling tl = lds_tiling(g, TW);
+  const LdsTiling tl = lds_tiling(g.nx, g.ny, TW);
   const long long vec = g.vec_len(), total = vec * R;
   int rc;
   if (c->plan_kind[which] != 2 || c->plan_R[which] != R || c->plan_target[which] != items_target) {
     std::vector<LdsItem> items;
     std::vector<int> ibeg;
-    lds_plan(g, tl, Ch::BX, Ch::BY, Ch::WBX, Ch::WBY, 64, items_target, items, ibeg);
+    lds_plan(g.nx, g.ny, tl, Ch::BX, Ch::BY, Ch::WBX, Ch::WBY, 64, items_target, items, ibeg);
     c->plan_nreg[which] = ibeg[tl.n_reg];
     if ((rc = ensure(c, c->plan_items[which], items.size() * sizeof(LdsItem))) != TM_OK) return rc;
     if ((rc = ensure(c, c->plan_ibeg[which], ibeg.size() * sizeof(int))) != TM_OK) return rc;
@@ -790,7 +672,7 @@ static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 template <typename T>
 size_t lds_fixed_bytes(const Geometry& g, int R, int ipt) {
   using Ch = LdsChoice<T>;
-  const LdsTiling tl = lds_tiling(g, 4 * Ch::GX);
+  const LdsTiling tl = lds_tiling(g.nx, g.ny, 4 * Ch::GX);
   const size_t ntile = (size_t)tl.n_reg + tl.n_wide;
   const size_t nitems = ntile * ipt;
   return align256(nitems * sizeof(LdsItem)) + align256((ntile + 1) * sizeof(int)) +
@@ -800,7 +682,7 @@ size_t lds_fixed_bytes(const Geometry& g, int R, int ipt) {
 template <typename T>
 int lds_fixed_default_ipt(const Geometry& g, int R) {
   using Ch = LdsChoice<T>;
-  const LdsTiling tl = lds_tiling(g, 4 * Ch::GX);
+  const LdsTiling tl = lds_tiling(g.nx, g.ny, 4 * Ch::GX);
   const int ntile = tl.n_reg + tl.n_wide;
   const int target = std::max(1, (16384 + 2 * R - 1) / (2 * R));
   return std::max(1, (target + ntile - 1) / ntile);
@@ -815,7 +697,7 @@ int lds_apply_fixed(tm_ctx* c, int R, const void* table, const void* xin, const 
                     int op, int pf, int ipt, void* buf) {
   using Ch = LdsChoice<T>;
   const Geometry& g = c->g;
-  const LdsTiling tl = lds_tiling(g, 4 * Ch::GX);
+  const LdsTiling tl = lds_tiling(g.nx, g.ny, 4 * Ch::GX);
   const int ntile = tl.n_reg + tl.n_wide;
   const int nitems = ntile * ipt;
   char* p = static_cast<char*>(buf);

@@ -28,35 +28,6 @@
 
 namespace tmh {
 
-static long double lfact(int n) {
-  long double r = 1.0L;
-  for (int i = 2; i <= n; ++i) r *= (long double)i;
-  return r;
-}
-
-// Wigner 3j symbol by the Racah formula (all factorials exact in long double
-// for the orders used here, j <= 12).
-static double wigner3j(int j1, int j2, int j3, int m1, int m2, int m3) {
-  if (m1 + m2 + m3 != 0) return 0.0;
-  if (j3 < std::abs(j1 - j2) || j3 > j1 + j2) return 0.0;
-  if (std::abs(m1) > j1 || std::abs(m2) > j2 || std::abs(m3) > j3) return 0.0;
-  long double tri = lfact(j1 + j2 - j3) * lfact(j1 - j2 + j3) * lfact(-j1 + j2 + j3) /
-                    lfact(j1 + j2 + j3 + 1);
-  long double pre = std::sqrt(tri * lfact(j1 + m1) * lfact(j1 - m1) * lfact(j2 + m2) *
-                              lfact(j2 - m2) * lfact(j3 + m3) * lfact(j3 - m3));
-  int kmin = std::max(0, std::max(j2 - j3 - m1, j1 - j3 + m2));
-  int kmax = std::min(j1 + j2 - j3, std::min(j1 - m1, j2 + m2));
-  long double s = 0.0L;
-  for (int k = kmin; k <= kmax; ++k) {
-    long double den = lfact(k) * lfact(j1 + j2 - j3 - k) * lfact(j1 - m1 - k) *
-                      lfact(j2 + m2 - k) * lfact(j3 - j2 + m1 + k) * lfact(j3 - j1 - m2 + k);
-    s += ((k & 1) ? -1.0L : 1.0L) / den;
-  }
-  int e = j1 - j2 - m3;
-  long double sign = ((e % 2) + 2) % 2 ? -1.0L : 1.0L;
-  return (double)(sign * pre * s);
-}
-
 // i^e as (re, im)
 static void ipow(int e, double& re, double& im) {
   switch (((e % 4) + 4) % 4) {
