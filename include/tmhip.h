@@ -367,7 +367,12 @@ int tm_detector_vector(tm_ctx* ctx, const double* xd, const tm_c128* w, tm_c128*
  * a_exc = a0 + A s (exciting field).  mu, s, a0: device [R][N][L];
  * grad: device [R][N] doubles.  With mu from tm_adjoint_solve of the
  * objective's weighted detector vector this is dO/dr_i (App. IV,
- * eq. "grad_geometry_overlap"). */
+ * eq. "grad_geometry_overlap").  Factor convention: for a real function f
+ * of s, the 2 Re above assumes the adjoint right-hand side w = df/ds (the
+ * holomorphic derivative, as the detector vector gives for O = |E|^2 with
+ * conj(E) folded into w).  A caller holding instead G = 2 df/ds*, the
+ * gradient convention of PyTorch, solves with w = conj(G) and halves the
+ * result: df/dr_i = grad[i] / 2. */
 int tm_grad_radius(tm_ctx* ctx, int n_rhs, const tm_c128* mu, const tm_c128* s,
                    const tm_c128* a0, double* grad);
 
