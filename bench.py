@@ -41,7 +41,7 @@ def kernel_names(variant, ctype):
     if variant >= 8:
         # (columns groups per wave, displacement block) of the regular and the
         # wide tiles
-        gx, reg, wide = (4, (16, 8), (16, 4)) if ctype == "float" else (2, (8, 16), (8, 4))
+        gx, reg, wide = (4, (16, 8), (16, 8)) if ctype == "float" else (2, (8, 16), (8, 16))
         pf = variant - 7 if ctype == "float" else min(variant - 7, 2)
         # regular tiles, then the wide-tile instance for the rows past the
         # last multiple of 16 (absent when the height is a multiple of 16)

@@ -23,9 +23,9 @@ struct LdsItem {
 inline double tile_block_work(int nx, int ny, int X0, int Y0, bool wide, int TW, int BX, int BY,
                               int win_cost, std::vector<double>& wb) {
   const int GX = TW / 4;
-  const int TWT = wide ? 4 * TW : TW;
-  // displacement rows relative to each wave's first row (as in the kernel)
-  const int dxlo = X0 - (nx - 1), dxhi = std::min(X0 + TWT - 1, nx - 1);
+  // displacements relative to each wave's first row and column (as in the
+  // kernel): wave w applies (x + wxo, y + wyo) at relative (x, y)
+  const int dxlo = X0 - (nx - 1), dxhi = std::min(X0 + TW - 1, nx - 1);
   const int dylo = Y0 - (ny - 1), dyhi = std::min(Y0 + 3, ny - 1);
   const int nbx = (dxhi - dxlo + BX) / BX, nby = (dyhi - dylo + BY) / BY;
   wb.assign((size_t)nbx * nby, 0.0);
@@ -41,17 +41,18 @@ inline double tile_block_work(int nx, int ny, int X0, int Y0, bool wide, int TW,
     for (int wv = 0; wv < 4; ++wv) {
       const int gy0 = gyw[wv], gx = gxw[wv];
       if (gy0 >= ny || gx >= nx) continue;
+      const int wxo = gx - X0, wyo = gy0 - Y0;
       const int yb = std::max(by0, dylo);
-      const int ye = std::min(by0 + BY - 1, std::min(Y0 + 3, ny - 1 - (gy0 - Y0)));
-      const int xb = std::max(bx0, std::max(dxlo, gx - (nx - 1)));
-      const int xe = std::min(bx0 + BX - 1, std::min(dxhi, std::min(gx + TW - 1, nx - 1)));
+      const int ye = std::min(by0 + BY - 1, std::min(Y0 + 3, ny - 1 - wyo));
+      const int xb = std::max(bx0, dxlo);
+      const int xe = std::min(bx0 + BX - 1, std::min(X0 + TW - 1, nx - 1 - wxo));
       if (yb > ye || xb > xe) continue;
       double row = 0.0;
       for (int dx = xb; dx <= xe; ++dx) {
         int groups = 0;
         for (int q = 0; q < GX; ++q) {
-          const int gx0 = gx + 4 * q;
-          if (gx0 < nx && gx0 + 3 - dx >= 0 && gx0 - dx < nx) ++groups;
+          const int gx0 = gx + 4 * q, ad = dx + wxo;  // actual displacement column
+          if (gx0 < nx && gx0 + 3 - ad >= 0 && gx0 - ad < nx) ++groups;
         }
         row += 12.0 * groups + 4.0;
       }

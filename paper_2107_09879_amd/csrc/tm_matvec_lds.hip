@@ -131,10 +131,11 @@ struct LdsCfg {
   static constexpr int TW = 4 * GX;                // columns per wave
   static constexpr int TWT = WIDE ? 4 * TW : TW;   // tile width in sites
   static constexpr int THT = WIDE ? 4 : 16;        // tile height in sites
-  // every wave reads the same 4 source rows per displacement row (wave w of
-  // a regular tile takes its displacements shifted by 4w rows), so a window
-  // is 4 - 1 + BY rows high for both tile shapes
-  static constexpr int WX = TWT - 1 + BX, WY = 4 - 1 + BY;
+  // every wave reads the same 4 x TW source sites per displacement (wave w
+  // of a regular tile takes its displacements shifted by 4w rows, of a wide
+  // tile by TW w columns), so a window is (TW - 1 + BX) x (4 - 1 + BY) for
+  // both tile shapes
+  static constexpr int WX = TW - 1 + BX, WY = 4 - 1 + BY;
   static constexpr int CH = LdsT<T>::CH;
   // FP32 regular tiles use a padded layout instead of the XOR swizzle, so
   // that the address of a lane's B operand is affine in the displacement (one
@@ -144,7 +145,7 @@ struct LdsCfg {
   // padding (10 chunks per site) needs 8x6 displacement blocks to fit two
   // workgroups per CU and measured slower, the extra windows costing more
   // than the conflicts.
-  static constexpr bool PAD = std::is_same<T, float>::value && !WIDE;
+  static constexpr bool PAD = std::is_same<T, float>::value;
   static constexpr int SS = PAD ? CH + 1 : CH;
   static constexpr int RP = PAD ? ((WX * SS + 11) / 16) * 16 + 4 : WX * CH;
   static constexpr int CHUNKS = WY * RP;
@@ -199,22 +200,23 @@ __global__ __launch_bounds__(256, 2) void block_matvec_lds_kernel(LdsArgs a) {
       reinterpret_cast<const C*>(a.x) + voff + ((size_t)r * NCLASS + c) * N * S;
   const C* __restrict__ tab = reinterpret_cast<const C*>(a.table);
   const int wxt = 2 * a.tnx - 1;
-  // The tile's displacement range and its block grid.  Rows are counted
-  // relative to each wave: at relative row y, the wave with rows gy0..gy0+3
-  // applies the displacement row y + (gy0 - Y0), so that all waves read
-  // source rows Y0 - y .. Y0 + 3 - y of one shared window and have the same
-  // number of steps (waves of a tile cut by the lattice edge excepted).
-  const int dxlo = X0 - (nx - 1), dxhi = min(X0 + TWT - 1, nx - 1);
+  // The tile's displacement range and its block grid.  Displacements are
+  // counted relative to each wave: at relative (x, y), the wave whose sites
+  // start at (gxw, gy0) applies the displacement (x + wxo, y + wyo), so that
+  // all waves read source columns X0 - x .. X0 + TW - 1 - x and rows
+  // Y0 - y .. Y0 + 3 - y of one shared window and have the same number of
+  // steps (waves cut by the lattice edge excepted).
+  const int dxlo = X0 - (nx - 1), dxhi = min(X0 + TW - 1, nx - 1);
   const int dylo = Y0 - (ny - 1), dyhi = min(Y0 + 3, ny - 1);
   const int nbx = (dxhi - dxlo + BX) / BX;
   // this wave's valid displacements (its rows and columns must reach a
-  // source), rows relative
+  // source), relative
   const int wdylo = dylo, wdyhi = min(Y0 + 3, ny - 1 - wyo);
-  const int wdxlo = gxw - (nx - 1), wdxhi = min(gxw + TW - 1, nx - 1);
+  const int wdxlo = dxlo, wdxhi = min(X0 + TW - 1, nx - 1 - wxo);
   const bool wave_live = gy0 < ny && gxw < nx;
   // padded layout: chunk of this lane's B operand (group 0, K-chunk kq) at the
   // block's first displacement (bx0, by0)
-  const int lane_b0 = (ly + BY - 1) * Cfg::RP + (wxo + lx + BX - 1) * Cfg::SS + kq;
+  const int lane_b0 = (ly + BY - 1) * Cfg::RP + (lx + BX - 1) * Cfg::SS + kq;
 
   acc_t t1[GX], t2[GX], t3[GX];
 #pragma unroll
@@ -254,7 +256,7 @@ __global__ __launch_bounds__(256, 2) void block_matvec_lds_kernel(LdsArgs a) {
       y += wrap;
     };
     auto table_block = [&](int x, int y) {
-      return tab + (((size_t)(y + wyo + a.tny - 1) * wxt + (x + a.tnx - 1)) * NCLASS + c) * (size_t)(S * S) +
+      return tab + (((size_t)(y + wyo + a.tny - 1) * wxt + (x + wxo + a.tnx - 1)) * NCLASS + c) * (size_t)(S * S) +
              boff;
     };
     auto read_all_b = [&](int x, int y, T (*r_)[4], T (*i_)[4]) {
@@ -272,7 +274,7 @@ __global__ __launch_bounds__(256, 2) void block_matvec_lds_kernel(LdsArgs a) {
         const int wy = ly - (y - by0) + BY - 1;
 #pragma unroll
         for (int g = 0; g < GX; ++g) {
-          const int wx = wxo + 4 * g + lx - (x - bx0) + BX - 1;
+          const int wx = 4 * g + lx - (x - bx0) + BX - 1;
           read_b(win, (wy * WX + wx) * CH, wx, wy, kq, r_[g], i_[g]);
         }
       }
@@ -363,8 +365,9 @@ __global__ __launch_bounds__(256, 2) void block_matvec_lds_kernel(LdsArgs a) {
       int gmask = 0;
 #pragma unroll
       for (int g = 0; g < GX; ++g) {
-        const int gx0 = gxw + 4 * g;
-        gmask |= (((cdx - gx0 - 4) & (gx0 - cdx - nx) & (gx0 - nx)) >> 31) & (1 << g);
+        // target columns gx0..gx0+3; the actual displacement is cdx + wxo
+        const int gx0 = gxw + 4 * g, gxr = X0 + 4 * g;
+        gmask |= (((cdx - gxr - 4) & (gxr - cdx - nx) & (gx0 - nx)) >> 31) & (1 << g);
       }
 #pragma unroll
       for (int g = 0; g < GX; ++g)
@@ -478,10 +481,10 @@ __global__ void lds_combine_kernel(const cplx<T>* __restrict__ partial, const in
   y[idx] = o;
 }
 
-// Configurations (two workgroups per CU): FP32 16x16 tile with 16x8
-// displacement blocks in the padded layout (51 KB of LDS), its 64x4 wide
-// tiles with 16x4 blocks (71 KB); FP64 8x16 tile with 8x16 blocks (73 KB),
-// its 32x4 wide tiles with 8x4 blocks (70 KB).
+// Configurations: FP32 16x16 tiles (and 64x4 wide tiles) with 16x8
+// displacement blocks in the padded layout (51 KB of LDS: three workgroups
+// per CU at prefetch depth 1); FP64 8x16 tiles (and 32x4 wide tiles) with
+// 8x16 blocks (73 KB: two per CU).
 #ifndef TM_LDS_F32_BX
 #define TM_LDS_F32_BX 16
 #define TM_LDS_F32_BY 8
@@ -493,19 +496,16 @@ template <typename T>
 struct LdsChoice;
 template <>
 struct LdsChoice<float> {
-  static constexpr int GX = TM_LDS_F32_GX, BX = TM_LDS_F32_BX, BY = TM_LDS_F32_BY, WBX = 16, WBY = 4;
+  static constexpr int GX = TM_LDS_F32_GX, BX = TM_LDS_F32_BX, BY = TM_LDS_F32_BY, WBX = BX, WBY = BY;
 };
 template <>
 struct LdsChoice<double> {
-  static constexpr int GX = 2, BX = 8, BY = 16, WBX = 8, WBY = 4;
+  static constexpr int GX = 2, BX = 8, BY = 16, WBX = BX, WBY = BY;
 };
 static_assert(LdsCfg<float, LdsChoice<float>::GX, LdsChoice<float>::BX, LdsChoice<float>::BY,
                      false>::BYTES <= 80 * 1024,
               "two FP32 workgroups per CU");
-static_assert(LdsCfg<float, LdsChoice<float>::GX, 16, 4, true>::BYTES <= 80 * 1024,
-              "two FP32 workgroups per CU");
 static_assert(LdsCfg<double, 2, 8, 16, false>::BYTES <= 80 * 1024, "two FP64 workgroups per CU");
-static_assert(LdsCfg<double, 2, 8, 4, true>::BYTES <= 80 * 1024, "two FP64 workgroups per CU");
 
 template <typename T, int PF, bool WIDE>
 static void lds_launch_pf(hipStream_t st, int nitems, int R, const LdsArgs& a) {
@@ -643,23 +643,21 @@ __global__ void lds_uniform_plan_kernel(LdsItem* __restrict__ items, int* __rest
   }
   if (idx >= ntile * ipt) return;
   const int t = idx / ipt, k = idx % ipt;
-  int X0, Y0, TWT, BX, BY;
+  int X0, Y0, BX, BY;
   if (t < tl.n_reg) {
     X0 = (t % tl.tiles_x) * tl.TW;
     Y0 = (t / tl.tiles_x) * 16;
-    TWT = tl.TW;
     BX = Ch::BX;
     BY = Ch::BY;
   } else {
     const int w = t - tl.n_reg;
     X0 = (w % tl.tiles_xw) * 4 * tl.TW;
     Y0 = tl.y_wide + (w / tl.tiles_xw) * 4;
-    TWT = 4 * tl.TW;
     BX = Ch::WBX;
     BY = Ch::WBY;
   }
-  const int dxlo = X0 - (nx - 1), dxhi = min(X0 + TWT - 1, nx - 1);
-  const int dylo = Y0 - (ny - 1), dyhi = min(Y0 + 3, ny - 1);  // rows relative per wave
+  const int dxlo = X0 - (nx - 1), dxhi = min(X0 + tl.TW - 1, nx - 1);  // relative per wave
+  const int dylo = Y0 - (ny - 1), dyhi = min(Y0 + 3, ny - 1);
   const int nb = ((dxhi - dxlo + BX) / BX) * ((dyhi - dylo + BY) / BY);
   const int chunk = (nb + ipt - 1) / ipt;
   const int b0 = min(nb, k * chunk), b1 = min(nb, b0 + chunk);

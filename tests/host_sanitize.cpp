@@ -31,8 +31,9 @@ static int failures = 0;
   } while (0)
 
 // number of blocks of a tile, as the kernel and planner define the grid
-static int tile_blocks(int nx, int ny, int X0, int Y0, int TWT, int BX, int BY) {
-  const int dxlo = X0 - (nx - 1), dxhi = std::min(X0 + TWT - 1, nx - 1);
+// (displacements relative to each wave: TW columns, 4 rows)
+static int tile_blocks(int nx, int ny, int X0, int Y0, int TW, int BX, int BY) {
+  const int dxlo = X0 - (nx - 1), dxhi = std::min(X0 + TW - 1, nx - 1);
   const int dylo = Y0 - (ny - 1), dyhi = std::min(Y0 + 3, ny - 1);
   return ((dxhi - dxlo + BX) / BX) * ((dyhi - dylo + BY) / BY);
 }
@@ -43,8 +44,8 @@ static int tile_blocks(int nx, int ny, int X0, int Y0, int TWT, int BX, int BY) 
 // planner's cost model.
 static double replay_block(int nx, int ny, int X0, int Y0, bool wide, int TW, int BX, int BY, int b,
                            std::vector<int>* cover) {
-  const int GX = TW / 4, TWT = wide ? 4 * TW : TW;
-  const int dxlo = X0 - (nx - 1), dxhi = std::min(X0 + TWT - 1, nx - 1);
+  const int GX = TW / 4;
+  const int dxlo = X0 - (nx - 1), dxhi = std::min(X0 + TW - 1, nx - 1);
   const int dylo = Y0 - (ny - 1);
   const int nbx = (dxhi - dxlo + BX) / BX;
   const int bx0 = dxlo + (b % nbx) * BX, by0 = dylo + (b / nbx) * BY;
@@ -54,21 +55,21 @@ static double replay_block(int nx, int ny, int X0, int Y0, bool wide, int TW, in
     const int gy0 = Y0 + wyo, gxw = X0 + wxo;
     if (gy0 >= ny || gxw >= nx) continue;
     const int wdyhi = std::min(Y0 + 3, ny - 1 - wyo);
-    const int wdxlo = gxw - (nx - 1), wdxhi = std::min(gxw + TW - 1, nx - 1);
+    const int wdxhi = std::min(X0 + TW - 1, nx - 1 - wxo);
     const int dyb = std::max(by0, dylo), dye = std::min(by0 + BY - 1, wdyhi);
-    const int dxb = std::max(bx0, std::max(dxlo, wdxlo)), dxe = std::min(bx0 + BX - 1, std::min(dxhi, wdxhi));
+    const int dxb = std::max(bx0, dxlo), dxe = std::min(bx0 + BX - 1, std::min(dxhi, wdxhi));
     for (int y = dyb; y <= dye; ++y)
       for (int x = dxb; x <= dxe; ++x) {
         work += 4.0;
         for (int g = 0; g < GX; ++g) {
-          const int gx0 = gxw + 4 * g;
-          if (!(gx0 < nx && gx0 + 3 - x >= 0 && gx0 - x < nx)) continue;
+          const int gx0 = gxw + 4 * g, ax = x + wxo;  // actual displacement column
+          if (!(gx0 < nx && gx0 + 3 - ax >= 0 && gx0 - ax < nx)) continue;
           work += 12.0;
           if (!cover) continue;
           for (int ly = 0; ly < 4; ++ly)
             for (int lx = 0; lx < 4; ++lx) {
               const int tx = gx0 + lx, ty = gy0 + ly;
-              const int sx = tx - x, sy = ty - (y + wyo);
+              const int sx = tx - (x + wxo), sy = ty - (y + wyo);
               if (tx >= nx || ty >= ny || sx < 0 || sx >= nx || sy < 0 || sy >= ny) continue;
               (*cover)[((size_t)ty * nx + tx) * nx * ny + (size_t)sy * nx + sx] += 1;
             }
@@ -97,7 +98,7 @@ static void check_lattice(int nx, int ny, int TW, int BX, int BY, int WBX, int W
       const int X0 = wide ? (tt % tl.tiles_xw) * 4 * TW : (tt % tl.tiles_x) * TW;
       const int Y0 = wide ? tl.y_wide + (tt / tl.tiles_xw) * 4 : (tt / tl.tiles_x) * 16;
       const int bx = wide ? WBX : BX, by = wide ? WBY : BY;
-      const int nb = tile_blocks(nx, ny, X0, Y0, wide ? 4 * TW : TW, bx, by);
+      const int nb = tile_blocks(nx, ny, X0, Y0, TW, bx, by);
       CHECK(ibeg[t] < ibeg[t + 1], "tile %d has no item (%dx%d)", t, nx, ny);
       int next = 0;
       for (int i = ibeg[t]; i < ibeg[t + 1]; ++i) {
@@ -178,8 +179,9 @@ static void check_3j() {
 int main() {
   const int shapes[][2] = {{1, 1}, {3, 2}, {16, 16}, {17, 5}, {5, 17}, {33, 47}, {31, 20}, {64, 20}, {100, 100}};
   for (auto& sh : shapes) {
-    check_lattice(sh[0], sh[1], 16, 16, 8, 16, 4);  // complex64 kernel
-    check_lattice(sh[0], sh[1], 8, 8, 16, 8, 4);    // FP64 kernel
+    check_lattice(sh[0], sh[1], 16, 16, 8, 16, 8);  // complex64 kernel
+    check_lattice(sh[0], sh[1], 8, 8, 16, 8, 16);   // FP64 kernel
+    check_lattice(sh[0], sh[1], 16, 8, 8, 16, 4);   // other block shapes
   }
   check_subregions();
   check_3j();

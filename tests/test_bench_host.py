@@ -11,12 +11,12 @@ WL = "100x100 lattice, lmax 3 (3e5 unknowns)"
 def test_kernel_names_follow_the_launch_configuration():
     assert bench.kernel_names(10, "float") == [
         "block_matvec_lds_kernel<float, 4, 16, 8, 3, false>",
-        "block_matvec_lds_kernel<float, 4, 16, 4, 3, true>"]
+        "block_matvec_lds_kernel<float, 4, 16, 8, 3, true>"]
     # the FP64 kernel caps the table prefetch depth at 2
     assert bench.kernel_names(10, "double") == bench.kernel_names(9, "double")
     assert bench.kernel_names(8, "double") == [
         "block_matvec_lds_kernel<double, 2, 8, 16, 1, false>",
-        "block_matvec_lds_kernel<double, 2, 8, 4, 1, true>"]
+        "block_matvec_lds_kernel<double, 2, 8, 16, 1, true>"]
     assert bench.kernel_names(5, "float") == ["block_matvec_kernel<float, true, false, 4>"]
 
 
