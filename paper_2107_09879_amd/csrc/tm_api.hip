@@ -188,11 +188,11 @@ static int gmres(tm_ctx* c, Op op, const c128* b, c128* x, const tm_solve_opts& 
       c128* vj = G.V + (size_t)j * len;
       if ((rc = apply_op(c, op, prec, 1, vj, G.w)) != TM_OK) return rc;
       // CGS2: h1 = V^H w, w -= V h1, h2 = V^H w, w -= V h2, H(:,j) = h1 + h2
-      k_multidot(st, G.V, len, j + 1, G.w, len, G.dp, nblk, stop);
-      k_reduce_dots(st, G.dp, nblk, j + 1, G.dots, nullptr, stop);
+      int nseg = k_multidot(st, G.V, len, j + 1, G.w, len, G.dp, nblk, stop);
+      k_reduce_dots(st, G.dp, nseg, j + 1, G.dots, nullptr, stop);
       k_update(st, G.w, G.V, len, j + 1, G.dots, len, -1.0, stop);
-      k_multidot(st, G.V, len, j + 1, G.w, len, G.dp, nblk, stop);
-      k_reduce_dots(st, G.dp, nblk, j + 1, G.dots2, nullptr, stop);
+      nseg = k_multidot(st, G.V, len, j + 1, G.w, len, G.dp, nblk, stop);
+      k_reduce_dots(st, G.dp, nseg, j + 1, G.dots2, nullptr, stop);
       k_update(st, G.w, G.V, len, j + 1, G.dots2, len, -1.0, stop);
       k_norm2_partial(st, G.w, len, G.np, nblk, stop);
       k_reduce_norm(st, G.np, nblk, G.nout, stop);
@@ -319,7 +319,7 @@ void tm_destroy(tm_ctx* c) {
   hipSetDevice(c->device);
   hipStreamSynchronize(c->stream);
   for (tmh::DevBuf* b : {&c->dtab[0], &c->dtab[1], &c->dtab[2], &c->dtab[3], &c->gpos, &c->jinc_buf,
-                        &c->gm_dev})
+                        &c->gm_dev, &c->tmb, &c->tmflag})
     tmh::release(*b);
   for (tmh::DevBuf* b : {&c->tab64, &c->tab32, &c->tabT64, &c->tabT32, &c->t64, &c->t32, &c->dt64,
                         &c->tden, &c->ttmp, &c->partial, &c->xlow, &c->work_a, &c->work_b, &c->work_c, &c->basis,
@@ -403,7 +403,9 @@ int tm_set_geometry(tm_ctx* c, int n, const double* pos, double k, int lmax) {
   g.tnx = g.nx;
   g.tny = g.ny;
   tmh::host_slot_maps(lmax, g, c->maps);
+  tmh::host_mblock_maps(lmax, c->mbmaps);
   c->have_geom = c->have_t = c->have_dt = c->have_tabT = c->have_dtab = c->t_dense = false;
+  c->t_mblock = false;
   c->plan_R[0] = c->plan_R[1] = -1;
   int rc;
   if (lattice) {
@@ -554,7 +556,7 @@ int tm_set_spheres(tm_ctx* c, const double* radii, double n_re, double n_im) {
   rc = tmh::launch_mie(c, radii, n_re, n_im);
   if (rc != TM_OK) return rc;
   c->have_t = c->have_dt = true;
-  c->t_dense = false;
+  c->t_dense = c->t_mblock = false;
   return TM_OK;
 }
 
@@ -588,7 +590,7 @@ int tm_set_cylinders(tm_ctx* c, const double* radii, double height, double n_re,
   c->have_t = true;
   c->have_dt = false;
   c->t_dense = true;
-  return TM_OK;
+  return tmh::tdense_prepare(c);
 }
 
 int tm_ebcm_cylinder(int lmax, double k, double radius, double height, double n_re, double n_im,
@@ -633,7 +635,7 @@ int tm_set_tmatrix_diag(tm_ctx* c, const tm_c128* t) {
   TM_HIP(c, hipMemsetAsync(c->dt64.p, 0, c->dt64.bytes, c->stream));
   c->have_t = true;
   c->have_dt = false;
-  c->t_dense = false;
+  c->t_dense = c->t_mblock = false;
   return TM_OK;
 }
 
@@ -649,7 +651,7 @@ int tm_set_tmatrix_dense(tm_ctx* c, const tm_c128* T) {
   c->have_t = true;
   c->have_dt = false;
   c->t_dense = true;
-  return TM_OK;
+  return tmh::tdense_prepare(c);
 }
 
 int tm_get_tmatrix_diag(tm_ctx* c, tm_c128* t, tm_c128* dtdr) {

@@ -262,6 +262,72 @@ __global__ void tdense_kernel(const tm_c128* __restrict__ T, SlotMaps mp, long l
   }
 }
 
+// Structure test of a dense T: *flag |= 1 if some entry couples two different
+// azimuthal orders (m(n) != m(n')) and is not exactly zero (NaN counts).
+__global__ void tdense_mcheck_kernel(const tm_c128* __restrict__ T, MbMaps mb, int L,
+                                     long long total, int* __restrict__ flag) {
+  int hit = 0;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int n2 = (int)(e % L);
+    const int n = (int)((e / L) % L);
+    if (mb.blk_of[n] != mb.blk_of[n2]) {
+      const tm_c128 v = T[e];
+      if (!(v.re == 0.0) || !(v.im == 0.0)) hit = 1;
+    }
+  }
+  if (__any(hit) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+}
+
+// Tm[i][off_b + q nm_b + t] = T[i][mem_b[q]][mem_b[t]] for every m-block b
+__global__ void tdense_mpack_kernel(const tm_c128* __restrict__ T, MbMaps mb, int L, long long N,
+                                    c128* __restrict__ Tm) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N * mb.per_site) return;
+  const long long i = e / mb.per_site;
+  const int r = (int)(e % mb.per_site);
+  int b = 0;
+  while (b + 1 < mb.nblk && mb.off[b + 1] <= r) ++b;
+  const int nm = mb.nm[b];
+  const int q = (r - mb.off[b]) / nm, t = (r - mb.off[b]) % nm;
+  const tm_c128 v = T[((size_t)i * L + mb.mem[mb.first[b] + q]) * L + mb.mem[mb.first[b] + t]];
+  Tm[e] = c128{v.re, v.im};
+}
+
+// The dense-T apply of tdense_kernel for a T kept as m-blocks: the same
+// thread mapping and the same nonzero terms in the same order (members of a
+// block in increasing n), reading nm_b instead of L entries per output.
+__global__ void tdense_mb_kernel(const c128* __restrict__ Tm, MbMaps mb, SlotMaps mp, long long N,
+                                 int mode, const c128* __restrict__ x, const c128* __restrict__ z,
+                                 c128* __restrict__ y, long long total) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const int slot = (int)(e % mp.S);
+  const long long site = (e / mp.S) % N;
+  const long long rc = e / (mp.S * N);
+  const long long r = rc / NCLASS;
+  const int c = (int)(rc % NCLASS);
+  const int n = mp.n_of[c][slot];
+  double ar = 0.0, ai = 0.0;
+  if (n >= 0) {
+    const int b = mb.blk_of[n], q = mb.q_of[n], nm = mb.nm[b], f = mb.first[b];
+    const c128* Tb = Tm + (size_t)site * mb.per_site + mb.off[b];
+    for (int t = 0; t < nm; ++t) {
+      const int n2 = mb.mem[f + t];
+      const c128 zv = z[((size_t)(r * NCLASS + mp.cls_of[n2]) * N + site) * mp.S + mp.slot_of[n2]];
+      const c128 tv = mode == 2 ? Tb[t * nm + q] : Tb[q * nm + t];
+      ar += tv.re * zv.re - tv.im * zv.im;
+      ai += tv.re * zv.im + tv.im * zv.re;
+    }
+  }
+  if (mode == 1) {
+    const c128 xv = x[e];
+    y[e] = c128{xv.re - ar, xv.im - ai};
+  } else {
+    y[e] = c128{ar, ai};
+  }
+}
+
 // ---------------------------------------------------------------- plane wave
 struct PwArgs {
   double khat[3 * 8];
@@ -1496,9 +1562,39 @@ int launch_mie(tm_ctx* c, const double* radii, double n_re, double n_im) {
 int launch_tdense(tm_ctx* c, int R, int mode, const c128* x, const c128* z, c128* y) {
   const Geometry& g = c->g;
   const long long total = (long long)R * g.vec_len();
-  hipLaunchKernelGGL(tdense_kernel, dim3(nblk(total)), dim3(256), 0, c->stream,
-                     (const tm_c128*)c->tden.p, c->maps, (long long)g.n, mode, x, z, y, total);
+  if (c->t_mblock)
+    hipLaunchKernelGGL(tdense_mb_kernel, dim3(nblk(total)), dim3(256), 0, c->stream,
+                       (const c128*)c->tmb.p, c->mbmaps, c->maps, (long long)g.n, mode, x, z, y,
+                       total);
+  else
+    hipLaunchKernelGGL(tdense_kernel, dim3(nblk(total)), dim3(256), 0, c->stream,
+                       (const tm_c128*)c->tden.p, c->maps, (long long)g.n, mode, x, z, y, total);
   TM_HIP(c, hipGetLastError());
+  return TM_OK;
+}
+
+int tdense_prepare(tm_ctx* c) {
+  const Geometry& g = c->g;
+  const MbMaps& mb = c->mbmaps;
+  c->t_mblock = false;
+  int rc;
+  if ((rc = ensure(c, c->tmflag, sizeof(int))) != TM_OK) return rc;
+  TM_HIP(c, hipMemsetAsync(c->tmflag.p, 0, sizeof(int), c->stream));
+  const long long total = (long long)g.n * g.L * g.L;
+  const long long nb = std::min<long long>(nblk(total), 8192);
+  hipLaunchKernelGGL(tdense_mcheck_kernel, dim3((unsigned)nb), dim3(256), 0, c->stream,
+                     (const tm_c128*)c->tden.p, mb, g.L, total, (int*)c->tmflag.p);
+  TM_HIP(c, hipGetLastError());
+  int flag = 1;
+  TM_HIP(c, hipMemcpyAsync(&flag, c->tmflag.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  TM_HIP(c, hipStreamSynchronize(c->stream));
+  if (flag) return TM_OK;  // couples different m: the general apply
+  const long long packed = (long long)g.n * mb.per_site;
+  if ((rc = ensure(c, c->tmb, (size_t)packed * sizeof(c128))) != TM_OK) return rc;
+  hipLaunchKernelGGL(tdense_mpack_kernel, dim3(nblk(packed)), dim3(256), 0, c->stream,
+                     (const tm_c128*)c->tden.p, mb, g.L, (long long)g.n, (c128*)c->tmb.p);
+  TM_HIP(c, hipGetLastError());
+  c->t_mblock = true;
   return TM_OK;
 }
 

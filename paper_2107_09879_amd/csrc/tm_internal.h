@@ -59,6 +59,21 @@ struct SlotMaps {
   int L, lmax, S;
 };
 
+// Blocks of the coefficient index by azimuthal order m (boundary order n =
+// p*lmax(lmax+2) + l(l+1) - 1 + m): block b = m + lmax holds the 2(lmax -
+// max(1,|m|) + 1) indices with that m in increasing n.  A dense T that is
+// zero between different m (a scatterer symmetric about the z axis) is kept
+// as these square blocks only, `per_site` complex numbers per scatterer.
+constexpr int MBLK_MAX = 2 * LMAX_SUPPORTED + 1;
+struct MbMaps {
+  int blk_of[LM_MAX];  // n -> block
+  int q_of[LM_MAX];    // n -> row within its block
+  int mem[LM_MAX];     // block members, block after block
+  int first[MBLK_MAX], nm[MBLK_MAX], off[MBLK_MAX];
+  int nblk, per_site;
+};
+void host_mblock_maps(int lmax, MbMaps& mb);
+
 // Scatterer centres in the z = 0 plane as kernels see them: on a lattice
 // they follow from the site index, otherwise from a device array [N][2].
 struct SitePos {
@@ -114,6 +129,7 @@ struct tm_ctx {
   tmh::SlotMaps maps{};
   bool have_geom = false, have_t = false, have_dt = false;
   bool t_dense = false;  // T given as dense per-scatterer blocks (tden), not diagonal
+  bool t_mblock = false;  // ... and zero between different m: applied from tmb
   // translation tables [D][2][S][S]
   tmh::DevBuf tab64, tab32, tabT64, tabT32;
   bool have_tabT = false;
@@ -129,6 +145,8 @@ struct tm_ctx {
   // T and dT/dr in slot layout [2][N][S]
   tmh::DevBuf t64, t32, dt64;
   tmh::DevBuf tden, ttmp;  // dense T [N][L][L] (boundary order); its scratch vector
+  tmh::DevBuf tmb, tmflag;  // dense T as m-blocks [N][per_site]; structure flag
+  tmh::MbMaps mbmaps{};
   // workspaces
   tmh::DevBuf partial, xlow, work_a, work_b, work_c, basis, dots, dotpart, scal;
   // single-system GMRES state on the device (flags, Hessenberg, rotations)
@@ -208,6 +226,9 @@ int launch_far_field(tm_ctx* c, int R, const tm_c128* s, int D, const double* di
 int launch_detector(tm_ctx* c, const double* xd, const tm_c128* w, tm_c128* v);
 // dense T on slot-layout vectors: mode 0 y = T z, 1 y = x - T z, 2 y = T^T z
 int launch_tdense(tm_ctx* c, int R, int mode, const c128* x, const c128* z, c128* y);
+// after tden is filled: if T is zero between different m, pack its m-blocks
+// into tmb and set t_mblock (the apply then reads only the blocks)
+int tdense_prepare(tm_ctx* c);
 int launch_mie_one(hipStream_t st, double radius, double k, double nre, double nim, int lmax,
                    tm_c128* out);
 int launch_near_field_t(tm_ctx* c, int R, int P, const double* pts, const tm_c128* w, tm_c128* v);
@@ -266,8 +287,9 @@ int lds_apply_fixed(tm_ctx* c, int R, const void* table, const void* xin, const 
 int noalloc_init(tm_ctx* c);
 
 // Krylov kernels (tm_krylov.hip).  `stop` (nullable, device): the kernel
-// returns at once when *stop is nonzero.
-void k_multidot(hipStream_t st, const c128* V, long long stride, int nvec, const c128* w,
+// returns at once when *stop is nonzero.  k_multidot returns the number of
+// partial-sum rows it wrote (at most nblk), to be passed to k_reduce_dots.
+int k_multidot(hipStream_t st, const c128* V, long long stride, int nvec, const c128* w,
                 long long len, c128* partial, int nblk, const int* stop = nullptr);
 void k_reduce_dots(hipStream_t st, const c128* partial, int nblk, int nvec, c128* out,
                    const c128* add, const int* stop = nullptr);

@@ -35,11 +35,12 @@ __device__ inline double block_sum(double v, double* sh) {
   return r;
 }
 
-// partial[blk][k] = sum over the block's element range of conj(V_k[e]) w[e]
-// partial[blk][k] = sum over the block's segment of conj(V_k) w.  The
-// vectors are taken KC at a time: each thread keeps KC complex sums, loads
-// its w elements once per chunk, and the block reduces the 2*KC sums with one
-// LDS pass (a tall-skinny V^H w, bound by reading V).
+// partial[seg][k] = sum over segment seg of conj(V_k) w (a tall-skinny V^H w,
+// bound by reading V once).  Grid (segments, chunks of KC vectors): a block
+// streams its whole segment for its KC vectors, each thread keeping KC
+// complex sums, and reduces the 2*KC sums once at the end.  Few enough
+// segments that every thread walks many elements keeps the loads in flight
+// instead of spending the block in reductions.
 constexpr int KC = 8;
 __global__ __launch_bounds__(KB) void multidot_kernel(const c128* __restrict__ V, long long stride,
                                                       int nvec, const c128* __restrict__ w,
@@ -51,39 +52,64 @@ __global__ __launch_bounds__(KB) void multidot_kernel(const c128* __restrict__ V
   const long long lo = (long long)blockIdx.x * per;
   const long long hi = min(len, lo + per);
   const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
-  for (int k0 = 0; k0 < nvec; k0 += KC) {
-    double sr[KC], si[KC];
+  const int k0 = blockIdx.y * KC;
+  const int nk = min(KC, nvec - k0);
+  const c128* Vk = V + (size_t)k0 * stride;
+  double sr[KC], si[KC];
 #pragma unroll
-    for (int i = 0; i < KC; ++i) sr[i] = si[i] = 0.0;
-    const int nk = min(KC, nvec - k0);
-    for (long long e = lo + threadIdx.x; e < hi; e += blockDim.x) {
+  for (int i = 0; i < KC; ++i) sr[i] = si[i] = 0.0;
+  if (nk == KC) {
+#pragma unroll 2
+    for (long long e = lo + threadIdx.x; e < hi; e += KB) {
+      const c128 b = w[e];
+#pragma unroll
+      for (int i = 0; i < KC; ++i) {
+        const c128 a = Vk[(size_t)i * stride + e];
+        sr[i] += a.re * b.re + a.im * b.im;
+        si[i] += a.re * b.im - a.im * b.re;
+      }
+    }
+  } else {
+    for (long long e = lo + threadIdx.x; e < hi; e += KB) {
       const c128 b = w[e];
 #pragma unroll
       for (int i = 0; i < KC; ++i) {
         if (i < nk) {
-          const c128 a = V[(size_t)(k0 + i) * stride + e];
+          const c128 a = Vk[(size_t)i * stride + e];
           sr[i] += a.re * b.re + a.im * b.im;
           si[i] += a.re * b.im - a.im * b.re;
         }
       }
     }
-#pragma unroll
-    for (int i = 0; i < KC; ++i) {
-      const double r = warp_sum(sr[i]), m = warp_sum(si[i]);
-      if (ln == 0) {
-        sh[wv][2 * i] = r;
-        sh[wv][2 * i + 1] = m;
-      }
-    }
-    __syncthreads();
-    if (threadIdx.x < 2 * nk) {
-      double s = 0.0;
-      for (int q = 0; q < (int)(blockDim.x >> 6); ++q) s += sh[q][threadIdx.x];
-      double* out = reinterpret_cast<double*>(partial + (size_t)blockIdx.x * nvec + k0);
-      out[threadIdx.x] = s;
-    }
-    __syncthreads();
   }
+#pragma unroll
+  for (int i = 0; i < KC; ++i) {
+    const double r = warp_sum(sr[i]), m = warp_sum(si[i]);
+    if (ln == 0) {
+      sh[wv][2 * i] = r;
+      sh[wv][2 * i + 1] = m;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 2 * nk) {
+    double s = 0.0;
+    for (int q = 0; q < KB / 64; ++q) s += sh[q][threadIdx.x];
+    double* out = reinterpret_cast<double*>(partial + (size_t)blockIdx.x * nvec + k0);
+    out[threadIdx.x] = s;
+  }
+}
+
+// Segments of a multidot over nvec vectors: about 2048 blocks in all, at
+// most nblk segments (the rows of the partial-sum buffer).  Depends only on
+// (len, nvec, nblk), so the reduction order is fixed for a given step.
+int multidot_segments(long long len, int nvec, int nblk) {
+  const int nch = (nvec + KC - 1) / KC;
+  long long seg = (2048 + nch - 1) / nch;
+  const long long by_len = (len + 4 * KB - 1) / (4 * KB);  // >= 4 elements per thread
+  if (seg > by_len) seg = by_len;
+  if (seg > nblk) seg = nblk;
+  if (seg < 1) seg = 1;
+  return (int)seg;
 }
 
 // out[k] = sum_blk partial[blk][k] (+ add[k]); one block per k
@@ -111,7 +137,8 @@ __global__ __launch_bounds__(KB) void reduce_dots_kernel(const c128* __restrict_
   }
 }
 
-// w += sign * sum_k V_k h_k
+// w += sign * sum_k V_k h_k (the loop over k unrolled so that several
+// vectors' loads are in flight per thread)
 __global__ void update_kernel(c128* __restrict__ w, const c128* __restrict__ V, long long stride,
                               int nvec, const c128* __restrict__ h, long long len, double sign,
                               const int* __restrict__ stop) {
@@ -119,6 +146,7 @@ __global__ void update_kernel(c128* __restrict__ w, const c128* __restrict__ V, 
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= len) return;
   double sr = 0.0, si = 0.0;
+#pragma unroll 8
   for (int k = 0; k < nvec; ++k) {
     const c128 v = V[(size_t)k * stride + e];
     const c128 c = h[k];
@@ -239,10 +267,12 @@ void unpack_slots(hipStream_t st, const Geometry& g, const SlotMaps& m, int R, c
   hipLaunchKernelGGL(unpack_kernel, dim3(nb_of(total)), dim3(KB), 0, st, in, out, m,
                      (long long)g.n, total);
 }
-void k_multidot(hipStream_t st, const c128* V, long long stride, int nvec, const c128* w,
-                long long len, c128* partial, int nblk, const int* stop) {
-  hipLaunchKernelGGL(multidot_kernel, dim3(nblk), dim3(KB), 0, st, V, stride, nvec, w, len,
-                     partial, stop);
+int k_multidot(hipStream_t st, const c128* V, long long stride, int nvec, const c128* w,
+               long long len, c128* partial, int nblk, const int* stop) {
+  const int nseg = multidot_segments(len, nvec, nblk);
+  hipLaunchKernelGGL(multidot_kernel, dim3(nseg, (nvec + KC - 1) / KC), dim3(KB), 0, st, V, stride,
+                     nvec, w, len, partial, stop);
+  return nseg;
 }
 void k_reduce_dots(hipStream_t st, const c128* partial, int nblk, int nvec, c128* out,
                    const c128* add, const int* stop) {
