@@ -127,6 +127,54 @@ def copy_calibration(torch, mib=512):
     del x, y
 
 
+def tune_matvec(ctx, args, n_rhs):
+    """Block-matvec kernel of each precision: fixed by --matvec-config, else
+    autotuned on the context's geometry (set-up, outside any timed region)."""
+    tuned = {}
+    fixed = {}
+    for spec in args.matvec_config:
+        prec, v, items = spec.split(":")
+        fixed[prec] = (int(v), int(items))
+    for prec in ("mixed", "fp64"):
+        if prec in fixed:
+            ctx.set_matvec_config(prec, *fixed[prec])
+            tuned[prec] = {"variant": fixed[prec][0], "items": fixed[prec][1], "fixed": True}
+            log(f"[bench] {prec} matvec fixed: variant {fixed[prec][0]}, items {fixed[prec][1]}")
+        elif not args.no_autotune:
+            ms, conf = ctx.autotune(n_rhs, prec)
+            tuned[prec] = {"block_matvec_ms": ms, "variant": conf[0], "items": conf[1]}
+            log(f"[bench] autotune {prec}: {ms:.3f} ms, variant {conf[0]}, items {conf[1]}")
+    return tuned
+
+
+def isolated_matvec(ctx, n_rhs, reps):
+    """Average block-matvec launch of each precision over `reps` back-to-back
+    forward operators on a seeded random vector (HIP events on the library's
+    stream), with the algorithmic FP32 / FP64 rate against the matrix peak."""
+    import torch
+
+    rng = np.random.default_rng(0)
+    shape = (n_rhs, ctx.n, ctx.L)
+    x = torch.tensor(rng.normal(size=shape) + 1j * rng.normal(size=shape), dtype=torch.complex128,
+                     device="cuda")
+    mv = {}
+    for which, prec, peak in ((1, "mixed", PEAK_FP32_MFMA), (0, "fp64", PEAK_FP64_MFMA)):
+        ctx.apply_operator(x, "forward", prec)
+        ctx.profile_reset()
+        ctx.profile_enable(True)
+        for _ in range(reps):
+            ctx.apply_operator(x, "forward", prec)
+        ctx.profile_enable(False)
+        ms, launches, flops = ctx.profile_query(which)
+        avg = ms / max(launches, 1) / 1e3
+        tf = flops / avg / 1e12
+        mv[prec] = {"avg_launch_ms": avg * 1e3, "tflops": tf, "peak_tflops": peak, "frac": tf / peak,
+                    "flops_per_launch": flops, "launches": launches}
+        log(f"[bench] {prec} block matvec: {avg*1e3:.3f} ms, {tf:.2f} TFLOP/s ({tf/peak:.1%} of {peak})")
+    ctx.profile_reset()
+    return mv
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -156,6 +204,8 @@ def main():
                          "ends it on a cycle boundary, where a later run can resume exactly)")
     ap.add_argument("--tile-x0", default="", help="c5: .npy start vector of the --tile-rhs solve")
     ap.add_argument("--tile-save", default="", help="c5: .npy file for the --tile-rhs solution")
+    ap.add_argument("--cyl-max-iter", type=int, default=5000,
+                    help="cyl6: Arnoldi steps allowed to the solve of each step")
     ap.add_argument("--matvec-config", action="append", default=[], metavar="PREC:VARIANT:ITEMS",
                     help="fix the block-matvec kernel of a precision (mixed or fp64) instead of "
                          "autotuning it, e.g. mixed:9:16384")
@@ -172,6 +222,8 @@ def main():
         return bench_tile(args)
     if args.config == "jinc":
         return bench_jinc_padding(args)
+    if args.config == "cyl6":
+        return bench_cylinders(args)
 
     import torch
 
@@ -192,20 +244,7 @@ def main():
 
     # set-up outside the timed region: kernel variant / work split per precision
     ctx.set_geometry(pos, wl.K, lmax)
-    tuned = {}
-    fixed = {}
-    for spec in args.matvec_config:
-        prec, v, items = spec.split(":")
-        fixed[prec] = (int(v), int(items))
-    for prec in ("mixed", "fp64"):
-        if prec in fixed:
-            ctx.set_matvec_config(prec, *fixed[prec])
-            tuned[prec] = {"variant": fixed[prec][0], "items": fixed[prec][1], "fixed": True}
-            log(f"[bench] {prec} matvec fixed: variant {fixed[prec][0]}, items {fixed[prec][1]}")
-        elif not args.no_autotune:
-            ms, conf = ctx.autotune(len(kh), prec)
-            tuned[prec] = {"block_matvec_ms": ms, "variant": conf[0], "items": conf[1]}
-            log(f"[bench] autotune {prec}: {ms:.3f} ms, variant {conf[0]}, items {conf[1]}")
+    tuned = tune_matvec(ctx, args, len(kh))
 
     def step(precision):
         ctx.set_geometry(pos, wl.K, lmax)
@@ -255,24 +294,7 @@ def main():
         fp64["mixed_vs_fp64_rel_diff"] = float(d)
 
     # block-matvec throughput in isolation (same kernels, back to back)
-    rng = np.random.default_rng(0)
-    x = torch.tensor(rng.normal(size=(len(kh), N, ctx.L)) + 1j * rng.normal(size=(len(kh), N, ctx.L)),
-                     dtype=torch.complex128, device=dev)
-    mv = {}
-    for which, prec, peak in ((1, "mixed", PEAK_FP32_MFMA), (0, "fp64", PEAK_FP64_MFMA)):
-        ctx.apply_operator(x, "forward", prec)
-        ctx.profile_reset()
-        ctx.profile_enable(True)
-        for _ in range(args.matvec_reps):
-            ctx.apply_operator(x, "forward", prec)
-        ctx.profile_enable(False)
-        ms, launches, flops = ctx.profile_query(which)
-        avg = ms / max(launches, 1) / 1e3
-        tf = flops / avg / 1e12
-        mv[prec] = {"avg_launch_ms": avg * 1e3, "tflops": tf, "peak_tflops": peak, "frac": tf / peak,
-                    "flops_per_launch": flops, "launches": launches}
-        log(f"[bench] {prec} block matvec: {avg*1e3:.3f} ms, {tf:.2f} TFLOP/s ({tf/peak:.1%} of {peak})")
-    ctx.profile_reset()
+    mv = isolated_matvec(ctx, len(kh), args.matvec_reps)
 
     # algorithmic bytes of one complex64 matvec: table + input + output
     L = ctx.L
@@ -463,6 +485,106 @@ def near_field_plane(ctx, s, cfg):
         f"VALU issue {roof['frac'] if roof else None}")
     return {"points": pts.shape[0], "ms": ms, "pair_rhs_per_s": pairs / ms * 1e3,
             "max_abs": float(E.abs().max()), "roofline": roof}
+
+
+def bench_cylinders(args):
+    """100 x 100 lattice of silicon cylinders at lmax 6 (9.6e5 unknowns, dense
+    null-field T per cylinder).  One step is the sphere workloads' step with
+    the T-matrices built by the null-field kernel: translation table, T,
+    plane-wave right-hand side, mixed-precision GMRES to 1e-8 and the far
+    field.  Then the lmax-6 block matvec in isolation in both precisions."""
+    import torch
+
+    import workloads as wl
+    from paper_2107_09879_amd import tmhip
+
+    pos, radii, kh, po, cfg = wl.config_inputs("cyl6")
+    n, lmax, R = cfg["nx"], cfg["lmax"], len(kh)
+    height, n_rel = cfg["cylinders"]
+    N = n * n
+    tol = cfg["tol"]
+    restart = args.restart or cfg["restart"]
+    ctx = tmhip.Context(0)
+    radii_d = torch.tensor(radii, dtype=torch.float64, device="cuda")
+    dirs = torch.tensor([[0.0, 0.0, 1.0], [0.0, 0.0, -1.0]], dtype=torch.float64, device="cuda")
+    ctx.set_geometry(pos, wl.K, lmax)
+    log(f"[bench] cylinders: N={N}, lmax={lmax}, L={ctx.L}, restart {restart}")
+    tuned = tune_matvec(ctx, args, R)
+
+    def progress(cycles, iters, n_live, worst):
+        if cycles % 5 == 0:
+            log(f"[bench] cycle {cycles}, iters {iters}, residual {worst:.2e}")
+
+    ctx.set_progress(progress)
+
+    def step(precision):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.set_geometry(pos, wl.K, lmax)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ctx.set_cylinders(radii_d, height, n_rel)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        a0 = ctx.plane_wave_rhs(kh, po)
+        s, info = ctx.solve(a0, tol=tol, restart=restart, precision=precision, inner_tol=1e-4,
+                            max_iter=args.cyl_max_iter)
+        F = ctx.far_field(s, dirs)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        return s, info, F, {"table_s": t1 - t0, "tmatrix_s": t2 - t1, "rhs_solve_farfield_s": t3 - t2}
+
+    for w in range(args.warmup):
+        _, info, _, ph = step("mixed")
+        log(f"[bench] warmup {w}: {info[0]}, {ph}")
+    ctx.profile_reset()
+    ctx.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        s, info, F, ph = step("mixed")
+        log(f"[bench] step {k}: {info[0]}, {ph}")
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    ctx.profile_enable(False)
+    live = {}
+    for which, prec, peak in ((1, "mixed", PEAK_FP32_MFMA), (0, "fp64", PEAK_FP64_MFMA)):
+        ms, launches, flops = ctx.profile_query(which)
+        if launches:
+            avg = ms / launches / 1e3
+            live[prec] = {"avg_launch_ms": avg * 1e3, "launches": launches, "flops_per_launch": flops,
+                          "tflops": flops / avg / 1e12, "frac": flops / avg / 1e12 / peak}
+    ctx.profile_reset()
+    ctx.set_progress(None)
+    log(f"[bench] cylinders time-to-solution {dt:.3f} s/step, matvec {live}")
+    mv = isolated_matvec(ctx, R, args.matvec_reps)
+    dom = live.get("mixed", mv["mixed"])
+    variant = ctx.get_matvec_config("mixed")[0]
+    knames = kernel_names(variant, "float")
+    if n % 16 == 0:
+        knames = knames[:1]
+    L = ctx.L
+    alg_bytes = (2 * n - 1) ** 2 * (L * L // 2) * 8 + 2 * N * L * 8
+    out = {"metric": "time-to-solution at 1e-8 residual + translation-matvec GB/s, 1e4-1e5 scatterers",
+           "value": dt, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": dt * 1e3, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+           "dtype": "c64+f64", "data": "synthetic",
+           "config": {"workload": cfg["name"], "scatterers": N, "lmax": lmax, "unknowns": N * L,
+                      "rhs": R, "tol": tol, "restart": restart, "precision": "mixed",
+                      "scatterer": "silicon cylinder, null-field T"},
+           "solve_info": info[0], "phases_s": ph, "autotuned": tuned,
+           "matvec_timed_region": live, "matvec_isolated": mv,
+           "matvec_algorithmic_GBps": alg_bytes / (dom["avg_launch_ms"] / 1e3) / 1e9,
+           "roofline": {"bound": "mfma", "achieved": dom["tflops"], "peak": PEAK_FP32_MFMA,
+                        "unit": "TFLOP/s", "frac": dom["tflops"] / PEAK_FP32_MFMA,
+                        "mfma_issue_frac": dom["tflops"] * mfma_issue_ratio(lmax) / PEAK_FP32_MFMA,
+                        "effective_ceiling_tflops": PEAK_FP32_MFMA / mfma_issue_ratio(lmax),
+                        "traffic": measured_traffic(knames, cfg["name"]),
+                        "kernel": " + ".join(knames), "avg_launch_ms": dom["avg_launch_ms"],
+                        "flops_per_launch": dom["flops_per_launch"],
+                        "kernel_source_digest": kernel_source_digest()}}
+    print(json.dumps(out), flush=True)
+    ctx.close()
 
 
 def bench_batched(args):

@@ -7,7 +7,10 @@
   * the near field and its transpose past one LDS chunk of spheres and one
     tile of points, and at the 300 x 300 lens tile on sampled plane points;
   * the four smallest and four largest of the 48 lens subregions, batched at
-    GMRES(200), each checked through oracle residual rows.
+    GMRES(200), each checked through oracle residual rows;
+  * the 100 x 100 silicon-cylinder lattice at lmax 6 (dense null-field T) in
+    its autotuned launch configurations: the coupling product on sampled rows
+    and the forward operator on the centre row.
 Row residuals are ||s_rows - t A_rows s - t a0_rows|| / ||t a0_rows||."""
 import numpy as np
 import pytest
@@ -18,6 +21,7 @@ if not torch.cuda.is_available():
 
 import oracle  # noqa: E402
 import workloads as wl  # noqa: E402
+from oracle.ebcm import cylinder_surface, ebcm_tmatrix  # noqa: E402
 from paper_2107_09879_amd import tmhip  # noqa: E402
 
 pytestmark = pytest.mark.gpu
@@ -188,4 +192,48 @@ def test_c3_smallest_and_largest_subregions():
         print(f"  subregion {k} {subs[k]}: iters {info[k][0]['iters']}, oracle row residual {res:.2e}",
               flush=True)
         assert res < 5e-8
+    ctx.close()
+
+
+def test_cyl6_cylinder_lattice_operator_sampled():
+    """100 x 100 silicon cylinders at lmax 6 with the kernels the benchmark
+    autotunes.  The coupling product of a vector living on 8 sites is checked
+    on 32 target rows (corners, centre, the sources themselves, random) with
+    the oracle's row routine over just those sites; the forward operator
+    x - T A x of a dense random vector on the centre row with the oracle's
+    full row of A and its null-field T of that cylinder."""
+    print("[case] cyl6 operator sampled", flush=True)
+    pos, radii, kh, po, cfg = wl.config_inputs("cyl6")
+    height, n_rel = cfg["cylinders"]
+    n, lmax = cfg["nx"], cfg["lmax"]
+    N = n * n
+    ctx = tmhip.Context(0)
+    ctx.set_geometry(pos, K, lmax)
+    ctx.set_cylinders(to_dev(radii, torch.float64), height, n_rel)
+    L = ctx.L
+    rng = np.random.default_rng(66)
+    src = [0, n - 1, N // 2 + n // 2, N - n, N - 1] + [int(v) for v in rng.choice(N, 3, replace=False)]
+    xs = np.zeros((1, N, L), dtype=complex)
+    xs[0, src] = rng.normal(size=(len(src), L)) + 1j * rng.normal(size=(len(src), L))
+    rows = list(dict.fromkeys(src + [1, n, 2 * n + 3] + [int(v) for v in rng.choice(N, 32, replace=False)]))[:32]
+    ref = []
+    for j in rows:
+        others = [i for i in src if i != j]
+        sub = np.concatenate([xs[0, [j]] * 0.0, xs[0, others]])
+        ref.append(oracle.rows_A(pos[[j] + others], K, lmax, sub, [0])[0])
+    ref = np.array(ref)
+    x = rng.normal(size=(1, N, L)) + 1j * rng.normal(size=(1, N, L))
+    c = N // 2 + n // 2
+    Tc = ebcm_tmatrix(lmax, K, n_rel, cylinder_surface(radii[c], height, 96))
+    fref = x[0, c] - Tc @ oracle.rows_A(pos, K, lmax, x[0], [c])[0]
+    for prec, tol in (("fp64", 1e-12), ("mixed", 2e-5)):
+        ms, conf = ctx.autotune(1, prec)
+        y = host(ctx.apply_operator(to_dev(xs), "coupling", prec))[0]
+        e = rel(y[rows], ref)
+        f = host(ctx.apply_operator(to_dev(x), "forward", prec))[0, c]
+        ef = rel(f, fref)
+        print(f"  {prec} (variant {conf[0]}, items {conf[1]}): sampled rows {e:.2e}, "
+              f"forward centre row {ef:.2e}", flush=True)
+        assert e < tol
+        assert ef < tol
     ctx.close()

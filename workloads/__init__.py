@@ -12,7 +12,9 @@ iy*nx + ix.  Radii come from numpy.random.default_rng(seed) in index order.
 
 The paper's scatterers are silicon cylinders taken from external libraries
 (App. III); those libraries are not available, so these spheres stand in for
-them, with lattice sizes matching the paper's per-GPU subregion scale.
+them, with lattice sizes matching the paper's per-GPU subregion scale.  The
+"cyl6" workload puts silicon cylinders of the paper's dimensions on its
+lattice instead (T-matrices from the null-field method, lmax 6).
 """
 import numpy as np
 
@@ -20,6 +22,13 @@ WAVELENGTH = 1.0
 K = 2.0 * np.pi / WAVELENGTH
 PITCH = 0.6
 N_REL = 2.0
+
+
+# the paper's meta-atoms in wavelength units: silicon cylinders (n = 3.48) of
+# height 940 nm on a 1070 nm square lattice at 1550 nm
+CYL_N_REL = 3.48
+CYL_HEIGHT = 0.94 / 1.55
+CYL_PITCH = 1.07 / 1.55
 
 
 def lattice_positions(nx, ny=None, pitch=PITCH):
@@ -95,6 +104,9 @@ CONFIGS = {
                radii=(0.12, 0.28), rhs=["x"], detector=(74.5 * PITCH, 74.5 * PITCH, 50.0)),
     "c5": dict(name="300x300 lens tile, lmax 3, 2 RHS", nx=300, lmax=3, lens=True,
                rhs=["x", "y"], tol=1e-8, restart=50, plane=(1000, 299 * PITCH, 5.0)),
+    "cyl6": dict(name="100x100 silicon-cylinder lattice, lmax 6 (9.6e5 unknowns)", nx=100, lmax=6,
+                 seed=6, radii=(0.05, 0.16), pitch=CYL_PITCH, cylinders=(CYL_HEIGHT, CYL_N_REL),
+                 rhs=["x"], tol=1e-8, restart=200),
 }
 
 
@@ -102,7 +114,7 @@ def config_inputs(key):
     """(positions [N,3], radii [N], khat [R,3], pol [R,3], cfg) for a config."""
     cfg = CONFIGS[key]
     n = cfg["nx"]
-    pos = lattice_positions(n, n)
+    pos = lattice_positions(n, n, cfg.get("pitch", PITCH))
     if cfg.get("lens"):
         radii = lens_radii(n, n)
     else:
