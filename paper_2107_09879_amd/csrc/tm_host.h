@@ -1,5 +1,6 @@
 // Host-only helpers of libtmhip that need no GPU: the LDS block-matvec work
-// planner and the Wigner 3j symbol of the translation coefficients.  Plain
+// planner, the azimuthal-order blocks of a dense T and the Wigner 3j symbol
+// of the translation coefficients.  Plain
 // C++17 (no HIP), so that a CPU build under the address and undefined-
 // behaviour sanitizers can exercise them (tests/host_sanitize.cpp).
 #pragma once
@@ -9,6 +10,46 @@
 #include <vector>
 
 namespace tmh {
+
+// ---------------------------------------------------------------- m-blocks
+// Blocks of the coefficient index by azimuthal order m, for the boundary
+// order n = p lmax(lmax+2) + l(l+1) - 1 + m (p = 0, 1; l = 1..lmax;
+// |m| <= l): block b = m + lmax holds the 2(lmax - max(1,|m|) + 1) indices
+// with that m in increasing n.  A dense T that is zero between different m
+// (a scatterer symmetric about the z axis) is kept as these square blocks,
+// `per_site` complex numbers per scatterer.  Sized for lmax <= 6.
+constexpr int MB_LM_MAX = 96, MB_BLK_MAX = 13;
+struct MbMaps {
+  int blk_of[MB_LM_MAX];  // n -> block
+  int q_of[MB_LM_MAX];    // n -> row within its block
+  int mem[MB_LM_MAX];     // block members, block after block
+  int first[MB_BLK_MAX], nm[MB_BLK_MAX], off[MB_BLK_MAX];
+  int nblk, per_site;
+};
+
+inline void host_mblock_maps(int lmax, MbMaps& mb) {
+  mb = MbMaps{};
+  const int half = lmax * (lmax + 2), L = 2 * half;
+  mb.nblk = 2 * lmax + 1;
+  int k = 0, off = 0;
+  for (int b = 0; b < mb.nblk; ++b) {
+    mb.first[b] = k;
+    for (int n = 0; n < L; ++n) {
+      const int r = n % half;  // l(l+1) - 1 + m
+      int l = 1;
+      while ((l + 1) * (l + 1) - 1 <= r) ++l;
+      const int m = r - (l * (l + 1) - 1);
+      if (m + lmax != b) continue;
+      mb.blk_of[n] = b;
+      mb.q_of[n] = k - mb.first[b];
+      mb.mem[k++] = n;
+    }
+    mb.nm[b] = k - mb.first[b];
+    mb.off[b] = off;
+    off += mb.nm[b] * mb.nm[b];
+  }
+  mb.per_site = off;
+}
 
 // Work item of the LDS-staged block matvec: a target tile of a (sub)lattice
 // and a range [b0, b1) of its displacement blocks.

@@ -59,20 +59,8 @@ struct SlotMaps {
   int L, lmax, S;
 };
 
-// Blocks of the coefficient index by azimuthal order m (boundary order n =
-// p*lmax(lmax+2) + l(l+1) - 1 + m): block b = m + lmax holds the 2(lmax -
-// max(1,|m|) + 1) indices with that m in increasing n.  A dense T that is
-// zero between different m (a scatterer symmetric about the z axis) is kept
-// as these square blocks only, `per_site` complex numbers per scatterer.
-constexpr int MBLK_MAX = 2 * LMAX_SUPPORTED + 1;
-struct MbMaps {
-  int blk_of[LM_MAX];  // n -> block
-  int q_of[LM_MAX];    // n -> row within its block
-  int mem[LM_MAX];     // block members, block after block
-  int first[MBLK_MAX], nm[MBLK_MAX], off[MBLK_MAX];
-  int nblk, per_site;
-};
-void host_mblock_maps(int lmax, MbMaps& mb);
+static_assert(MB_LM_MAX == LM_MAX && MB_BLK_MAX == 2 * LMAX_SUPPORTED + 1,
+              "m-block maps sized for the supported lmax");
 
 // Scatterer centres in the z = 0 plane as kernels see them: on a lattice
 // they follow from the site index, otherwise from a device array [N][2].

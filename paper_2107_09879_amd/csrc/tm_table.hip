@@ -92,28 +92,6 @@ void host_slot_maps(int lmax, Geometry& g, SlotMaps& mp) {
     for (int s = 0; s < SMAX; ++s) mp.n_of[c][s] = s < g.S ? g.n_of[c][s] : -1;
 }
 
-void host_mblock_maps(int lmax, MbMaps& mb) {
-  mb = MbMaps{};
-  const int L = 2 * lmax * (lmax + 2);
-  mb.nblk = 2 * lmax + 1;
-  int k = 0, off = 0;
-  for (int b = 0; b < mb.nblk; ++b) {
-    mb.first[b] = k;
-    for (int n = 0; n < L; ++n) {
-      int p, l, m;
-      plm_of(n, lmax, p, l, m);
-      if (m + lmax != b) continue;
-      mb.blk_of[n] = b;
-      mb.q_of[n] = k - mb.first[b];
-      mb.mem[k++] = n;
-    }
-    mb.nm[b] = k - mb.first[b];
-    mb.off[b] = off;
-    off += mb.nm[b] * mb.nm[b];
-  }
-  mb.per_site = off;
-}
-
 // Host constants: coef[c][i][j][q] (i target slot, j source slot) and
 // dm[c][i][j] = m_src - m_tgt, sig[c][i] = (-1)^(l+p).
 static void host_table_constants(const Geometry& g, int Q, std::vector<double>& coef,

@@ -9,6 +9,10 @@
 //    relative to the wave, blocks, per-wave clipping, column-group mask)
 //    touches every (target, source) pair of the lattice exactly once;
 //  * the planner's work per block equals the replay's MFMA count per block.
+// m-block checks (lmax 1..6): the blocks partition the coefficient index,
+// every member has the block's m, sizes 2(lmax - max(1,|m|) + 1), members in
+// increasing order, offsets and rows consistent, 872 entries per scatterer
+// at lmax 6.
 // 3j checks: closed forms, selection rules and the orthogonality sum.
 #include <cmath>
 #include <cstdio>
@@ -176,6 +180,42 @@ static void check_3j() {
           }
 }
 
+static void check_mblocks() {
+  for (int lmax = 1; lmax <= 6; ++lmax) {
+    MbMaps mb;
+    host_mblock_maps(lmax, mb);
+    const int L = 2 * lmax * (lmax + 2);
+    std::vector<int> seen(L, 0);
+    int off = 0;
+    CHECK(mb.nblk == 2 * lmax + 1, "lmax %d nblk %d", lmax, mb.nblk);
+    for (int b = 0; b < mb.nblk; ++b) {
+      const int m = b - lmax, am = m < 0 ? -m : m;
+      const int want = 2 * (lmax - (am > 1 ? am : 1) + 1);
+      CHECK(mb.nm[b] == want, "lmax %d m %d size %d want %d", lmax, m, mb.nm[b], want);
+      CHECK(mb.off[b] == off, "lmax %d m %d offset", lmax, m);
+      off += mb.nm[b] * mb.nm[b];
+      for (int q = 0; q < mb.nm[b]; ++q) {
+        const int n = mb.mem[mb.first[b] + q];
+        CHECK(n >= 0 && n < L, "lmax %d member out of range", lmax);
+        if (n < 0 || n >= L) continue;
+        ++seen[n];
+        // m of n from the (p, l, m) enumeration: p-major, then l, then m = -l..l
+        int idx = 0, mn = 99;
+        for (int p = 0; p < 2; ++p)
+          for (int l = 1; l <= lmax; ++l)
+            for (int mm = -l; mm <= l; ++mm, ++idx)
+              if (idx == n) mn = mm;
+        CHECK(mn == m, "lmax %d n %d has m %d, block m %d", lmax, n, mn, m);
+        CHECK(mb.blk_of[n] == b && mb.q_of[n] == q, "lmax %d n %d block/row", lmax, n);
+        if (q > 0) CHECK(mb.mem[mb.first[b] + q - 1] < n, "lmax %d block %d not increasing", lmax, b);
+      }
+    }
+    CHECK(mb.per_site == off, "lmax %d per_site", lmax);
+    for (int n = 0; n < L; ++n) CHECK(seen[n] == 1, "lmax %d n %d seen %d times", lmax, n, seen[n]);
+    if (lmax == 6) CHECK(mb.per_site == 872, "per_site %d at lmax 6", mb.per_site);
+  }
+}
+
 int main() {
   const int shapes[][2] = {{1, 1}, {3, 2}, {16, 16}, {17, 5}, {5, 17}, {33, 47}, {31, 20}, {64, 20}, {100, 100}};
   for (auto& sh : shapes) {
@@ -184,6 +224,7 @@ int main() {
     check_lattice(sh[0], sh[1], 16, 8, 8, 16, 4);   // other block shapes
   }
   check_subregions();
+  check_mblocks();
   check_3j();
   std::printf("%s (%d failures)\n", failures ? "FAILED" : "ok", failures);
   return failures ? 1 : 0;
