@@ -537,6 +537,7 @@ def bench_cylinders(args):
     for w in range(args.warmup):
         _, info, _, ph = step("mixed")
         log(f"[bench] warmup {w}: {info[0]}, {ph}")
+    copy_calibration(torch)
     ctx.profile_reset()
     ctx.profile_enable(True)
     torch.cuda.synchronize()
