@@ -108,7 +108,10 @@ int tm_get_lattice(const tm_ctx* ctx, int* nx, int* ny, double* pitch);
  * (tm_grad_radius returns TM_ERR_STATE), tm_get_tmatrix_diag returns
  * TM_ERR_STATE and tm_solve_batched (diagonal T only) returns TM_ERR_STATE
  * until spheres or a diagonal T are set again.  Entries are not checked for
- * NaN. */
+ * NaN.  A T whose entries between different azimuthal orders m are all
+ * exactly zero (a scatterer symmetric about the z axis) is also packed into
+ * its m-blocks, which the product then reads alone (same terms, same order);
+ * the test runs on the device and the call waits for its one-word result. */
 int tm_set_tmatrix_dense(tm_ctx* ctx, const tm_c128* T);
 
 /* Mie T-matrix of one homogeneous sphere (the sphere case of App. I.B),
