@@ -206,6 +206,8 @@ def main():
     ap.add_argument("--tile-save", default="", help="c5: .npy file for the --tile-rhs solution")
     ap.add_argument("--cyl-max-iter", type=int, default=5000,
                     help="cyl6: Arnoldi steps allowed to the solve of each step")
+    ap.add_argument("--offl-max-iter", type=int, default=5000,
+                    help="offl: Arnoldi steps allowed to the solve of each step")
     ap.add_argument("--matvec-config", action="append", default=[], metavar="PREC:VARIANT:ITEMS",
                     help="fix the block-matvec kernel of a precision (mixed or fp64) instead of "
                          "autotuning it, e.g. mixed:9:16384")
@@ -224,6 +226,8 @@ def main():
         return bench_jinc_padding(args)
     if args.config == "cyl6":
         return bench_cylinders(args)
+    if args.config == "offl":
+        return bench_offlattice(args)
 
     import torch
 
@@ -588,6 +592,114 @@ def bench_cylinders(args):
     ctx.close()
 
 
+OL_SOURCE = "paper_2107_09879_amd/csrc/tm_offlattice.hip"
+
+
+def ol_valu_per_pair(kernel):
+    """VALU lane-instructions per (target, source) pair and right-hand side of
+    the off-lattice kernel from the committed counter summary, or None if the
+    source changed since."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "offlattice_matvec_100x100_lmax3.md")
+    if not os.path.exists(path):
+        return None
+    with open(os.path.join(ROOT, OL_SOURCE), "rb") as fh:
+        digest = hashlib.sha256(fh.read()).hexdigest()[:16]
+    with open(path) as f:
+        for line in f:
+            cells = [c.strip() for c in line.strip().strip("|").split("|")]
+            if len(cells) == 3 and cells[0] == kernel and cells[1] == digest:
+                try:
+                    return float(cells[2])
+                except ValueError:
+                    return None
+    return None
+
+
+def bench_offlattice(args):
+    """100 x 100 lattice with every site jittered in-plane (the 100 x 100
+    workload's spheres): no two pairs share a displacement, so the translation
+    blocks are formed on the fly per (target, source) pair.  One step = the
+    lattice workload's step (geometry, Mie, RHS, mixed GMRES(50) to 1e-8, far
+    field); then the off-lattice operator in isolation in both precisions,
+    the complex64 one against the FP32 VALU issue peak."""
+    import torch
+
+    import workloads as wl
+    from paper_2107_09879_amd import tmhip
+
+    pos, radii, kh, po, cfg = wl.config_inputs("offl")
+    n, lmax, R = cfg["nx"], cfg["lmax"], len(kh)
+    N = n * n
+    restart = args.restart or cfg["restart"]
+    ctx = tmhip.Context(0)
+    ctx.set_geometry(pos, wl.K, lmax)
+    if ctx.get_lattice()[2] != 0.0:
+        raise RuntimeError("the jittered workload was taken for a lattice")
+    radii_d = torch.tensor(radii, dtype=torch.float64, device="cuda")
+    dirs = torch.tensor([[0.0, 0.0, 1.0], [0.0, 0.0, -1.0]], dtype=torch.float64, device="cuda")
+    log(f"[bench] off-lattice: N={N}, lmax={lmax}, restart {restart}")
+
+    def progress(cycles, iters, n_live, worst):
+        if cycles % 5 == 0:
+            log(f"[bench] cycle {cycles}, iters {iters}, residual {worst:.2e}")
+
+    ctx.set_progress(progress)
+
+    def step():
+        ctx.set_geometry(pos, wl.K, lmax)
+        ctx.set_spheres(radii_d, wl.N_REL)
+        a0 = ctx.plane_wave_rhs(kh, po)
+        s, info = ctx.solve(a0, tol=cfg["tol"], restart=restart, precision="mixed", inner_tol=1e-4,
+                            max_iter=args.offl_max_iter)
+        F = ctx.far_field(s, dirs)
+        return s, info, F
+
+    for w in range(args.warmup):
+        _, info, _ = step()
+        log(f"[bench] warmup {w}: {info[0]}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        s, info, F = step()
+        log(f"[bench] step {k}: {info[0]}")
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    ctx.set_progress(None)
+    rng = np.random.default_rng(0)
+    x = torch.tensor(rng.normal(size=(R, N, ctx.L)) + 1j * rng.normal(size=(R, N, ctx.L)),
+                     dtype=torch.complex128, device="cuda")
+    op = {}
+    for prec in ("mixed", "fp64"):
+        ctx.apply_operator(x, "forward", prec)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.matvec_reps):
+            ctx.apply_operator(x, "forward", prec)
+        torch.cuda.synchronize()
+        op[prec] = {"ms": (time.perf_counter() - t1) / args.matvec_reps * 1e3}
+        log(f"[bench] off-lattice {prec} operator: {op[prec]['ms']:.2f} ms")
+    kernel = "offlattice_kernel<float>"
+    ipp = ol_valu_per_pair(kernel)
+    roof = None
+    if ipp is not None:
+        achieved = N * (N - 1) * R * ipp / (op["mixed"]["ms"] * 1e-3)
+        roof = {"bound": "alu", "kernel": kernel, "valu_lane_instr_per_pair": ipp,
+                "achieved": achieved / 1e12, "peak": PEAK_VALU_LANE_INSTR / 1e12,
+                "unit": "T VALU lane-instructions/s", "frac": achieved / PEAK_VALU_LANE_INSTR,
+                "timing": "host clock around the operator (kernel + combine), device synchronised"}
+    out = {"metric": "time-to-solution at 1e-8 residual + translation-matvec GB/s, 1e4-1e5 scatterers",
+           "value": dt, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": dt * 1e3, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+           "dtype": "c64+f64", "data": "synthetic",
+           "config": {"workload": cfg["name"], "scatterers": N, "lmax": lmax, "unknowns": N * ctx.L,
+                      "rhs": R, "tol": cfg["tol"], "restart": restart, "precision": "mixed"},
+           "solve_info": info[0], "operator_isolated": op, "roofline": roof}
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
 def bench_batched(args):
     """Overlapping square subregions (side 20-80 plus a 10-site buffer) of a
     300 x 300 lens layout, 4 right-hand sides each, solved as one batch
@@ -808,6 +920,27 @@ def bench_adjoint(args):
     torch.cuda.synchronize()
     t_grad = time.perf_counter() - t0
     log(f"[bench] forward+adjoint+gradient {t_grad:.2f} s, O={O:.6e}, fwd {info_f[0]}, adj {info_a[0]}")
+    # in-plane position gradient from the same two solutions (coupling, incident and detector
+    # terms); the first call also builds the four FP64 derivative tables
+    gpos = {}
+    for key in ("first_call_s", "s"):
+        if key == "s":
+            ctx.profile_reset()
+            ctx.profile_enable(True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ctx.grad_position(mu, s, a0, khat=kh, xd=xd, w=np.conj(Et)[None])
+        torch.cuda.synchronize()
+        gpos[key] = time.perf_counter() - t1
+    ctx.profile_enable(False)
+    ms, launches, flops = ctx.profile_query(0)
+    if launches:
+        avg = ms / launches / 1e3
+        gpos["derivative_matvecs"] = {"launches": launches, "avg_launch_ms": avg * 1e3,
+                                      "tflops": flops / avg / 1e12,
+                                      "frac": flops / avg / 1e12 / PEAK_FP64_MFMA}
+    ctx.profile_reset()
+    log(f"[bench] position gradient {gpos}")
     idx = np.random.default_rng(5).choice(len(radii), 20, replace=False)[: max(1, args.steps)]
     fd = []
     h = 1e-6
@@ -828,7 +961,8 @@ def bench_adjoint(args):
            "data": "synthetic", "config": {"workload": cfg["name"], "scatterers": len(radii),
                                            "solves": "mixed precision, FP64 true residual 1e-12"},
            "objective": O, "forward": info_f[0], "adjoint": info_a[0],
-           "fd_check": {"indices": idx.tolist(), "step": h, "max_err_rel_to_max_grad": err}}
+           "fd_check": {"indices": idx.tolist(), "step": h, "max_err_rel_to_max_grad": err},
+           "position_gradient": gpos}
     print(json.dumps(out), flush=True)
     ctx.close()
 

@@ -10,7 +10,9 @@
     GMRES(200), each checked through oracle residual rows;
   * the 100 x 100 silicon-cylinder lattice at lmax 6 (dense null-field T) in
     its autotuned launch configurations: the coupling product on sampled rows
-    and the forward operator on the centre row.
+    and the forward operator on the centre row;
+  * the jittered 100 x 100 lattice (off-lattice blocks formed per pair): the
+    coupling product and its transpose on sampled rows.
 Row residuals are ||s_rows - t A_rows s - t a0_rows|| / ||t a0_rows||."""
 import numpy as np
 import pytest
@@ -236,4 +238,33 @@ def test_cyl6_cylinder_lattice_operator_sampled():
               f"forward centre row {ef:.2e}", flush=True)
         assert e < tol
         assert ef < tol
+    ctx.close()
+
+
+def test_offl_jittered_lattice_operator_sampled():
+    """The benchmark's jittered 100 x 100 lattice, where every translation
+    block is formed on the fly: rows of A x and A^T x for a dense random x at
+    corners, centre and random targets, both precisions, against the oracle's
+    row routine."""
+    print("[case] offl operator sampled", flush=True)
+    pos, radii, kh, po, cfg = wl.config_inputs("offl")
+    n, lmax = cfg["nx"], cfg["lmax"]
+    N = n * n
+    ctx = tmhip.Context(0)
+    ctx.set_geometry(pos, K, lmax)
+    assert ctx.get_lattice()[2] == 0.0
+    L = ctx.L
+    rng = np.random.default_rng(77)
+    x = rng.normal(size=(1, N, L)) + 1j * rng.normal(size=(1, N, L))
+    rows = [0, n - 1, N // 2 + n // 2, N - 1] + [int(v) for v in rng.choice(N, 2, replace=False)]
+    ref = oracle.rows_A(pos, K, lmax, x[0], rows)
+    refT = oracle.rows_A(pos, K, lmax, x[0], rows, transpose=True)
+    xd = to_dev(x)
+    for prec, tol in (("fp64", 1e-12), ("mixed", 2e-5)):
+        y = host(ctx.apply_operator(xd, "coupling", prec))[0][rows]
+        yT = host(ctx.apply_operator(xd, "coupling_t", prec))[0][rows]
+        e, eT = rel(y, ref), rel(yT, refT)
+        print(f"  {prec}: rows {e:.2e}, transposed rows {eT:.2e}", flush=True)
+        assert e < tol
+        assert eT < tol
     ctx.close()

@@ -104,6 +104,9 @@ CONFIGS = {
                radii=(0.12, 0.28), rhs=["x"], detector=(74.5 * PITCH, 74.5 * PITCH, 50.0)),
     "c5": dict(name="300x300 lens tile, lmax 3, 2 RHS", nx=300, lmax=3, lens=True,
                rhs=["x", "y"], tol=1e-8, restart=50, plane=(1000, 299 * PITCH, 5.0)),
+    "offl": dict(name="100x100 jittered lattice (off-lattice blocks), lmax 3 (3e5 unknowns)", nx=100,
+                 lmax=3, seed=2, radii=(0.15, 0.25), rhs=["x"], tol=1e-8, restart=50,
+                 jitter=(0.035, 8)),
     "cyl6": dict(name="100x100 silicon-cylinder lattice, lmax 6 (9.6e5 unknowns)", nx=100, lmax=6,
                  seed=6, radii=(0.05, 0.16), pitch=CYL_PITCH, cylinders=(CYL_HEIGHT, CYL_N_REL),
                  rhs=["x"], tol=1e-8, restart=200),
@@ -115,6 +118,11 @@ def config_inputs(key):
     cfg = CONFIGS[key]
     n = cfg["nx"]
     pos = lattice_positions(n, n, cfg.get("pitch", PITCH))
+    if cfg.get("jitter"):
+        # every site moved in-plane by up to amp in x and in y (seeded), so that no
+        # two sites share a displacement and the per-displacement table does not apply
+        amp, jseed = cfg["jitter"]
+        pos[:, :2] += np.random.default_rng(jseed).uniform(-amp, amp, (n * n, 2))
     if cfg.get("lens"):
         radii = lens_radii(n, n)
     else:
