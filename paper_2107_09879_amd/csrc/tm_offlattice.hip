@@ -17,6 +17,7 @@
 // modulo 2 pi in FP64 before the FP32 sine and cosine).
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "tm_internal.h"
 
@@ -47,6 +48,36 @@ __device__ inline void ol_hankel(double kr, int qmax, T* hr, T* hi) {
   hr[1] = -(c * x - s) * ix * ix;
   hi[1] = -(s * x + c) * ix * ix;
   for (int q = 1; q < qmax; ++q) {
+    const T f = (T)(2 * q + 1) * ix;
+    hr[q + 1] = f * hr[q] - hr[q - 1];
+    hi[q + 1] = f * hi[q] - hi[q - 1];
+  }
+}
+
+// h_q(kr), q = 0..Q-1 (Q >= 3 a template argument), as ol_hankel
+template <typename T, int Q>
+__device__ inline void ol_hankel_fixed(double kr, T* hr, T* hi) {
+  const double twopi = 6.283185307179586476925286766559;
+  const double red = kr - twopi * rint(kr / twopi);
+  T s, c;
+  if (sizeof(T) == 4) {
+    float sf, cf;
+    sincosf((float)red, &sf, &cf);
+    s = (T)sf;
+    c = (T)cf;
+  } else {
+    double sd, cd;
+    sincos(red, &sd, &cd);
+    s = (T)sd;
+    c = (T)cd;
+  }
+  const T x = (T)kr, ix = (T)1 / x;
+  hr[0] = s * ix;
+  hi[0] = -c * ix;
+  hr[1] = -(c * x - s) * ix * ix;
+  hi[1] = -(s * x + c) * ix * ix;
+#pragma unroll
+  for (int q = 1; q < Q - 1; ++q) {
     const T f = (T)(2 * q + 1) * ix;
     hr[q + 1] = f * hr[q] - hr[q - 1];
     hi[q + 1] = f * hi[q] - hi[q - 1];
@@ -133,6 +164,128 @@ __global__ __launch_bounds__(OL_THREADS) void offlattice_kernel(
   for (int i = 0; i < S; ++i) out[i] = cplx<T>{yr[i], yi[i]};
 }
 
+// The same product for lmax <= 3 with every loop over coefficients unrolled
+// (lmax a template argument): the Hankel values, phases, the source vector
+// and the output accumulators sit in registers at fixed places and the
+// constants (in T: the complex64 kernel reads an FP32 copy) are scalar loads
+// at fixed offsets.  The phase of an entry is split as
+//   e^{i (m_j - m_i) phi} = e^{i d_j phi} e^{-i d_i phi},  d_j = m_j - m_0
+// (d_j = dm[c][0][j]): the source vector is rotated once per (pair, j) and
+// the sum over j once per (pair, i), instead of once per entry.  For the
+// transposed operator (entry (j, i), displacement source - target) the two
+// rotations change sign.
+template <typename T, int Q>
+__device__ inline void ol_rot(const T* er, const T* ei, int d, T& pr, T& pi) {
+  const int ad = d < 0 ? -d : d;
+  pr = er[0];
+  pi = ei[0];
+#pragma unroll
+  for (int u = 1; u < Q; ++u)
+    if (u == ad) {
+      pr = er[u];
+      pi = ei[u];
+    }
+  if (d < 0) pi = -pi;
+}
+
+template <typename T, int LMAX>
+__global__ __launch_bounds__(OL_THREADS) void offlattice_small_kernel(
+    const double* __restrict__ xy, const cplx<T>* __restrict__ x, const T* __restrict__ coef,
+    const int* __restrict__ dm, int N, double k, int chunk, int transpose,
+    cplx<T>* __restrict__ partial, const int* __restrict__ stop) {
+  constexpr int Q = 2 * LMAX + 1;           // Hankel orders and phase powers
+  constexpr int NH = LMAX * (LMAX + 2);     // members of a class
+  constexpr int S = 16 * ((NH + 15) / 16);  // slots of a class
+  if (stop && *stop) return;  // a stopped GMRES cycle
+  extern __shared__ double ol_lds[];
+  double* sxy = ol_lds;                                            // [OL_GROUP][2]
+  cplx<T>* sx = reinterpret_cast<cplx<T>*>(ol_lds + 2 * OL_GROUP);  // [OL_GROUP][S]
+  const int t = blockIdx.x * OL_THREADS + threadIdx.x;
+  const int rc = blockIdx.y;  // r * 2 + c
+  const int c = rc & 1;
+  const int s0 = blockIdx.z * chunk, s1 = min(N, s0 + chunk);
+  const bool live = t < N;
+  const double xt = live ? xy[2 * t] : 0.0, yt = live ? xy[2 * t + 1] : 0.0;
+  const cplx<T>* xin = x + (size_t)rc * N * S;
+  const T* cf = coef + (size_t)c * S * S * Q * 2;
+  const int* dmc = dm + (size_t)c * S * S;
+  const int sg = transpose ? -1 : 1;
+  int d[NH];
+#pragma unroll
+  for (int j = 0; j < NH; ++j) d[j] = sg * dmc[j];  // +-(m_j - m_0)
+  T yr[NH], yi[NH];
+#pragma unroll
+  for (int i = 0; i < NH; ++i) yr[i] = yi[i] = (T)0;
+  for (int g0 = s0; g0 < s1; g0 += OL_GROUP) {
+    const int ng = min(OL_GROUP, s1 - g0);
+    __syncthreads();
+    for (int q = threadIdx.x; q < ng * S; q += OL_THREADS) {
+      const int ss = q / S, j = q % S;
+      sx[q] = xin[(size_t)(g0 + ss) * S + j];
+    }
+    for (int q = threadIdx.x; q < 2 * ng; q += OL_THREADS) sxy[q] = xy[2 * g0 + q];
+    __syncthreads();
+    if (!live) continue;
+    for (int ss = 0; ss < ng; ++ss) {
+      const int s = g0 + ss;
+      if (s == t) continue;
+      // displacement of the block: target - source (source - target for A^T)
+      const double dx = transpose ? sxy[2 * ss] - xt : xt - sxy[2 * ss];
+      const double dy = transpose ? sxy[2 * ss + 1] - yt : yt - sxy[2 * ss + 1];
+      const double r = sqrt(dx * dx + dy * dy);
+      T hr[Q], hi[Q];
+      ol_hankel_fixed<T, Q>(k * r, hr, hi);
+      const T cph = (T)(dx / r), sph = (T)(dy / r);
+      T er[Q], ei[Q];
+      er[0] = (T)1;
+      ei[0] = (T)0;
+#pragma unroll
+      for (int mu = 1; mu < Q; ++mu) {
+        er[mu] = er[mu - 1] * cph - ei[mu - 1] * sph;
+        ei[mu] = er[mu - 1] * sph + ei[mu - 1] * cph;
+      }
+      // source vector rotated by e^{i d_j phi}
+      const cplx<T>* xs = sx + (size_t)ss * S;
+      T vr[NH], vi[NH];
+#pragma unroll
+      for (int j = 0; j < NH; ++j) {
+        T pr, pi;
+        ol_rot<T, Q>(er, ei, d[j], pr, pi);
+        const cplx<T> v = xs[j];
+        vr[j] = pr * v.re - pi * v.im;
+        vi[j] = pr * v.im + pi * v.re;
+      }
+#pragma unroll
+      for (int i = 0; i < NH; ++i) {
+        T ar = (T)0, ai = (T)0;
+#pragma unroll
+        for (int j = 0; j < NH; ++j) {
+          const T* ce = cf + (size_t)(transpose ? j * S + i : i * S + j) * Q * 2;
+          T sr = (T)0, si = (T)0;
+#pragma unroll
+          for (int q = 0; q < Q; ++q) {
+            const T cr = ce[2 * q], ci = ce[2 * q + 1];
+            sr += cr * hr[q] - ci * hi[q];
+            si += cr * hi[q] + ci * hr[q];
+          }
+          ar += sr * vr[j] - si * vi[j];
+          ai += sr * vi[j] + si * vr[j];
+        }
+        T pr, pi;
+        ol_rot<T, Q>(er, ei, -d[i], pr, pi);
+        yr[i] += pr * ar - pi * ai;
+        yi[i] += pr * ai + pi * ar;
+      }
+    }
+  }
+  if (!live) return;
+  cplx<T>* out = partial + (((size_t)blockIdx.z * gridDim.y + rc) * N + t) * S;
+#pragma unroll
+  for (int i = 0; i < NH; ++i) out[i] = cplx<T>{yr[i], yi[i]};
+#pragma unroll
+  for (int i = NH; i < S; ++i) out[i] = cplx<T>{(T)0, (T)0};
+}
+
 // y = x - t * z (Forward), x - z (Adjoint, z from t x), or z, z = sum of the
 // chunks' partials in chunk order.
 template <typename T>
@@ -175,14 +328,31 @@ int offlattice_apply(tm_ctx* c, Op op, int R, const void* xin, const c128* x, c1
   nchunk = (N + chunk - 1) / chunk;
   int rc;
   if ((rc = ensure(c, c->partial, (size_t)nchunk * total * sizeof(cplx<T>))) != TM_OK) return rc;
-  const size_t cb = (size_t)NCLASS * S * S * (2 * g.lmax + 1) * 2 * sizeof(double);
+  // constants buffer: coef (FP64), dm, coef (FP32)
+  const size_t ne = (size_t)NCLASS * S * S;
+  const size_t cb = ne * (2 * g.lmax + 1) * 2 * sizeof(double), db = ne * sizeof(int);
   const double* coef = (const double*)c->olc.p;
+  const T* coefT = std::is_same<T, float>::value ? (const T*)((const char*)c->olc.p + cb + db)
+                                                 : (const T*)c->olc.p;
   const int* dm = (const int*)((const char*)c->olc.p + cb);
   const size_t lds = 2 * OL_GROUP * sizeof(double) + (size_t)OL_GROUP * S * sizeof(cplx<T>);
   const bool tr = (op == Op::Adjoint || op == Op::CouplingT);
-  hipLaunchKernelGGL(offlattice_kernel<T>, dim3(tb, 2 * R, nchunk), dim3(OL_THREADS), lds, c->stream,
-                     (const double*)c->xy.p, (const cplx<T>*)xin, coef, dm, N, S, nh, g.lmax, g.k, chunk,
-                     tr ? 1 : 0, (cplx<T>*)c->partial.p, c->mv_stop);
+  const dim3 grid(tb, 2 * R, nchunk);
+#define OL_SMALL(LM)                                                                              \
+  hipLaunchKernelGGL((offlattice_small_kernel<T, LM>), grid, dim3(OL_THREADS), lds, c->stream,    \
+                     (const double*)c->xy.p, (const cplx<T>*)xin, coefT, dm, N, g.k, chunk,         \
+                     tr ? 1 : 0, (cplx<T>*)c->partial.p, c->mv_stop)
+  if (g.lmax == 1)
+    OL_SMALL(1);
+  else if (g.lmax == 2)
+    OL_SMALL(2);
+  else if (g.lmax == 3)
+    OL_SMALL(3);
+  else
+    hipLaunchKernelGGL(offlattice_kernel<T>, grid, dim3(OL_THREADS), lds, c->stream,
+                       (const double*)c->xy.p, (const cplx<T>*)xin, coef, dm, N, S, nh, g.lmax, g.k,
+                       chunk, tr ? 1 : 0, (cplx<T>*)c->partial.p, c->mv_stop);
+#undef OL_SMALL
   hipLaunchKernelGGL(offlattice_combine_kernel<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
                      c->stream, (const cplx<T>*)c->partial.p, nchunk, total, x, (const c128*)c->t64.p,
                      g.vec_len(), y, (int)op, c->mv_stop);

@@ -464,18 +464,23 @@ int build_tables(tm_ctx* c) { return build_impl(c, c->tab64, c->tab32, 0); }
 
 // Off-lattice geometries: no displacement tables; the on-the-fly matvec reads
 // the per-entry constants coef [2][S][S][Q] (complex, Pbar_q(0) folded in: every
-// scatterer lies in z = 0) and dm [2][S][S] from one device buffer.
+// scatterer lies in z = 0), dm [2][S][S] and coef again in FP32 from one
+// device buffer.
 int build_offlattice_constants(tm_ctx* c) {
   const Geometry& g = c->g;
   std::vector<double> coef;
   std::vector<int> dm, sig;
   const int Q = 2 * g.lmax + 1;
   host_table_constants(g, Q, coef, dm, sig);
+  // followed by an FP32 copy of coef for the complex64 kernel (no conversion per use)
+  std::vector<float> coef32(coef.begin(), coef.end());
   const size_t cb = coef.size() * sizeof(double), db = dm.size() * sizeof(int);
+  const size_t fb = coef32.size() * sizeof(float);
   int rc;
-  if ((rc = ensure(c, c->olc, cb + db)) != TM_OK) return rc;
+  if ((rc = ensure(c, c->olc, cb + db + fb)) != TM_OK) return rc;
   TM_HIP(c, hipMemcpy(c->olc.p, coef.data(), cb, hipMemcpyHostToDevice));
   TM_HIP(c, hipMemcpy((char*)c->olc.p + cb, dm.data(), db, hipMemcpyHostToDevice));
+  TM_HIP(c, hipMemcpy((char*)c->olc.p + cb + db, coef32.data(), fb, hipMemcpyHostToDevice));
   return TM_OK;
 }
 

@@ -49,7 +49,7 @@ def cluster(n, seed):
     return pos
 
 
-CASES = [("jitter", 3), ("cluster", 2), ("jitter", 5)]
+CASES = [("jitter", 3), ("cluster", 2), ("jitter", 5), ("cluster", 1)]
 
 
 def geometry(kind, lmax):
