@@ -173,7 +173,18 @@ __global__ __launch_bounds__(OL_THREADS) void offlattice_kernel(
 // (d_j = dm[c][0][j]): the source vector is rotated once per (pair, j) and
 // the sum over j once per (pair, i), instead of once per entry.  For the
 // transposed operator (entry (j, i), displacement source - target) the two
-// rotations change sign.
+// rotations change sign; the operator is a template argument, so that the
+// constants of every entry sit at fixed offsets from one base.
+// a * b + c in one rounding (the sums below are written as chains of these,
+// which the compiler does not form on its own from a*b - c*d + e)
+template <typename T>
+__device__ inline T ol_fma(T a, T b, T c) {
+  if constexpr (sizeof(T) == 4)
+    return __builtin_fmaf(a, b, c);
+  else
+    return __builtin_fma(a, b, c);
+}
+
 template <typename T, int Q>
 __device__ inline void ol_rot(const T* er, const T* ei, int d, T& pr, T& pi) {
   const int ad = d < 0 ? -d : d;
@@ -188,11 +199,11 @@ __device__ inline void ol_rot(const T* er, const T* ei, int d, T& pr, T& pi) {
   if (d < 0) pi = -pi;
 }
 
-template <typename T, int LMAX>
+template <typename T, int LMAX, bool TR>
 __global__ __launch_bounds__(OL_THREADS) void offlattice_small_kernel(
     const double* __restrict__ xy, const cplx<T>* __restrict__ x, const T* __restrict__ coef,
-    const int* __restrict__ dm, int N, double k, int chunk, int transpose,
-    cplx<T>* __restrict__ partial, const int* __restrict__ stop) {
+    const int* __restrict__ dm, int N, double k, int chunk, cplx<T>* __restrict__ partial,
+    const int* __restrict__ stop) {
   constexpr int Q = 2 * LMAX + 1;           // Hankel orders and phase powers
   constexpr int NH = LMAX * (LMAX + 2);     // members of a class
   constexpr int S = 16 * ((NH + 15) / 16);  // slots of a class
@@ -209,7 +220,7 @@ __global__ __launch_bounds__(OL_THREADS) void offlattice_small_kernel(
   const cplx<T>* xin = x + (size_t)rc * N * S;
   const T* cf = coef + (size_t)c * S * S * Q * 2;
   const int* dmc = dm + (size_t)c * S * S;
-  const int sg = transpose ? -1 : 1;
+  const int sg = TR ? -1 : 1;
   int d[NH];
 #pragma unroll
   for (int j = 0; j < NH; ++j) d[j] = sg * dmc[j];  // +-(m_j - m_0)
@@ -230,8 +241,8 @@ __global__ __launch_bounds__(OL_THREADS) void offlattice_small_kernel(
       const int s = g0 + ss;
       if (s == t) continue;
       // displacement of the block: target - source (source - target for A^T)
-      const double dx = transpose ? sxy[2 * ss] - xt : xt - sxy[2 * ss];
-      const double dy = transpose ? sxy[2 * ss + 1] - yt : yt - sxy[2 * ss + 1];
+      const double dx = TR ? sxy[2 * ss] - xt : xt - sxy[2 * ss];
+      const double dy = TR ? sxy[2 * ss + 1] - yt : yt - sxy[2 * ss + 1];
       const double r = sqrt(dx * dx + dy * dy);
       T hr[Q], hi[Q];
       ol_hankel_fixed<T, Q>(k * r, hr, hi);
@@ -252,29 +263,29 @@ __global__ __launch_bounds__(OL_THREADS) void offlattice_small_kernel(
         T pr, pi;
         ol_rot<T, Q>(er, ei, d[j], pr, pi);
         const cplx<T> v = xs[j];
-        vr[j] = pr * v.re - pi * v.im;
-        vi[j] = pr * v.im + pi * v.re;
+        vr[j] = ol_fma(pr, v.re, -pi * v.im);
+        vi[j] = ol_fma(pr, v.im, pi * v.re);
       }
 #pragma unroll
       for (int i = 0; i < NH; ++i) {
         T ar = (T)0, ai = (T)0;
 #pragma unroll
         for (int j = 0; j < NH; ++j) {
-          const T* ce = cf + (size_t)(transpose ? j * S + i : i * S + j) * Q * 2;
+          const T* ce = cf + (size_t)(TR ? j * S + i : i * S + j) * Q * 2;
           T sr = (T)0, si = (T)0;
 #pragma unroll
           for (int q = 0; q < Q; ++q) {
             const T cr = ce[2 * q], ci = ce[2 * q + 1];
-            sr += cr * hr[q] - ci * hi[q];
-            si += cr * hi[q] + ci * hr[q];
+            sr = ol_fma(-ci, hi[q], ol_fma(cr, hr[q], sr));
+            si = ol_fma(ci, hr[q], ol_fma(cr, hi[q], si));
           }
-          ar += sr * vr[j] - si * vi[j];
-          ai += sr * vi[j] + si * vr[j];
+          ar = ol_fma(-si, vi[j], ol_fma(sr, vr[j], ar));
+          ai = ol_fma(si, vr[j], ol_fma(sr, vi[j], ai));
         }
         T pr, pi;
         ol_rot<T, Q>(er, ei, -d[i], pr, pi);
-        yr[i] += pr * ar - pi * ai;
-        yi[i] += pr * ai + pi * ar;
+        yr[i] = ol_fma(-pi, ai, ol_fma(pr, ar, yr[i]));
+        yi[i] = ol_fma(pi, ar, ol_fma(pr, ai, yi[i]));
       }
     }
   }
@@ -338,21 +349,28 @@ int offlattice_apply(tm_ctx* c, Op op, int R, const void* xin, const c128* x, c1
   const size_t lds = 2 * OL_GROUP * sizeof(double) + (size_t)OL_GROUP * S * sizeof(cplx<T>);
   const bool tr = (op == Op::Adjoint || op == Op::CouplingT);
   const dim3 grid(tb, 2 * R, nchunk);
-#define OL_SMALL(LM)                                                                              \
-  hipLaunchKernelGGL((offlattice_small_kernel<T, LM>), grid, dim3(OL_THREADS), lds, c->stream,    \
-                     (const double*)c->xy.p, (const cplx<T>*)xin, coefT, dm, N, g.k, chunk,         \
-                     tr ? 1 : 0, (cplx<T>*)c->partial.p, c->mv_stop)
-  if (g.lmax == 1)
-    OL_SMALL(1);
-  else if (g.lmax == 2)
-    OL_SMALL(2);
-  else if (g.lmax == 3)
-    OL_SMALL(3);
-  else
-    hipLaunchKernelGGL(offlattice_kernel<T>, grid, dim3(OL_THREADS), lds, c->stream,
-                       (const double*)c->xy.p, (const cplx<T>*)xin, coef, dm, N, S, nh, g.lmax, g.k,
-                       chunk, tr ? 1 : 0, (cplx<T>*)c->partial.p, c->mv_stop);
+#define OL_SMALL2(LM, TRV)                                                                        \
+  hipLaunchKernelGGL((offlattice_small_kernel<T, LM, TRV>), grid, dim3(OL_THREADS), lds, c->stream, \
+                     (const double*)c->xy.p, (const cplx<T>*)xin, coefT, dm, N, g.k, chunk,          \
+                     (cplx<T>*)c->partial.p, c->mv_stop)
+#define OL_SMALL(LM)          \
+  {                           \
+    if (tr)                   \
+      OL_SMALL2(LM, true);    \
+    else                      \
+      OL_SMALL2(LM, false);   \
+  }
+  switch (g.lmax) {
+    case 1: OL_SMALL(1); break;
+    case 2: OL_SMALL(2); break;
+    case 3: OL_SMALL(3); break;
+    default:
+      hipLaunchKernelGGL(offlattice_kernel<T>, grid, dim3(OL_THREADS), lds, c->stream,
+                         (const double*)c->xy.p, (const cplx<T>*)xin, coef, dm, N, S, nh, g.lmax,
+                         g.k, chunk, tr ? 1 : 0, (cplx<T>*)c->partial.p, c->mv_stop);
+  }
 #undef OL_SMALL
+#undef OL_SMALL2
   hipLaunchKernelGGL(offlattice_combine_kernel<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
                      c->stream, (const cplx<T>*)c->partial.p, nchunk, total, x, (const c128*)c->t64.p,
                      g.vec_len(), y, (int)op, c->mv_stop);
