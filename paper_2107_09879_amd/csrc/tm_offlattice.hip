@@ -26,35 +26,8 @@ namespace tmh {
 constexpr int OL_THREADS = 256;
 constexpr int OL_GROUP = 64;  // sources staged per LDS pass
 
-template <typename T>
-__device__ inline void ol_hankel(double kr, int qmax, T* hr, T* hi) {
-  const double twopi = 6.283185307179586476925286766559;
-  const double red = kr - twopi * rint(kr / twopi);
-  T s, c;
-  if (sizeof(T) == 4) {
-    float sf, cf;
-    sincosf((float)red, &sf, &cf);
-    s = (T)sf;
-    c = (T)cf;
-  } else {
-    double sd, cd;
-    sincos(red, &sd, &cd);
-    s = (T)sd;
-    c = (T)cd;
-  }
-  const T x = (T)kr, ix = (T)1 / x;
-  hr[0] = s * ix;
-  hi[0] = -c * ix;
-  hr[1] = -(c * x - s) * ix * ix;
-  hi[1] = -(s * x + c) * ix * ix;
-  for (int q = 1; q < qmax; ++q) {
-    const T f = (T)(2 * q + 1) * ix;
-    hr[q + 1] = f * hr[q] - hr[q - 1];
-    hi[q + 1] = f * hi[q] - hi[q - 1];
-  }
-}
-
-// h_q(kr), q = 0..Q-1 (Q >= 3 a template argument), as ol_hankel
+// h_q(kr), q = 0..Q-1 (Q >= 3 a template argument), by upward recurrence from
+// h_0 and h_1, with k r reduced modulo 2 pi in FP64 before the sine and cosine
 template <typename T, int Q>
 __device__ inline void ol_hankel_fixed(double kr, T* hr, T* hi) {
   const double twopi = 6.283185307179586476925286766559;
@@ -84,86 +57,7 @@ __device__ inline void ol_hankel_fixed(double kr, T* hr, T* hi) {
   }
 }
 
-// partial[chunk][r][c][t][S] = sum over the chunk's sources of M x_s (or M^T)
-template <typename T>
-__global__ __launch_bounds__(OL_THREADS) void offlattice_kernel(
-    const double* __restrict__ xy, const cplx<T>* __restrict__ x, const double* __restrict__ coef,
-    const int* __restrict__ dm, int N, int S, int nh, int lmax, double k, int chunk, int transpose,
-    cplx<T>* __restrict__ partial, const int* __restrict__ stop) {
-  if (stop && *stop) return;  // a stopped GMRES cycle
-  extern __shared__ double ol_lds[];
-  double* sxy = ol_lds;                                        // [OL_GROUP][2]
-  cplx<T>* sx = reinterpret_cast<cplx<T>*>(ol_lds + 2 * OL_GROUP);  // [OL_GROUP][S]
-  const int t = blockIdx.x * OL_THREADS + threadIdx.x;
-  const int rc = blockIdx.y;  // r * 2 + c
-  const int c = rc & 1;
-  const int s0 = blockIdx.z * chunk, s1 = min(N, s0 + chunk);
-  const bool live = t < N;
-  const double xt = live ? xy[2 * t] : 0.0, yt = live ? xy[2 * t + 1] : 0.0;
-  const int Q = 2 * lmax + 1;
-  const cplx<T>* xin = x + (size_t)rc * N * S;
-  const double* cf = coef + (size_t)c * S * S * Q * 2;
-  const int* dmc = dm + (size_t)c * S * S;
-  T yr[SMAX], yi[SMAX];
-  for (int i = 0; i < S; ++i) yr[i] = yi[i] = (T)0;
-  for (int g0 = s0; g0 < s1; g0 += OL_GROUP) {
-    const int ng = min(OL_GROUP, s1 - g0);
-    __syncthreads();
-    for (int q = threadIdx.x; q < ng * S; q += OL_THREADS) {
-      const int ss = q / S, j = q % S;
-      sx[q] = xin[(size_t)(g0 + ss) * S + j];
-    }
-    for (int q = threadIdx.x; q < 2 * ng; q += OL_THREADS) sxy[q] = xy[2 * g0 + q];
-    __syncthreads();
-    if (!live) continue;
-    for (int ss = 0; ss < ng; ++ss) {
-      const int s = g0 + ss;
-      if (s == t) continue;
-      // displacement of the block: target - source (source - target for A^T)
-      const double dx = transpose ? sxy[2 * ss] - xt : xt - sxy[2 * ss];
-      const double dy = transpose ? sxy[2 * ss + 1] - yt : yt - sxy[2 * ss + 1];
-      const double r = sqrt(dx * dx + dy * dy);
-      T hr[2 * LMAX_SUPPORTED + 1], hi[2 * LMAX_SUPPORTED + 1];
-      ol_hankel<T>(k * r, Q - 1, hr, hi);
-      // e^{i mu phi}, mu = 0..2 lmax, from (dx + i dy)/r
-      const T cph = (T)(dx / r), sph = (T)(dy / r);
-      T er[2 * LMAX_SUPPORTED + 1], ei[2 * LMAX_SUPPORTED + 1];
-      er[0] = (T)1;
-      ei[0] = (T)0;
-      for (int mu = 1; mu < Q; ++mu) {
-        er[mu] = er[mu - 1] * cph - ei[mu - 1] * sph;
-        ei[mu] = er[mu - 1] * sph + ei[mu - 1] * cph;
-      }
-      const cplx<T>* xs = sx + (size_t)ss * S;
-      for (int i = 0; i < nh; ++i) {
-        T ar = (T)0, ai = (T)0;
-        for (int j = 0; j < nh; ++j) {
-          // entry (i, j) of M, or (j, i) for the transposed operator
-          const int e = transpose ? j * S + i : i * S + j;
-          const double* ce = cf + (size_t)e * Q * 2;
-          T sr = (T)0, si = (T)0;
-          for (int q = 0; q < Q; ++q) {
-            const T cr = (T)ce[2 * q], ci = (T)ce[2 * q + 1];
-            sr += cr * hr[q] - ci * hi[q];
-            si += cr * hi[q] + ci * hr[q];
-          }
-          const int mu = dmc[e];
-          const T pr = er[mu < 0 ? -mu : mu], pi = mu < 0 ? -ei[-mu] : ei[mu];
-          const T mr = sr * pr - si * pi, mi = sr * pi + si * pr;
-          const cplx<T> v = xs[j];
-          ar += mr * v.re - mi * v.im;
-          ai += mr * v.im + mi * v.re;
-        }
-        yr[i] += ar;
-        yi[i] += ai;
-      }
-    }
-  }
-  if (!live) return;
-  cplx<T>* out = partial + (((size_t)blockIdx.z * gridDim.y + rc) * N + t) * S;
-  for (int i = 0; i < S; ++i) out[i] = cplx<T>{yr[i], yi[i]};
-}
-
+// partial[chunk][r][c][t][S] = sum over the chunk's sources of M x_s (or M^T).
 // The same product for lmax <= 3 with every loop over coefficients unrolled
 // (lmax a template argument): the Hankel values, phases, the source vector
 // and the output accumulators sit in registers at fixed places and the
@@ -297,6 +191,113 @@ __global__ __launch_bounds__(OL_THREADS) void offlattice_small_kernel(
   for (int i = NH; i < S; ++i) out[i] = cplx<T>{(T)0, (T)0};
 }
 
+// The product for lmax 4..6: loops over entries at run time (unrolled, classes
+// of up to 48 members would not fit the register file), the sum over q
+// unrolled with the Hankel values in registers, FP32 constants for the
+// complex64 kernel, and (complex64) the phases e^{i mu phi} of the current
+// pair in an LDS table [mu][thread] read once per entry.  LDS per workgroup
+// stays under 64 KB: at lmax 6, 25 KB of staged sources and 27 KB of phases
+// (FP32), 50 KB of staged sources (FP64).
+template <typename T, int LMAX, bool TR>
+__global__ __launch_bounds__(OL_THREADS) void offlattice_mid_kernel(
+    const double* __restrict__ xy, const cplx<T>* __restrict__ x, const T* __restrict__ coef,
+    const int* __restrict__ dm, int N, double k, int chunk, cplx<T>* __restrict__ partial,
+    const int* __restrict__ stop) {
+  constexpr int Q = 2 * LMAX + 1;
+  constexpr int NH = LMAX * (LMAX + 2);
+  constexpr int S = 16 * ((NH + 15) / 16);
+  // the FP32 kernel reads each entry's phase from an LDS table; the FP64 one
+  // (whose table would not fit beside the staged sources) selects it in registers
+  constexpr bool PHT = sizeof(T) == 4;
+  if (stop && *stop) return;  // a stopped GMRES cycle
+  extern __shared__ double ol_lds[];
+  double* sxy = ol_lds;                                             // [OL_GROUP][2]
+  cplx<T>* sx = reinterpret_cast<cplx<T>*>(ol_lds + 2 * OL_GROUP);  // [OL_GROUP][S]
+  cplx<T>* sph = sx + (size_t)OL_GROUP * S;                          // [Q][OL_THREADS] (PHT)
+  const int t = blockIdx.x * OL_THREADS + threadIdx.x;
+  const int rc = blockIdx.y;  // r * 2 + c
+  const int c = rc & 1;
+  const int s0 = blockIdx.z * chunk, s1 = min(N, s0 + chunk);
+  const bool live = t < N;
+  const double xt = live ? xy[2 * t] : 0.0, yt = live ? xy[2 * t + 1] : 0.0;
+  const cplx<T>* xin = x + (size_t)rc * N * S;
+  const T* cf = coef + (size_t)c * S * S * Q * 2;
+  const int* dmc = dm + (size_t)c * S * S;
+  cplx<T>* myph = sph + threadIdx.x;
+  T yr[NH], yi[NH];
+#pragma unroll
+  for (int i = 0; i < NH; ++i) yr[i] = yi[i] = (T)0;
+  for (int g0 = s0; g0 < s1; g0 += OL_GROUP) {
+    const int ng = min(OL_GROUP, s1 - g0);
+    __syncthreads();
+    for (int q = threadIdx.x; q < ng * S; q += OL_THREADS) {
+      const int ss = q / S, j = q % S;
+      sx[q] = xin[(size_t)(g0 + ss) * S + j];
+    }
+    for (int q = threadIdx.x; q < 2 * ng; q += OL_THREADS) sxy[q] = xy[2 * g0 + q];
+    __syncthreads();
+    if (!live) continue;
+    for (int ss = 0; ss < ng; ++ss) {
+      const int s = g0 + ss;
+      if (s == t) continue;
+      const double dx = TR ? sxy[2 * ss] - xt : xt - sxy[2 * ss];
+      const double dy = TR ? sxy[2 * ss + 1] - yt : yt - sxy[2 * ss + 1];
+      const double r = sqrt(dx * dx + dy * dy);
+      T hr[Q], hi[Q];
+      ol_hankel_fixed<T, Q>(k * r, hr, hi);
+      const T cph = (T)(dx / r), sphi = (T)(dy / r);
+      T er[Q], ei[Q];
+      er[0] = (T)1;
+      ei[0] = (T)0;
+#pragma unroll
+      for (int mu = 1; mu < Q; ++mu) {
+        er[mu] = er[mu - 1] * cph - ei[mu - 1] * sphi;
+        ei[mu] = er[mu - 1] * sphi + ei[mu - 1] * cph;
+      }
+      if constexpr (PHT) {
+#pragma unroll
+        for (int mu = 0; mu < Q; ++mu) myph[(size_t)mu * OL_THREADS] = cplx<T>{er[mu], ei[mu]};
+      }
+      const cplx<T>* xs = sx + (size_t)ss * S;
+      for (int i = 0; i < NH; ++i) {
+        T ar = (T)0, ai = (T)0;
+        for (int j = 0; j < NH; ++j) {
+          const int e = TR ? j * S + i : i * S + j;
+          const T* ce = cf + (size_t)e * Q * 2;
+          T sr = (T)0, si = (T)0;
+#pragma unroll
+          for (int q = 0; q < Q; ++q) {
+            const T cr = ce[2 * q], ci = ce[2 * q + 1];
+            sr = ol_fma(-ci, hi[q], ol_fma(cr, hr[q], sr));
+            si = ol_fma(ci, hr[q], ol_fma(cr, hi[q], si));
+          }
+          const int mu = dmc[e];
+          T qr, qi;
+          if constexpr (PHT) {
+            const cplx<T> ph = myph[(size_t)(mu < 0 ? -mu : mu) * OL_THREADS];
+            qr = ph.re;
+            qi = mu < 0 ? -ph.im : ph.im;
+          } else {
+            ol_rot<T, Q>(er, ei, mu, qr, qi);
+          }
+          const T mr = ol_fma(-si, qi, sr * qr), mi = ol_fma(si, qr, sr * qi);
+          const cplx<T> v = xs[j];
+          ar = ol_fma(-mi, v.im, ol_fma(mr, v.re, ar));
+          ai = ol_fma(mi, v.re, ol_fma(mr, v.im, ai));
+        }
+        yr[i] += ar;
+        yi[i] += ai;
+      }
+    }
+  }
+  if (!live) return;
+  cplx<T>* out = partial + (((size_t)blockIdx.z * gridDim.y + rc) * N + t) * S;
+#pragma unroll
+  for (int i = 0; i < NH; ++i) out[i] = cplx<T>{yr[i], yi[i]};
+#pragma unroll
+  for (int i = NH; i < S; ++i) out[i] = cplx<T>{(T)0, (T)0};
+}
+
 // y = x - t * z (Forward), x - z (Adjoint, z from t x), or z, z = sum of the
 // chunks' partials in chunk order.
 template <typename T>
@@ -330,7 +331,6 @@ template <typename T>
 int offlattice_apply(tm_ctx* c, Op op, int R, const void* xin, const c128* x, c128* y) {
   const Geometry& g = c->g;
   const int N = g.n, S = g.S;
-  const int nh = g.L / 2;
   const long long total = g.vec_len() * R;
   // enough workgroups to fill the chip: target blocks x (rhs, class) x chunks
   const int tb = (N + OL_THREADS - 1) / OL_THREADS;
@@ -342,7 +342,6 @@ int offlattice_apply(tm_ctx* c, Op op, int R, const void* xin, const c128* x, c1
   // constants buffer: coef (FP64), dm, coef (FP32)
   const size_t ne = (size_t)NCLASS * S * S;
   const size_t cb = ne * (2 * g.lmax + 1) * 2 * sizeof(double), db = ne * sizeof(int);
-  const double* coef = (const double*)c->olc.p;
   const T* coefT = std::is_same<T, float>::value ? (const T*)((const char*)c->olc.p + cb + db)
                                                  : (const T*)c->olc.p;
   const int* dm = (const int*)((const char*)c->olc.p + cb);
@@ -360,15 +359,32 @@ int offlattice_apply(tm_ctx* c, Op op, int R, const void* xin, const c128* x, c1
     else                      \
       OL_SMALL2(LM, false);   \
   }
+  // the mid kernel adds a phase table [Q][OL_THREADS] behind the staged sources
+  const size_t lds_mid =
+      lds + (std::is_same<T, float>::value ? (size_t)(2 * g.lmax + 1) * OL_THREADS * sizeof(cplx<T>) : 0);
+#define OL_MID2(LM, TRV)                                                                           \
+  hipLaunchKernelGGL((offlattice_mid_kernel<T, LM, TRV>), grid, dim3(OL_THREADS), lds_mid,         \
+                     c->stream, (const double*)c->xy.p, (const cplx<T>*)xin, coefT, dm, N, g.k,     \
+                     chunk, (cplx<T>*)c->partial.p, c->mv_stop)
+#define OL_MID(LM)            \
+  {                           \
+    if (tr)                   \
+      OL_MID2(LM, true);      \
+    else                      \
+      OL_MID2(LM, false);     \
+  }
   switch (g.lmax) {
     case 1: OL_SMALL(1); break;
     case 2: OL_SMALL(2); break;
     case 3: OL_SMALL(3); break;
+    case 4: OL_MID(4); break;
+    case 5: OL_MID(5); break;
+    case 6: OL_MID(6); break;
     default:
-      hipLaunchKernelGGL(offlattice_kernel<T>, grid, dim3(OL_THREADS), lds, c->stream,
-                         (const double*)c->xy.p, (const cplx<T>*)xin, coef, dm, N, S, nh, g.lmax,
-                         g.k, chunk, tr ? 1 : 0, (cplx<T>*)c->partial.p, c->mv_stop);
+      return set_err(c, TM_ERR_INVALID_ARG, "lmax outside 1..6");
   }
+#undef OL_MID
+#undef OL_MID2
 #undef OL_SMALL
 #undef OL_SMALL2
   hipLaunchKernelGGL(offlattice_combine_kernel<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
