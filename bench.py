@@ -680,7 +680,8 @@ def bench_offlattice(args):
         torch.cuda.synchronize()
         op[prec] = {"ms": (time.perf_counter() - t1) / args.matvec_reps * 1e3}
         log(f"[bench] off-lattice {prec} operator: {op[prec]['ms']:.2f} ms")
-    kernel = f"offlattice_small_kernel<float, {lmax}, false>" if lmax <= 3 else "offlattice_kernel<float>"
+    kernel = (f"offlattice_small_kernel<float, {lmax}, false>" if lmax <= 3
+              else f"offlattice_mid_kernel<float, {lmax}, false>")
     ipp = ol_valu_per_pair(kernel)
     roof = None
     if ipp is not None:
