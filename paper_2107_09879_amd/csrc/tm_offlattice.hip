@@ -373,10 +373,19 @@ int offlattice_apply(tm_ctx* c, Op op, int R, const void* xin, const c128* x, c1
     else                      \
       OL_MID2(LM, false);     \
   }
+  // FP64 takes the run-time-loop kernel at every lmax: unrolled, it needs 256
+  // VGPRs at lmax 3 (one wave per SIMD)
+  constexpr bool fp64 = std::is_same<T, double>::value;
   switch (g.lmax) {
-    case 1: OL_SMALL(1); break;
-    case 2: OL_SMALL(2); break;
-    case 3: OL_SMALL(3); break;
+    case 1:
+      if constexpr (fp64) OL_MID(1) else OL_SMALL(1);
+      break;
+    case 2:
+      if constexpr (fp64) OL_MID(2) else OL_SMALL(2);
+      break;
+    case 3:
+      if constexpr (fp64) OL_MID(3) else OL_SMALL(3);
+      break;
     case 4: OL_MID(4); break;
     case 5: OL_MID(5); break;
     case 6: OL_MID(6); break;
