@@ -180,7 +180,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c2")
+    ap.add_argument("--config", default="c2",
+                    help="workload: c1, c2 (default), c3 (batched subregions), c4 (adjoint and "
+                         "gradients), c5 (300x300 tile), jinc (padding study), cyl6 (lmax-6 "
+                         "silicon cylinders), offl (off-lattice blocks)")
     ap.add_argument("--matvec-reps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
